@@ -1,0 +1,159 @@
+"""Chemical problem (Sec. 2.2 eqs. (13)-(22); Sec. 3.2 Chemical problem,
+eqs. (37)-(50); Alg. 3 "Chemical diffusion problem").
+
+Backward-Euler, semi-implicit step (eq. (42) [ChemDTsolve]) with residual
+(eq. (43) [Chemresidualfc])
+    f(c) = c + dt div[ M(d_t) c_t (1 - c_t) C_t^-1 grad mu(c) ] - dt cdot_B - c_t,
+mobility M(d) = -D/RT (0.9 (1-d)^2 + 0.1 d^2) (eq. (20)),
+chemical potential mu = mu_c + mu_e, mu_c = RT log(c/(1-c)) (eq. (17)).
+Newton from c^0 = c_t, c^{i+1} = c^i + dc (eq. (47)), stopped when
+||dc|| / ||c_t|| < tol_chem (eq. (48)).
+
+The operators are applied in Fourier space as in eqs. (49)-(50): grad by the
+forward-difference frequencies xi_j = (e^{i q_j} - 1)/h_j, div by the
+backward-difference frequencies -conj(xi_j) (their adjoint, so that
+div grad is the 7-point Laplacian).
+
+Readings (A9-A13):
+* M(d) literal: the effective diffusivity at d = 0 is 0.9 D.
+* mu_e is re-derived from the chosen energy (the printed eq. (18) is
+  garbled):  mu_e = dpsi_e/dc = -g Omega / (3 (1 + Omega c))
+  [ G (tr C_e - 3) + 3 lambda ln J_e ]  (J/m^3), divided by c_max (mol/m^3)
+  to give J/mol before adding to mu_c.
+* The Newton linearisation keeps only mu_c (as eq. (45) does):
+      dmu_c/dc = w = RT (1/c + 1/(1 - c)),
+  and the linear step is solved for dmu = w dc with the SPD operator
+      B(dmu) = dmu / w + dt div[ M c_t (1-c_t) C_t^-1 grad dmu ] = -f(c),
+  then dc = dmu / w (identical to the dc of the literal Jacobian; pinned on
+  tiny grids against a dense solve of eq. (45) in dc form).
+* Preconditioner (the paper gives none for this problem): the
+  constant-coefficient inverse F^-1[ F(.) / (mean(1/w) + dt abar lambda(q)) ]
+  with abar = mean(tr(-M c_t(1-c_t) C_t^-1)) / 3.
+* C_t = F^T F of the stored deformation, d_t the stored damage (chemistry is
+  solved once per step with the fields of the previous step, Sec. 3.2
+  Global problem).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .constitutive import DomainError, det_and_inv_transpose, lame, swelling_factors
+from .krylov import pcg
+from .spectral import forward_difference_symbol, irfft3, laplacian_symbol, rfft3
+
+
+def chemical_potential(c, F, d, mat):
+    """mu(c) = mu_c + mu_e / c_max (J/mol)."""
+    if np.any(c <= 0.0) or np.any(c >= 1.0):
+        raise DomainError("c outside (0, 1)")
+    RT = mat["RT"]
+    mu_c = RT * np.log(c / (1.0 - c))
+    lam, G = lame(mat["E"], mat["nu"])
+    Om = mat["Omega"]
+    g = (1.0 - d) ** 2
+    a, s2inv = swelling_factors(c, Om)
+    J, _ = det_and_inv_transpose(F)
+    lnJe = np.log(J) - np.log(a)
+    trC = np.einsum("ij...,ij...->...", F, F)
+    mu_e = -g * Om / (3.0 * a) * (G * (trC * s2inv - 3.0) + 3.0 * lam * lnJe)
+    return mu_c + mu_e / mat["c_max"]
+
+
+def mobility(d, D, RT):
+    """M(d) of eq. (20) (negative)."""
+    return -D / RT * (0.9 * (1.0 - d) ** 2 + 0.1 * d * d)
+
+
+def flux_coefficient(c_t, F_t, d_t, mat):
+    """Q = M(d_t) c_t (1 - c_t) C_t^-1, shape (3, 3, ...) (negative definite)."""
+    Fl = np.moveaxis(F_t, (0, 1), (-2, -1))
+    C = np.swapaxes(Fl, -1, -2) @ Fl
+    Cinv = np.moveaxis(np.linalg.inv(C), (-2, -1), (0, 1))
+    return mobility(d_t, mat["D"], mat["RT"]) * c_t * (1.0 - c_t) * Cinv
+
+
+def grad(v, spacing):
+    """Forward-difference gradient via its symbol, shape (3, ...)."""
+    xi = forward_difference_symbol(v.shape, spacing)
+    vh = rfft3(v)
+    return np.stack([irfft3(xi[j] * vh, v.shape) for j in range(3)])
+
+
+def div(w, spacing):
+    """Backward-difference divergence (minus the adjoint of grad)."""
+    shape = w.shape[1:]
+    xi = forward_difference_symbol(shape, spacing)
+    acc = 0.0
+    for j in range(3):
+        acc = acc - np.conj(xi[j]) * rfft3(w[j])
+    return irfft3(acc, shape)
+
+
+def div_Q_grad(v, Q, spacing):
+    """div[ Q grad v ] with a voxel-wise 3x3 coefficient Q."""
+    g = grad(v, spacing)
+    return div(np.einsum("jk...,k...->j...", Q, g), spacing)
+
+
+def residual(c, c_t, F_t, d_t, cdot_B, dt, mat, Q=None):
+    """f(c) of eq. (43)."""
+    if Q is None:
+        Q = flux_coefficient(c_t, F_t, d_t, mat)
+    mu = chemical_potential(c, F_t, d_t, mat)
+    return c + dt * div_Q_grad(mu, Q, mat["spacing"]) - dt * cdot_B - c_t
+
+
+def potential_slope(c, RT):
+    """w = d mu_c / dc = RT (1/c + 1/(1 - c))."""
+    return RT * (1.0 / c + 1.0 / (1.0 - c))
+
+
+def fick_step(c_t, F_t, d_t, cdot_B, dt, mat, tol_chem=1e-8, tol_lin=1e-10,
+              max_newton=50, maxit_lin=10000, fixed_lin=None):
+    """Alg. 3: one backward-Euler step.  Returns (c_{t+dt}, stats)."""
+    spacing = mat["spacing"]
+    Q = flux_coefficient(c_t, F_t, d_t, mat)
+    lam = laplacian_symbol(c_t.shape, spacing)
+    abar = float(np.mean(-(Q[0, 0] + Q[1, 1] + Q[2, 2]))) / 3.0
+    norm_ct = float(np.sqrt(np.sum(c_t * c_t)))
+    c = c_t.copy()
+    lin_iters, rel = [], []
+    for it in range(max_newton):
+        f = residual(c, c_t, F_t, d_t, cdot_B, dt, mat, Q)
+        w = potential_slope(c, mat["RT"])
+        winv_mean = float(np.mean(1.0 / w))
+
+        def B(x):
+            return x / w + dt * div_Q_grad(x, Q, spacing)
+
+        def M(r):
+            return irfft3(rfft3(r) / (winv_mean + dt * abar * lam), r.shape)
+
+        fixed = None if fixed_lin is None else fixed_lin[it]
+        dmu, n, _ = pcg(B, M, -f, tol_lin, maxit_lin, fixed_iters=fixed)
+        dc = dmu / w
+        c = c + dc
+        lin_iters.append(n)
+        r = float(np.sqrt(np.sum(dc * dc))) / norm_ct
+        rel.append(r)
+        if r < tol_chem:
+            return c, dict(newton_iters=it + 1, lin_iters=lin_iters, dc_history=rel)
+    raise RuntimeError("Fick Newton did not converge")
+
+
+def literal_newton_increment_dense(c, c_t, F_t, d_t, cdot_B, dt, mat):
+    """One Newton increment dc of eq. (46) with the Jacobian of eq. (45)
+    assembled as a dense (non-symmetric) matrix in dc form and solved by LU.
+    Tiny grids only (pins the dmu-form PCG)."""
+    shape = c.shape
+    n = c.size
+    Q = flux_coefficient(c_t, F_t, d_t, mat)
+    w = potential_slope(c, mat["RT"])
+    f = residual(c, c_t, F_t, d_t, cdot_B, dt, mat, Q)
+    Jm = np.empty((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        e = e.reshape(shape)
+        Jm[:, k] = (e + dt * div_Q_grad(w * e, Q, mat["spacing"])).ravel()
+    return np.linalg.solve(Jm, -f.ravel()).reshape(shape)

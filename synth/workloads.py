@@ -1,0 +1,213 @@
+"""The five seeded workloads (material fields, state and load schedules).
+
+Workloads (grid sizes are defaults; every builder takes a size so that the
+same generator makes the small twins used for parity):
+
+* ``inclusion``   16^3 unit cell, centred sphere r = 4 voxels, stiff inclusion
+                  (100 GPa / 0.25) in a 10 GPa / 0.3 matrix, macro F = I +
+                  0.01 e1 (x) e1 in 5 increments, no damage, no chemistry.
+* ``particle``    128^3, L = 15 um, one ellipsoidal particle (semi-axes
+                  40/32/28 voxels, 15 GPa, D = 1e-14 m^2/s, Omega = 0.03) in a
+                  compliant buffer (E = 1e-3 E_p), constant inward flux on a
+                  one-voxel inner shell, 200 backward-Euler steps, AT2 damage.
+* ``polydisperse`` 256^3 unit cell, 60 RSA spheres, radii U(10, 24) voxels,
+                  contrast 20, macro stretch ramped to 1.05 in 20 increments.
+* ``batch``       48 two-phase RVEs with N in {32, 48, 64, 96}, Boolean spheres
+                  r = N/8 at volume fraction U(0.1, 0.4), 6 load cases.
+* ``grf``         128^3 Gaussian random fields for log E and Omega.
+
+SI units throughout (Pa, m, s, J/mol).  The concentration c is a normalised
+mole fraction in (0, 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .microstructure import (
+    SEED_BASE,
+    boolean_spheres,
+    ellipsoid_mask,
+    gaussian_random_field,
+    inner_shell,
+    rng_for,
+    rsa_spheres,
+    sphere_mask,
+)
+
+__all__ = [
+    "GAS_R",
+    "Workload",
+    "uniaxial_schedule",
+    "six_load_cases",
+    "inclusion_workload",
+    "particle_workload",
+    "polydisperse_workload",
+    "batch_workloads",
+    "grf_workload",
+    "homogeneous_workload",
+]
+
+GAS_R = 8.314462618  # J / (mol K)
+
+
+class Workload(dict):
+    """Plain dict with attribute access.
+
+    Keys: shape, spacing, E, nu, Omega, D, sigma_max (voxel fields, float64),
+    gc, lc, RT, c_max (scalars), c0, d0 (initial fields), loads (list of 3x3
+    macro F), plus workload-specific extras.
+    """
+
+    __getattr__ = dict.__getitem__
+
+
+def uniaxial_schedule(total_strain, n_inc):
+    """F_n = I + (n / n_inc) * total_strain * e1 (x) e1, n = 1..n_inc."""
+    out = []
+    for n in range(1, n_inc + 1):
+        F = np.eye(3)
+        F[0, 0] += total_strain * n / n_inc
+        out.append(F)
+    return out
+
+
+def six_load_cases(eps):
+    """F = I + eps * E^(k) for the 6 Voigt directions 11, 22, 33, 23, 13, 12
+    (shear directions symmetrised, (a (x) b + b (x) a)/2)."""
+    pairs = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    out = []
+    for i, j in pairs:
+        E = np.zeros((3, 3))
+        E[i, j] += 0.5
+        E[j, i] += 0.5
+        out.append(np.eye(3) + eps * E)
+    return out
+
+
+def _base(shape, length):
+    shape = tuple(int(n) for n in shape)
+    if np.isscalar(length):
+        length = (float(length),) * 3
+    spacing = tuple(float(L) / n for L, n in zip(length, shape))
+    return shape, spacing
+
+
+def homogeneous_workload(shape=(8, 8, 8), length=1.0, E=10e9, nu=0.3, Omega=0.0,
+                         D=1e-14, sigma_max=1e30):
+    shape, spacing = _base(shape, length)
+    one = np.ones(shape)
+    return Workload(
+        name="homogeneous", shape=shape, spacing=spacing,
+        E=E * one, nu=nu * one, Omega=Omega * one, D=D * one,
+        sigma_max=sigma_max * one, gc=1.0, lc=2.0 * spacing[0],
+        RT=GAS_R * 298.15, c_max=3.0e4,
+        c0=np.zeros(shape), d0=np.zeros(shape), loads=uniaxial_schedule(0.01, 1),
+    )
+
+
+def inclusion_workload(n=16, radius=None, n_inc=5, total_strain=0.01):
+    """Centred spherical inclusion in a unit cell (deterministic)."""
+    shape, spacing = _base((n, n, n), 1.0)
+    if radius is None:
+        radius = 4.0 * n / 16.0
+    inc = sphere_mask(shape, radius)
+    E = np.where(inc, 100e9, 10e9)
+    nu = np.where(inc, 0.25, 0.3)
+    return Workload(
+        name="inclusion", shape=shape, spacing=spacing, phase=inc,
+        E=E, nu=nu, Omega=np.zeros(shape), D=np.full(shape, 1e-14),
+        sigma_max=np.full(shape, 1e30), gc=1.0, lc=2.0 * spacing[0],
+        RT=GAS_R * 298.15, c_max=3.0e4,
+        c0=np.zeros(shape), d0=np.zeros(shape),
+        loads=uniaxial_schedule(total_strain, n_inc),
+        tol_newton=1e-8, tol_lin=1e-10,
+    )
+
+
+def particle_workload(n=128, n_steps=200, dt=5.0, q_in=4.0e-10, sigma_max=20e6):
+    """Chemo-mechanical particle: ellipsoid in a compliant buffer with an inward
+    flux on its one-voxel inner shell.  Sizes scale with n / 128."""
+    shape, spacing = _base((n, n, n), 15e-6)
+    s = n / 128.0
+    part = ellipsoid_mask(shape, (40.0 * s, 32.0 * s, 28.0 * s))
+    shell = inner_shell(part)
+    Ep, Dp = 15e9, 1e-14
+    E = np.where(part, Ep, 1e-3 * Ep)
+    nu = np.full(shape, 0.3)
+    Omega = np.where(part, 0.03, 0.0)
+    D = np.where(part, Dp, 1e-5 * Dp)
+    h = spacing[0]
+    cdot_B = np.where(shell, q_in / h, 0.0)
+    return Workload(
+        name="particle", shape=shape, spacing=spacing, phase=part, shell=shell,
+        E=E, nu=nu, Omega=Omega, D=D, sigma_max=np.full(shape, sigma_max),
+        gc=1.0, lc=2.0 * h, RT=GAS_R * 298.15, c_max=3.0e4,
+        c0=np.full(shape, 1e-2), d0=np.zeros(shape), cdot_B=cdot_B,
+        dt=dt, n_steps=n_steps, loads=[np.eye(3)] * n_steps,
+        tol_newton=1e-8, tol_lin=1e-10, tol_chem=1e-8,
+    )
+
+
+def polydisperse_workload(n=256, n_spheres=60, n_inc=20, total_strain=0.05,
+                          sigma_max=400e6):
+    """Periodic RSA spheres (radii U(10, 24) voxels at 256^3, scaled with
+    n / 256), spheres 200 GPa, matrix 10 GPa, nu = 0.3."""
+    shape, spacing = _base((n, n, n), 1.0)
+    s = n / 256.0
+    rng = rng_for(3)
+    inc, centres, radii = rsa_spheres(shape, n_spheres, 10.0 * s, 24.0 * s, rng)
+    E = np.where(inc, 200e9, 10e9)
+    return Workload(
+        name="polydisperse", shape=shape, spacing=spacing, phase=inc,
+        centres=centres, radii=radii,
+        E=E, nu=np.full(shape, 0.3), Omega=np.zeros(shape),
+        D=np.full(shape, 1e-14), sigma_max=np.full(shape, sigma_max),
+        gc=1.0, lc=2.0 * spacing[0], RT=GAS_R * 298.15, c_max=3.0e4,
+        c0=np.zeros(shape), d0=np.zeros(shape),
+        loads=uniaxial_schedule(total_strain, n_inc),
+        tol_newton=1e-8, tol_lin=1e-10,
+    )
+
+
+def batch_workloads(n_items=48, sizes=(32, 48, 64, 96), eps=1e-3):
+    """Two-phase RVEs: grid size ~ uniform over ``sizes``, Boolean spheres of
+    radius N/8 up to a volume fraction ~ U(0.1, 0.4); materials as the
+    inclusion workload; 6 load cases each."""
+    rng = rng_for(4)
+    items = []
+    for k in range(n_items):
+        n = int(rng.choice(np.asarray(sizes)))
+        phi = float(rng.uniform(0.1, 0.4))
+        shape, spacing = _base((n, n, n), 1.0)
+        inc = boolean_spheres(shape, n / 8.0, phi, rng)
+        items.append(Workload(
+            name="batch_item", index=k, shape=shape, spacing=spacing,
+            phase=inc, target_fraction=phi,
+            E=np.where(inc, 100e9, 10e9), nu=np.where(inc, 0.25, 0.3),
+            Omega=np.zeros(shape), D=np.full(shape, 1e-14),
+            sigma_max=np.full(shape, 1e30), gc=1.0, lc=2.0 * spacing[0],
+            RT=GAS_R * 298.15, c_max=3.0e4,
+            c0=np.zeros(shape), d0=np.zeros(shape),
+            loads=six_load_cases(eps),
+        ))
+    return items
+
+
+def grf_workload(n=128, corr_len=8.0):
+    """Gaussian random fields for log-stiffness and swelling coefficient."""
+    shape, spacing = _base((n, n, n), 1.0)
+    rng = rng_for(5)
+    g1 = gaussian_random_field(shape, corr_len * n / 128.0, rng)
+    g2 = gaussian_random_field(shape, corr_len * n / 128.0, rng)
+    logE = np.log(10e9) + 0.5 * g1
+    F = np.eye(3)
+    F[0, 0] += 0.02
+    return Workload(
+        name="grf", shape=shape, spacing=spacing,
+        E=np.exp(logE), nu=np.full(shape, 0.3), Omega=0.03 + 0.01 * g2,
+        D=np.full(shape, 1e-14), sigma_max=np.full(shape, 1e30),
+        gc=1.0, lc=2.0 * spacing[0], RT=GAS_R * 298.15, c_max=3.0e4,
+        c0=np.full(shape, 0.5), d0=np.zeros(shape), loads=[F],
+        fd_voxels=rng.integers(0, int(np.prod(shape)), size=32),
+        tol_newton=1e-8, tol_lin=1e-10,
+    )

@@ -1,0 +1,186 @@
+/*
+ * fgfft: Fourier-Galerkin chemo-mechanical solver core for MI355X (gfx950).
+ *
+ * C ABI of the hot path of Zarzoso, Roque, Montero-Chacon, Segurado, "An FFT
+ * based chemo-mechanical framework with fracture" (arXiv:2411.16583): the
+ * matrix-free operator  y = F^-1[ G^ : F[ K : x ] ]  applied by conjugate
+ * gradients inside the finite-strain Newton iteration (Sec. 3.2, eq. (30),
+ * Alg. 1), the preconditioned CG of the phase-field equation (eqs. (32)-(36),
+ * Alg. 2) and the backward-Euler Fick step (eqs. (42)-(50), Alg. 3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Grid: N0 x N1 x N2 voxels on a periodic box, spacing h[3] (metres), N2 the
+ * fastest axis, N = N0 N1 N2.  Supported sizes: N0, N1 in {4, 6, 8, 12, 16,
+ * 24, 32, 48, 64, 96, 128, 256}; N2 = 2 M with M in {2, 3, 4, 6, 8, 12, 16,
+ * 24, 32, 48, 64, 96, 128, 256}.  Others return FG_E_SIZE.
+ * Fields: device pointers, double precision, component-major.  A scalar field
+ * is N doubles in C order (index (i0 N1 + i1) N2 + i2); a 3x3 tensor field is
+ * 9 such planes, plane 3 i + j holding the ij component (row-major tensor
+ * index, so F_ij = du_i / dX_j).  Tensors passed by value (F_macro, P_avg)
+ * are host arrays of 9 doubles, row-major.
+ * Memory: every field, material array and the workspace is owned by the
+ * caller (for example PyTorch tensors) and must stay valid until it is
+ * replaced or the plan is destroyed.  The library allocates no device
+ * memory; it owns only the opaque plan and a little pinned host memory for
+ * scalar read-backs.
+ * Streams: all device work is issued on the stream given at plan creation
+ * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL is the
+ * default stream).  Calls that return solver statistics synchronise that
+ * stream; fg_fft_* and fg_apply_operator do not.
+ * Errors: every call returns an fg_status; nothing throws across the ABI.
+ * Arguments are validated before any device work is issued; on error the
+ * device state is unchanged unless the description says otherwise.
+ * fg_last_error returns a message for the last failing call on a plan.
+ */
+#ifndef FGFFT_H
+#define FGFFT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fg_plan fg_plan;
+
+typedef enum {
+  FG_OK = 0,
+  FG_E_ARG = 1,       /* null pointer, bad value                         */
+  FG_E_SIZE = 2,      /* unsupported grid size or workspace too small    */
+  FG_E_HIP = 3,       /* a HIP runtime call failed                       */
+  FG_E_NOCONV = 4,    /* Newton / Krylov iteration limit reached         */
+  FG_E_BREAKDOWN = 5, /* p.Ap <= 0 inside CG (operator not SPD)          */
+  FG_E_DOMAIN = 6,    /* det F <= 0, 1 + Omega c <= 0 or c outside (0,1) */
+  FG_E_STATE = 7      /* workspace, material or state not set            */
+} fg_status;
+
+/* FG_FP64: everything in double precision.
+ * FG_MIXED: the CG operator (tangent state, FFTs, CG vectors) in single
+ * precision with double-precision dot products; the Newton residual, the
+ * stress and F stay double, so Newton refines to the double tolerance. */
+typedef enum { FG_FP64 = 0, FG_MIXED = 1 } fg_precision;
+
+typedef struct {
+  double tol_newton; /* err_res tolerance (eq. (31)), e.g. 1e-8           */
+  double tol_lin;    /* CG tolerance ||r|| <= tol ||b||, e.g. 1e-10       */
+  int max_newton;    /* Newton iteration limit, e.g. 50                   */
+  int max_lin;       /* CG iteration limit per solve                      */
+  int fixed_lin;     /* > 0: run exactly this many CG iterations per solve
+                        (tol_lin ignored); used for matched-count parity   */
+} fg_solver_opts;
+
+typedef struct {
+  int newton_iters;    /* Newton corrections applied                      */
+  int lin_iters_total; /* CG iterations summed over the Newton loop       */
+  int lin_iters_last;  /* CG iterations of the last linear solve          */
+  int n_history;       /* entries used in err_history                     */
+  double err_res;      /* final equilibrium residual (eq. (31))           */
+  double lin_relres;   /* final ||r|| / ||b|| of the last linear solve    */
+  double err_history[64]; /* err_res before each Newton correction       */
+  int lin_history[64];    /* CG iterations of each Newton correction      */
+} fg_stats;
+
+/* Create a plan for an N0 x N1 x N2 periodic grid with spacing h (Sec. 3.2:
+ * voxel grid, DFT over the three axes).  grid: 3 ints, spacing: 3 doubles
+ * (host).  stream: hipStream_t or NULL.  *out receives the plan.
+ * Errors: FG_E_ARG (null pointers, h <= 0), FG_E_SIZE (unsupported size). */
+fg_status fg_plan_create(const int grid[3], const double spacing[3], fg_precision prec,
+                         void* stream, fg_plan** out);
+
+/* Bytes of device workspace the plan needs (0 for a null plan). */
+size_t fg_plan_workspace_bytes(const fg_plan* plan);
+
+/* Hand the plan a caller-owned device buffer of at least
+ * fg_plan_workspace_bytes bytes, 256-byte aligned.  The plan writes its
+ * transform and symbol tables into it (asynchronously on the plan stream).
+ * Errors: FG_E_ARG, FG_E_SIZE (too small), FG_E_HIP. */
+fg_status fg_plan_set_workspace(fg_plan* plan, void* dev, size_t bytes);
+
+/* Material fields (Sec. 2; Table of Sec. 4.3 for the kind of data): Young's
+ * modulus E (Pa), Poisson ratio nu, swelling coefficient Omega (eq. (2)),
+ * diffusivity D (m^2/s, eq. (20)) and threshold stress sigma_max (Pa,
+ * eq. (8)); device arrays of N doubles each (D and sigma_max may be NULL if
+ * the chemistry / fracture calls are not used).  Scalars: fracture
+ * toughness gc (J/m^2), length scale lc (m) (eq. (5)), RT (J/mol) and the
+ * concentration scale c_max (mol/m^3) that converts the elastic chemical
+ * potential to J/mol.  Errors: FG_E_ARG. */
+fg_status fg_set_material(fg_plan* plan, const double* E, const double* nu, const double* Omega,
+                          const double* D, const double* sigma_max, double gc, double lc, double RT,
+                          double c_max);
+
+/* State fields, updated in place by the solvers: F (9 N, the deformation
+ * gradient, Sec. 3.1 eq. (23)), c (N, concentration in (0,1)), d (N, phase
+ * field), H (N, history of eq. (7)).  c, d and H may be NULL for pure
+ * mechanics (then c = d = 0).  Errors: FG_E_ARG. */
+fg_status fg_set_state(fg_plan* plan, double* F, double* c, double* d, double* H);
+
+/* Alg. 1 "Mechanical problem": add the macroscopic increment
+ * F_macro - <F> to F (F^0 = F_t + dFbar, the fluctuation is kept) and run
+ * Newton with a CG inner solve of eq. (30) until err_res (eq. (31),
+ * normalised by ||G*P(F_macro)||) <= tol_newton.  F_macro: host, 9 doubles.
+ * stats may be NULL.  Errors: FG_E_STATE, FG_E_NOCONV (F holds the last
+ * iterate), FG_E_BREAKDOWN, FG_E_DOMAIN, FG_E_HIP. */
+fg_status fg_newton_solve(fg_plan* plan, const double F_macro[9], const fg_solver_opts* opts,
+                          fg_stats* stats);
+
+/* Equilibrium residual of the current state (eq. (31)) with respect to the
+ * macroscopic F_macro (host, 9 doubles): *err_res (host).  Synchronises. */
+fg_status fg_residual(fg_plan* plan, const double F_macro[9], double* err_res);
+
+/* Homogenised first Piola-Kirchhoff stress <P> of the current state (Sec.
+ * 3.1): P_avg, host, 9 doubles.  Synchronises. */
+fg_status fg_homogenized_stress(fg_plan* plan, double P_avg[9]);
+
+/* First Piola-Kirchhoff stress field of the current state into P (device,
+ * 9 N doubles, caller-owned).  Errors: FG_E_DOMAIN (checked after a sync). */
+fg_status fg_stress(fg_plan* plan, double* P);
+
+/* One application of the operator of eq. (30) with the tangent of the
+ * current state: y = F^-1[ G^ : F[ K(F) : x ] ]  (x, y: device, 9 N doubles,
+ * may not alias).  In FG_MIXED plans the contraction and the transforms
+ * run in single precision.  Does not synchronise. */
+fg_status fg_apply_operator(fg_plan* plan, const double* x, double* y);
+
+/* Compatibility projection y = F^-1[ G^ : F[x] ] (eq. (28)), double
+ * precision (x, y: device, 9 N doubles; y may equal x).  Does not sync. */
+fg_status fg_project(fg_plan* plan, const double* x, double* y);
+
+/* 3-D real transform of ncomp scalar fields, double precision, in place:
+ * fg_fft_r2c turns ncomp real fields (ncomp N doubles) into the packed half
+ * spectrum (the same bytes: ncomp x N0 x N1 x N2/2 complex, where the kx = 0
+ * entry of each (kz, ky) line holds the real DC-plane value in .x and the
+ * real Nyquist-plane value in .y only after the N2 pass; after all three
+ * passes kx = 0 holds A + i B with A, B the 2-D spectra of the kx = 0 and
+ * kx = N2/2 planes).  fg_fft_c2r is its exact inverse including the 1/N
+ * normalisation.  Diagnostic entry points (parity of the transform). */
+fg_status fg_fft_r2c(fg_plan* plan, double* data, int ncomp);
+fg_status fg_fft_c2r(fg_plan* plan, double* data, int ncomp);
+
+/* Phase-field problem (Alg. 2): update the history H <- max(H, gc/(2 lc)
+ * D_f(sigma)) from the current F and c (eqs. (7), (8), effective Cauchy
+ * stress), then solve [gc/lc + 2H] d - gc lc Lap d = 2H (eq. (32)) for d by
+ * CG with the preconditioner of eq. (36), to ||r|| <= tol_lin ||b||.
+ * stats: lin_iters_last, lin_relres.  Errors: FG_E_STATE, FG_E_NOCONV,
+ * FG_E_BREAKDOWN, FG_E_HIP. */
+fg_status pff_solve(fg_plan* plan, const fg_solver_opts* opts, fg_stats* stats);
+
+/* Backward-Euler Fick step (Alg. 3, eq. (42)): Newton on
+ * f(c) = c - c_t + dt div[M(d) c_t(1-c_t) C^-1 grad mu(c)] - dt cdot_B with
+ * the linear step solved by preconditioned CG in dmu = w dc (w = RT(1/c +
+ * 1/(1-c))); stops when ||dc|| / ||c_t|| < tol_newton.  Uses the stored F
+ * and d.  cdot_B: device, N doubles (source of eq. (37)/(40)), may be NULL.
+ * Errors: FG_E_STATE, FG_E_DOMAIN (c leaves (0,1)), FG_E_NOCONV,
+ * FG_E_BREAKDOWN, FG_E_HIP. */
+fg_status fick_step(fg_plan* plan, double dt, const double* cdot_B, const fg_solver_opts* opts,
+                    fg_stats* stats);
+
+const char* fg_status_string(fg_status s);
+const char* fg_last_error(const fg_plan* plan);
+void fg_plan_destroy(fg_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGFFT_H */

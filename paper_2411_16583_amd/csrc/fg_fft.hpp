@@ -1,0 +1,579 @@
+// Batched 1-D FFTs of one line length L inside a workgroup, and the three
+// axis passes of the 3-D real transform used by the Fourier-Galerkin
+// operator (Sec. 3.2 "FFT resolution algorithms", eq. (30)).
+//
+// Line algorithm: two-stage Cooley-Tukey with L = R1 * R2.  T threads share a
+// line (T = gcd(R1, R2)); each thread keeps E = L / T elements in registers
+// and the only exchange between the stages goes through LDS:
+//   layout A (natural): thread t holds x[(t + T u) + R2 n1], e = u R1 + n1
+//   layout B (spectral): thread t holds X[(t + T v) + R1 k2], e = v R2 + k2
+// fwd: A -> B (stage 1 radix R1 over n1, twiddle W_L^{b k1}, stage 2 radix R2)
+// inv: B -> A (the mirror image), so a spectrum produced by fwd can be
+// multiplied pointwise and transformed back without any reordering.
+//
+// 3-D real layout: (C, N0, N1, N2) with N2 fastest.  The half spectrum is
+// stored "packed" in exactly the same bytes, (C, N0, N1, M) complex with
+// M = N2 / 2: along N2 the DC and Nyquist coefficients of a real line are
+// both real, and X[0] holds (Re X_0, Re X_M).  After the N1 and N0 passes
+// the kx = 0 column therefore carries A + i B, A and B being the 2-D spectra
+// of the kx = 0 and kx = M planes; the pointwise operator separates them with
+// the partner column at (-kz, -ky) (kernel k_fft_z_dc).
+#pragma once
+#include "fg_complex.hpp"
+
+namespace fg {
+
+template <int L> struct LineShape;
+#define FG_LINE_SHAPE(L_, R1_, R2_) \
+  template <> struct LineShape<L_> { static constexpr int R1 = R1_, R2 = R2_; };
+FG_LINE_SHAPE(2, 2, 1)
+FG_LINE_SHAPE(3, 3, 1)
+FG_LINE_SHAPE(4, 4, 1)
+FG_LINE_SHAPE(6, 6, 1)
+FG_LINE_SHAPE(8, 8, 1)
+FG_LINE_SHAPE(12, 12, 1)
+FG_LINE_SHAPE(16, 4, 4)
+FG_LINE_SHAPE(24, 6, 4)
+FG_LINE_SHAPE(32, 8, 4)
+FG_LINE_SHAPE(48, 12, 4)
+FG_LINE_SHAPE(64, 8, 8)
+FG_LINE_SHAPE(96, 12, 8)
+FG_LINE_SHAPE(128, 16, 8)
+FG_LINE_SHAPE(256, 16, 16)
+#undef FG_LINE_SHAPE
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
+template <int L> struct Line {
+  static constexpr int R1 = LineShape<L>::R1;
+  static constexpr int R2 = LineShape<L>::R2;
+  static constexpr int T = (R2 == 1) ? 1 : cgcd(R1, R2);
+  static constexpr int U = R2 / T;
+  static constexpr int V = R1 / T;
+  static constexpr int E = L / T;
+  __device__ __forceinline__ static int idxA(int t, int e) {
+    return t + T * (e / R1) + R2 * (e % R1);
+  }
+  __device__ __forceinline__ static int idxB(int t, int e) {
+    return t + T * (e / R2) + R1 * (e % R2);
+  }
+};
+
+// Multiply by the stage twiddle W_L^{j} (table tw[j] = e^{-2 pi i j / L}).
+template <bool INV, typename C>
+__device__ __forceinline__ C twiddle_tab(C a, const C* __restrict__ tw, int j) {
+  C w = tw[j];
+  return INV ? cmulc(a, w) : cmul(a, w);
+}
+
+// Forward (or, with INV, inverse) DFT of a line, layout A -> layout B.
+// lds: the line's exchange buffer, element i at lds[i * ls].  Ends with a
+// barrier so that the caller may reuse the buffer immediately.
+template <int L, bool INV, typename C>
+__device__ __forceinline__ void line_fft_AB(C (&v)[Line<L>::E], C* lds, int ls, int t,
+                                            const C* __restrict__ tw) {
+  using LS = Line<L>;
+  if constexpr (LS::R2 == 1) {
+    Dft<LS::R1, 1, INV, C>::run(v);
+  } else {
+#pragma unroll
+    for (int u = 0; u < LS::U; ++u) {
+      const int b = t + LS::T * u;
+      Dft<LS::R1, 1, INV, C>::run(v + u * LS::R1);
+#pragma unroll
+      for (int k1 = 1; k1 < LS::R1; ++k1)
+        v[u * LS::R1 + k1] = twiddle_tab<INV>(v[u * LS::R1 + k1], tw, (b * k1) % L);
+#pragma unroll
+      for (int k1 = 0; k1 < LS::R1; ++k1) lds[(k1 * LS::R2 + b) * ls] = v[u * LS::R1 + k1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < LS::V; ++w) {
+      const int k1 = t + LS::T * w;
+#pragma unroll
+      for (int n2 = 0; n2 < LS::R2; ++n2) v[w * LS::R2 + n2] = lds[(k1 * LS::R2 + n2) * ls];
+      Dft<LS::R2, 1, INV, C>::run(v + w * LS::R2);
+    }
+    __syncthreads();
+  }
+}
+
+// Inverse DFT of a line, layout B -> layout A (mirror of line_fft_AB).
+template <int L, typename C>
+__device__ __forceinline__ void line_ifft_BA(C (&v)[Line<L>::E], C* lds, int ls, int t,
+                                             const C* __restrict__ tw) {
+  using LS = Line<L>;
+  if constexpr (LS::R2 == 1) {
+    Dft<LS::R1, 1, true, C>::run(v);
+  } else {
+#pragma unroll
+    for (int w = 0; w < LS::V; ++w) {
+      const int k1 = t + LS::T * w;
+      Dft<LS::R2, 1, true, C>::run(v + w * LS::R2);
+#pragma unroll
+      for (int n2 = 1; n2 < LS::R2; ++n2)
+        v[w * LS::R2 + n2] = twiddle_tab<true>(v[w * LS::R2 + n2], tw, (n2 * k1) % L);
+#pragma unroll
+      for (int n2 = 0; n2 < LS::R2; ++n2) lds[(n2 * LS::R1 + k1) * ls] = v[w * LS::R2 + n2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < LS::U; ++u) {
+      const int n2 = t + LS::T * u;
+#pragma unroll
+      for (int k1 = 0; k1 < LS::R1; ++k1) v[u * LS::R1 + k1] = lds[(n2 * LS::R1 + k1) * ls];
+      Dft<LS::R1, 1, true, C>::run(v + u * LS::R1);
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Deterministic block reduction of one double per thread.  Fixed shuffle tree
+// within a wave, then wave partials summed in order by thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red /*>= 16 doubles in LDS*/) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < nw; ++k) s += red[k];
+  return s;  // valid in thread 0 only
+}
+
+// Tables of one 3-D plan (device pointers), in the working precision R.
+template <typename R> struct SpecTables {
+  const cplx<R>* tw0;   // W_{N0}^j, j < N0
+  const cplx<R>* tw1;   // W_{N1}^j
+  const cplx<R>* twM;   // W_M^j, M = N2/2
+  const cplx<R>* post;  // W_{N2}^k, k < M (real <-> half-length complex)
+  const R* cz;          // cos(pi kz / N0), exact 0 at kz = N0/2
+  const R* sz;          // (2/h0) sin(pi kz / N0)
+  const R* cy;          // cos(pi ky / N1)
+  const R* sy;          // (2/h1) sin(pi ky / N1)
+  const R* cx;          // cos(pi kx / N2), kx = 0..M, exact 0 at kx = M
+  const R* sx;          // (2/h2) sin(pi kx / N2)
+};
+
+// ----------------------------------------------------------------------------
+// Pass 1: real-to-complex along N2 for nlines lines (in place allowed).
+// Workgroups of the two real passes have XBLOCK threads (LPB lines).
+constexpr int XBLOCK = 128;
+
+template <typename R, int M>
+__global__ void __launch_bounds__(XBLOCK)
+k_fft_x_r2c(const R* in, R* out, long nlines, SpecTables<R> tb, const int* skip) {
+  using C = cplx<R>;
+  using LS = Line<M>;
+  constexpr int LPB = XBLOCK / LS::T;
+  constexpr int PAD = (M >= 16) ? 1 : 0;
+  __shared__ C lds[LPB * (M + PAD)];
+  if (skip && *skip) return;
+  const int t = threadIdx.x % LS::T;
+  const int ll = threadIdx.x / LS::T;
+  const long line = (long)blockIdx.x * LPB + ll;
+  const bool active = line < nlines;
+  const C* src = reinterpret_cast<const C*>(in) + line * M;
+  C* dst = reinterpret_cast<C*>(out) + line * M;
+  C* my = lds + ll * (M + PAD);
+  C v[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = active ? src[LS::idxA(t, e)] : mk<C>(R(0), R(0));
+  line_fft_AB<M, false>(v, my, 1, t, tb.twM);
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) my[LS::idxB(t, e)] = v[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const int k = LS::idxB(t, e);
+    const C zk = my[k];
+    C X;
+    if (k == 0) {
+      X = mk<C>(zk.x + zk.y, zk.x - zk.y);  // (Re X_0, Re X_M)
+    } else {
+      const C zm = my[M - k];
+      const C ev = cscale(cadd(zk, cconj(zm)), R(0.5));
+      const C od = cscale(mul_mi(csub(zk, cconj(zm))), R(0.5));
+      X = cadd(ev, cmul(od, tb.post[k]));
+    }
+    if (active) dst[k] = X;
+  }
+}
+
+// Epilogue of the inverse real pass: y = scale * x_out is stored (type R,
+// into out) and sum(y * dotv) (or sum(y*y) when dotv == nullptr) is reduced
+// per block into partials[blockIdx.x] (FP64).  A block skips everything when
+// *skip is nonzero.
+struct C2REpi {
+  double scale;
+  const void* dotv;  // same type R as the output, or nullptr
+  bool self_dot;     // sum y*y
+  double* partials;  // nullptr: no reduction
+  const int* skip;   // nullptr or device flag
+};
+
+template <typename R, int M>
+__global__ void __launch_bounds__(XBLOCK)
+k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
+  using C = cplx<R>;
+  using LS = Line<M>;
+  constexpr int LPB = XBLOCK / LS::T;
+  constexpr int PAD = (M >= 16) ? 1 : 0;
+  __shared__ C lds[LPB * (M + PAD)];
+  __shared__ double red[16];
+  if (epi.skip && *epi.skip) return;
+  const int t = threadIdx.x % LS::T;
+  const int ll = threadIdx.x / LS::T;
+  const long line = (long)blockIdx.x * LPB + ll;
+  const bool active = line < nlines;
+  const C* src = reinterpret_cast<const C*>(in) + line * M;
+  C* my = lds + ll * (M + PAD);
+  C v[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const int k = LS::idxA(t, e);
+    C Z = mk<C>(R(0), R(0));
+    if (active) {
+      const C xk = src[k];
+      if (k == 0) {
+        Z = mk<C>(xk.x + xk.y, xk.x - xk.y);
+      } else {
+        const C xm = src[M - k];
+        const C s = cadd(xk, cconj(xm));
+        const C d = cmulc(csub(xk, cconj(xm)), tb.post[k]);  // * W^{-k}
+        Z = cadd(s, mul_pi(d));
+      }
+    }
+    v[e] = Z;
+  }
+  line_fft_AB<M, true>(v, my, 1, t, tb.twM);
+  // v[e] = N2 * (x[2n] + i x[2n+1]) with n = idxB(t, e)
+  C* dst = reinterpret_cast<C*>(out) + line * M;
+  const C* dv = reinterpret_cast<const C*>(epi.dotv) + line * M;
+  const R sg = (R)epi.scale;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const int n = LS::idxB(t, e);
+    const C y = cscale(v[e], sg);
+    if (active) {
+      dst[n] = y;
+      if (epi.partials) {
+        if (epi.self_dot) {
+          acc += (double)y.x * (double)y.x + (double)y.y * (double)y.y;
+        } else {
+          const C q = dv[n];
+          acc += (double)y.x * (double)q.x + (double)y.y * (double)q.y;
+        }
+      }
+    }
+  }
+  if (epi.partials) {
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) epi.partials[blockIdx.x] = s;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Complex FFT of length L along one axis for tiles of B adjacent kx columns.
+// Element e of the line of column col: base + e * estride, with
+// base = data + blockIdx.y * ystride + blockIdx.z * zstride + blockIdx.x * B + col
+// (complex units).  Used for the N1 pass (estride = M) and, in the diagnostic
+// transforms, for the N0 pass (estride = N1 M).
+template <typename R, int L, bool INV>
+__global__ void __launch_bounds__(256)
+k_fft_axis(R* data, long estride, long ystride, long zstride, int B, const cplx<R>* __restrict__ tw,
+           const int* skip) {
+  using C = cplx<R>;
+  using LS = Line<L>;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  if (skip && *skip) return;
+  const int col = threadIdx.x % B;
+  const int t = threadIdx.x / B;
+  C* base = reinterpret_cast<C*>(data) + (long)blockIdx.y * ystride + (long)blockIdx.z * zstride +
+            (long)blockIdx.x * B + col;
+  C v[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = base[(long)LS::idxA(t, e) * estride];
+  line_fft_AB<L, INV>(v, lds + col, B, t, tw);
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) base[(long)LS::idxB(t, e) * estride] = v[e];
+}
+
+// ----------------------------------------------------------------------------
+// Pass 3 with the projection (eq. (28), (30)): per row i of the 3x3 field,
+// Z_ij = (sum_l A_il r_l) r_j / |r|^2 * scale, r the rotated-scheme vector.
+// Grid (M/B, N1, 3 rows).  The kx = 0 column is left to k_fft_z_dc.
+template <typename R> struct RVec {
+  R x, y, z;
+};
+
+template <typename R>
+__device__ __forceinline__ RVec<R> rot_vec(const SpecTables<R>& tb, int kz, int ky, int kx) {
+  const R cz = tb.cz[kz], sz = tb.sz[kz];
+  const R cy = tb.cy[ky], sy = tb.sy[ky];
+  const R cx = tb.cx[kx], sx = tb.sx[kx];
+  // components along axes 0 (z), 1 (y), 2 (x) of the grid = tensor index j
+  RVec<R> r;
+  r.x = sz * cy * cx;  // j = 0 (axis 0)
+  r.y = cz * sy * cx;  // j = 1 (axis 1)
+  r.z = cz * cy * sx;  // j = 2 (axis 2)
+  return r;
+}
+
+template <typename R>
+__device__ __forceinline__ R rget(const RVec<R>& r, int j) {
+  return j == 0 ? r.x : (j == 1 ? r.y : r.z);
+}
+
+template <typename R, int L>
+__global__ void __launch_bounds__(256)
+k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, const int* skip) {
+  using C = cplx<R>;
+  using LS = Line<L>;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  if (skip && *skip) return;
+  const int col = threadIdx.x % B;
+  const int t = threadIdx.x / B;
+  const int kx = blockIdx.x * B + col;
+  const int ky = blockIdx.y;
+  const int i = blockIdx.z;
+  const long plane = (long)N1 * M;
+  const long comp = (long)L * plane;
+  C* base = reinterpret_cast<C*>(data) + (long)ky * M + kx;
+  C acc[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) acc[e] = mk<C>(R(0), R(0));
+  for (int l = 0; l < 3; ++l) {
+    C* src = base + (3 * i + l) * comp;
+    C v[LS::E];
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) v[e] = src[LS::idxA(t, e) * plane];
+    line_fft_AB<L, false>(v, lds + col, B, t, tb.tw0);
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const RVec<R> r = rot_vec(tb, LS::idxB(t, e), ky, kx);
+      const R rl = rget(r, l);
+      acc[e] = mk<C>(acc[e].x + v[e].x * rl, acc[e].y + v[e].y * rl);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const RVec<R> r = rot_vec(tb, LS::idxB(t, e), ky, kx);
+    const R r2 = r.x * r.x + r.y * r.y + r.z * r.z;
+    const R f = (r2 > R(0)) ? scale / r2 : R(0);
+    acc[e] = cscale(acc[e], f);
+  }
+  for (int j = 0; j < 3; ++j) {
+    C v[LS::E];
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const RVec<R> r = rot_vec(tb, LS::idxB(t, e), ky, kx);
+      v[e] = cscale(acc[e], rget(r, j));
+    }
+    line_ifft_BA<L>(v, lds + col, B, t, tb.tw0);
+    if (kx != 0) {
+      C* dst = base + (3 * i + j) * comp;
+#pragma unroll
+      for (int e = 0; e < LS::E; ++e) dst[LS::idxA(t, e) * plane] = v[e];
+    }
+  }
+}
+
+// Scalar symbol variant (preconditioners of Alg. 2 / Alg. 3):
+//   Z = A * scale / (a0 + a1 lambda(q)),  lambda = sum_j (2/h_j)^2 sin^2(q_j/2).
+template <typename R>
+__device__ __forceinline__ R lap_sym(const SpecTables<R>& tb, int kz, int ky, int kx) {
+  const R a = tb.sz[kz], b = tb.sy[ky], c = tb.sx[kx];
+  return a * a + b * b + c * c;
+}
+
+template <typename R, int L>
+__global__ void __launch_bounds__(256)
+k_fft_z_scalar(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, double a0, double a1,
+               const int* skip) {
+  using C = cplx<R>;
+  using LS = Line<L>;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  if (skip && *skip) return;
+  const int col = threadIdx.x % B;
+  const int t = threadIdx.x / B;
+  const int kx = blockIdx.x * B + col;
+  const int ky = blockIdx.y;
+  const long plane = (long)N1 * M;
+  C* base = reinterpret_cast<C*>(data) + (long)ky * M + kx;
+  C v[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = base[LS::idxA(t, e) * plane];
+  line_fft_AB<L, false>(v, lds + col, B, t, tb.tw0);
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const double den = a0 + a1 * (double)lap_sym(tb, LS::idxB(t, e), ky, kx);
+    v[e] = cscale(v[e], (R)((double)scale / den));
+  }
+  line_ifft_BA<L>(v, lds + col, B, t, tb.tw0);
+  if (kx != 0) {
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) base[LS::idxA(t, e) * plane] = v[e];
+  }
+}
+
+// kx = 0 column: the packed value is A + i B (A: plane kx = 0, B: plane
+// kx = N2/2, both spectra of real fields).  A workgroup takes the column pair
+// (ky, -ky), transforms along N0, separates
+//   A(k) = (P(k) + conj P(-k)) / 2,   B(k) = (P(k) - conj P(-k)) / (2i),
+// applies the operator at qx = 0 to A and at qx = pi to B, and recombines.
+// OP = 0: projection (3 rows, grid.y = 3); OP = 1: scalar symbol.
+template <typename R, int L, int OP>
+__global__ void __launch_bounds__(64)
+k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, const int* skip) {
+  using C = cplx<R>;
+  using LS = Line<L>;
+  constexpr int NC = (OP == 0) ? 3 : 1;
+  __shared__ C xbuf[2 * L];
+  __shared__ C spec[NC * 2 * L];
+  if (skip && *skip) return;
+  const int col = threadIdx.x % 2;
+  const int t = threadIdx.x / 2;
+  if (t >= LS::T) {
+    // idle lanes still take part in every barrier below
+  }
+  const bool lane_ok = t < LS::T;
+  const int ky0 = blockIdx.x;
+  const int ky1 = (N1 - ky0) % N1;
+  const int myky = col ? ky1 : ky0;
+  const int i = blockIdx.y;
+  const long plane = (long)N1 * M;
+  const long comp = (long)L * plane;
+  C* base = reinterpret_cast<C*>(data) + (long)myky * M;  // kx = 0
+  const int c0 = (OP == 0) ? 3 * i : 0;
+  for (int l = 0; l < NC; ++l) {
+    C v[LS::E];
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e)
+      v[e] = lane_ok ? base[(c0 + l) * comp + LS::idxA(t, e) * plane] : mk<C>(R(0), R(0));
+    if constexpr (LS::R2 == 1) {
+      Dft<LS::R1, 1, false, C>::run(v);
+    } else {
+      // same two-stage transform, guarded for the idle lanes
+#pragma unroll
+      for (int u = 0; u < LS::U; ++u) {
+        const int b = t + LS::T * u;
+        Dft<LS::R1, 1, false, C>::run(v + u * LS::R1);
+#pragma unroll
+        for (int k1 = 1; k1 < LS::R1; ++k1)
+          if (lane_ok) v[u * LS::R1 + k1] = twiddle_tab<false>(v[u * LS::R1 + k1], tb.tw0, (b * k1) % L);
+        if (lane_ok)
+#pragma unroll
+          for (int k1 = 0; k1 < LS::R1; ++k1) xbuf[(k1 * LS::R2 + b) * 2 + col] = v[u * LS::R1 + k1];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < LS::V; ++w) {
+        const int k1 = t + LS::T * w;
+        if (lane_ok)
+#pragma unroll
+          for (int n2 = 0; n2 < LS::R2; ++n2) v[w * LS::R2 + n2] = xbuf[(k1 * LS::R2 + n2) * 2 + col];
+        Dft<LS::R2, 1, false, C>::run(v + w * LS::R2);
+      }
+      __syncthreads();
+    }
+    if (lane_ok)
+#pragma unroll
+      for (int e = 0; e < LS::E; ++e) spec[(l * 2 + col) * L + LS::idxB(t, e)] = v[e];
+  }
+  __syncthreads();
+  // separate, apply, recombine: thread (t, col) owns kz = idxB(t, e) of its column
+  C tA[LS::E], tB[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    tA[e] = mk<C>(R(0), R(0));
+    tB[e] = mk<C>(R(0), R(0));
+  }
+  if (lane_ok) {
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const int kz = LS::idxB(t, e);
+      const int kzm = (L - kz) % L;
+      if constexpr (OP == 0) {
+        const RVec<R> rA = rot_vec(tb, kz, myky, 0);
+        const RVec<R> rB = rot_vec(tb, kz, myky, M);
+        for (int l = 0; l < 3; ++l) {
+          const C P = spec[(l * 2 + col) * L + kz];
+          const C Pm = spec[(l * 2 + (1 - col)) * L + kzm];
+          const C A = cscale(cadd(P, cconj(Pm)), R(0.5));
+          const C Bv = cscale(mul_mi(csub(P, cconj(Pm))), R(0.5));
+          const R ra = rget(rA, l), rb = rget(rB, l);
+          tA[e] = mk<C>(tA[e].x + A.x * ra, tA[e].y + A.y * ra);
+          tB[e] = mk<C>(tB[e].x + Bv.x * rb, tB[e].y + Bv.y * rb);
+        }
+        const R a2 = rA.x * rA.x + rA.y * rA.y + rA.z * rA.z;
+        const R b2 = rB.x * rB.x + rB.y * rB.y + rB.z * rB.z;
+        tA[e] = cscale(tA[e], a2 > R(0) ? scale / a2 : R(0));
+        tB[e] = cscale(tB[e], b2 > R(0) ? scale / b2 : R(0));
+      } else {
+        const C P = spec[col * L + kz];
+        const C Pm = spec[(1 - col) * L + kzm];
+        const C A = cscale(cadd(P, cconj(Pm)), R(0.5));
+        const C Bv = cscale(mul_mi(csub(P, cconj(Pm))), R(0.5));
+        const double dA = a0 + a1 * (double)lap_sym(tb, kz, myky, 0);
+        const double dB = a0 + a1 * (double)lap_sym(tb, kz, myky, M);
+        tA[e] = cscale(A, (R)((double)scale / dA));
+        tB[e] = cscale(Bv, (R)((double)scale / dB));
+      }
+    }
+  }
+  const bool store = lane_ok && (col == 0 || ky1 != ky0);
+  for (int j = 0; j < NC; ++j) {
+    C v[LS::E];
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      R fa = R(1), fb = R(1);
+      if constexpr (OP == 0) {
+        const int kz = LS::idxB(t, e);
+        fa = rget(rot_vec(tb, kz, myky, 0), j);
+        fb = rget(rot_vec(tb, kz, myky, M), j);
+      }
+      const C a = cscale(tA[e], fa);
+      const C b = cscale(tB[e], fb);
+      v[e] = cadd(a, mul_pi(b));  // A' + i B'
+    }
+    if constexpr (LS::R2 == 1) {
+      Dft<LS::R1, 1, true, C>::run(v);
+    } else {
+#pragma unroll
+      for (int w = 0; w < LS::V; ++w) {
+        const int k1 = t + LS::T * w;
+        Dft<LS::R2, 1, true, C>::run(v + w * LS::R2);
+#pragma unroll
+        for (int n2 = 1; n2 < LS::R2; ++n2)
+          if (lane_ok) v[w * LS::R2 + n2] = twiddle_tab<true>(v[w * LS::R2 + n2], tb.tw0, (n2 * k1) % L);
+        if (lane_ok)
+#pragma unroll
+          for (int n2 = 0; n2 < LS::R2; ++n2) xbuf[(n2 * LS::R1 + k1) * 2 + col] = v[w * LS::R2 + n2];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < LS::U; ++u) {
+        const int n2 = t + LS::T * u;
+        if (lane_ok)
+#pragma unroll
+          for (int k1 = 0; k1 < LS::R1; ++k1) v[u * LS::R1 + k1] = xbuf[(n2 * LS::R1 + k1) * 2 + col];
+        Dft<LS::R1, 1, true, C>::run(v + u * LS::R1);
+      }
+      __syncthreads();
+    }
+    if (store)
+#pragma unroll
+      for (int e = 0; e < LS::E; ++e) base[(c0 + j) * comp + LS::idxA(t, e) * plane] = v[e];
+  }
+}
+
+}  // namespace fg

@@ -1,0 +1,122 @@
+// Definitions of the FFT pass launchers (included by fg_fft_f64.hip and
+// fg_fft_f32.hip, one working precision each).
+#pragma once
+#include <stdexcept>
+
+#include "fg_launch.hpp"
+
+namespace fg {
+
+#define FG_FOR_M(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
+#define FG_FOR_AXIS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
+
+template <typename R>
+void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const int* skip,
+                hipStream_t s) {
+  switch (M) {
+#define FG_CASE(L_)                                                                        \
+  case L_: {                                                                               \
+    constexpr int LPB = XBLOCK / Line<L_>::T;                                              \
+    const long blocks = (nlines + LPB - 1) / LPB;                                          \
+    hipLaunchKernelGGL((k_fft_x_r2c<R, L_>), dim3((unsigned)blocks), dim3(XBLOCK), 0, s, in, out, \
+                       nlines, tb, skip);                                                  \
+    return;                                                                                \
+  }
+    FG_FOR_M(FG_CASE)
+#undef FG_CASE
+  }
+  throw std::invalid_argument("unsupported N2/2");
+}
+
+template <typename R>
+int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const C2REpi& epi,
+               hipStream_t s) {
+  switch (M) {
+#define FG_CASE(L_)                                                                        \
+  case L_: {                                                                               \
+    constexpr int LPB = XBLOCK / Line<L_>::T;                                              \
+    const long blocks = (nlines + LPB - 1) / LPB;                                          \
+    hipLaunchKernelGGL((k_fft_x_c2r<R, L_>), dim3((unsigned)blocks), dim3(XBLOCK), 0, s, in, out, \
+                       nlines, tb, epi);                                                   \
+    return (int)blocks;                                                                    \
+  }
+    FG_FOR_M(FG_CASE)
+#undef FG_CASE
+  }
+  throw std::invalid_argument("unsupported N2/2");
+}
+
+template <typename R>
+void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
+                 const cplx<R>* tw, const int* skip, hipStream_t s) {
+  const int B = column_tile(L, M, (int)sizeof(cplx<R>));
+  const int T = line_threads(L);
+  const size_t shm = (size_t)L * B * sizeof(cplx<R>);
+  dim3 grid((unsigned)(M / B), (unsigned)gy, (unsigned)gz);
+  switch (L) {
+#define FG_CASE(L_)                                                                                  \
+  case L_:                                                                                           \
+    if (inv)                                                                                         \
+      hipLaunchKernelGGL((k_fft_axis<R, L_, true>), grid, dim3(T * B), shm, s, data, estride, ystride, \
+                         zstride, B, tw, skip);                                                      \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_fft_axis<R, L_, false>), grid, dim3(T * B), shm, s, data, estride,       \
+                         ystride, zstride, B, tw, skip);                                             \
+    return;
+    FG_FOR_AXIS(FG_CASE)
+#undef FG_CASE
+  }
+  throw std::invalid_argument("unsupported axis length");
+}
+
+template <typename R>
+void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const int* skip,
+                  hipStream_t s) {
+  const int B = column_tile(N0, M, (int)sizeof(cplx<R>));
+  const int T = line_threads(N0);
+  const size_t shm = (size_t)N0 * B * sizeof(cplx<R>);
+  dim3 grid((unsigned)(M / B), (unsigned)N1, 3);
+  dim3 gdc((unsigned)(N1 / 2 + 1), 3, 1);
+  switch (N0) {
+#define FG_CASE(L_)                                                                                    \
+  case L_:                                                                                             \
+    hipLaunchKernelGGL((k_fft_z_proj<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, skip); \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 0>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, skip); \
+    return;
+    FG_FOR_AXIS(FG_CASE)
+#undef FG_CASE
+  }
+  throw std::invalid_argument("unsupported N0");
+}
+
+template <typename R>
+void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0, double a1,
+                    const int* skip, hipStream_t s) {
+  const int B = column_tile(N0, M, (int)sizeof(cplx<R>));
+  const int T = line_threads(N0);
+  const size_t shm = (size_t)N0 * B * sizeof(cplx<R>);
+  dim3 grid((unsigned)(M / B), (unsigned)N1, 1);
+  dim3 gdc((unsigned)(N1 / 2 + 1), 1, 1);
+  switch (N0) {
+#define FG_CASE(L_)                                                                                   \
+  case L_:                                                                                            \
+    hipLaunchKernelGGL((k_fft_z_scalar<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, a0, \
+                       a1, skip);                                                                     \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 1>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, a0, a1, skip); \
+    return;
+    FG_FOR_AXIS(FG_CASE)
+#undef FG_CASE
+  }
+  throw std::invalid_argument("unsupported N0");
+}
+
+#define FG_INSTANTIATE_LAUNCHERS(R)                                                                     \
+  template void launch_r2c<R>(int, const R*, R*, long, const SpecTables<R>&, const int*, hipStream_t); \
+  template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t); \
+  template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const int*, \
+                               hipStream_t);                                                            \
+  template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const int*, hipStream_t);   \
+  template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const int*, \
+                                  hipStream_t);
+
+}  // namespace fg

@@ -1,0 +1,37 @@
+// Host-side launchers of the FFT passes (size dispatch).  Defined once per
+// working precision in fg_fft_f64.hip / fg_fft_f32.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fg_fft.hpp"
+
+namespace fg {
+
+bool fft_length_supported(int L);       // complex line lengths
+bool fft_axis_length_supported(int L);  // N0, N1
+
+// Largest power-of-two column tile dividing M with T * B <= 256 threads and
+// an exchange buffer of L * B complex values within 64 KiB.
+int column_tile(int L, int M, int elem_bytes);
+int line_threads(int L);
+
+template <typename R>
+void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const int* skip,
+                hipStream_t s);
+// returns the number of blocks (= partials written when epi.partials != nullptr)
+template <typename R>
+int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const C2REpi& epi,
+               hipStream_t s);
+template <typename R>
+void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
+                 const cplx<R>* tw, const int* skip, hipStream_t s);
+// N0 pass fused with the projection, for 9-component fields (3 rows).
+template <typename R>
+void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const int* skip,
+                  hipStream_t s);
+// N0 pass fused with a scalar symbol scale / (a0 + a1 lambda(q)), 1 component.
+template <typename R>
+void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0, double a1,
+                    const int* skip, hipStream_t s);
+
+}  // namespace fg

@@ -1,0 +1,285 @@
+// Pointwise and vector kernels of the mechanics path.
+//
+// Field layout: component-major, a 3x3 tensor field is 9 planes of N voxels,
+// plane 3i+j holds the ij component (row-major tensor index).
+#pragma once
+#include "fg_fft.hpp"
+
+namespace fg {
+
+// Device-side scalars of one Krylov solve (FP64, in the workspace).
+struct KrylovScalars {
+  double rr;     // current r.r
+  double rr0;    // b.b
+  double rz;     // r.z (preconditioned solves)
+  double pAp;
+  double alpha;
+  double beta;
+  double tol2;   // tol^2 (0: run to maxit)
+  int iter;
+  int maxit;
+  int done;      // 1 when converged, broken down or out of iterations
+  int flag;      // 0 running/converged, 1 breakdown, 2 max iterations
+};
+
+constexpr int FG_FLAG_DOMAIN = 1;  // det F <= 0 or 1 + Omega c <= 0
+
+// Constitutive update (Sec. 2, eqs. (1), (2), (9), (11), (27); compressible
+// Neo-Hookean energy, energy per reference volume):
+//   s^-2 = (1 + Omega c)^{-2/3}, ln J_e = ln det F - ln(1 + Omega c),
+//   P = g [ G s^-2 F + (lambda ln J_e - G) F^-T ],  g = (1 - d)^2,
+// and the 12-word tangent state {A = F^-T, alpha = g G s^-2, beta = g lambda,
+// gamma = g (G - lambda ln J_e)} with which
+//   K : X = alpha X + beta (A : X) A + gamma A X^T A.
+// F is either the field F (9 planes) or, when Fu != nullptr, the uniform
+// tensor Fu.  P (FP64) may be nullptr; state (type S) may be nullptr.
+// pnorm_partials (optional) receives per-block sums of P : P.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, const double* __restrict__ c,
+               const double* __restrict__ d, const double* __restrict__ E, const double* __restrict__ nu,
+               const double* __restrict__ Om, double* __restrict__ P, S* __restrict__ state,
+               double* __restrict__ pnorm_partials, int* __restrict__ flags, long N) {
+  __shared__ double red[16];
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double pp = 0.0;
+  if (i < N) {
+    double f[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f[k] = Fu ? Fu[k] : F[k * N + i];
+    // cofactor matrix: F^-T = cof(F) / det F
+    double cof[9];
+    cof[0] = f[4] * f[8] - f[5] * f[7];
+    cof[1] = f[5] * f[6] - f[3] * f[8];
+    cof[2] = f[3] * f[7] - f[4] * f[6];
+    cof[3] = f[2] * f[7] - f[1] * f[8];
+    cof[4] = f[0] * f[8] - f[2] * f[6];
+    cof[5] = f[1] * f[6] - f[0] * f[7];
+    cof[6] = f[1] * f[5] - f[2] * f[4];
+    cof[7] = f[2] * f[3] - f[0] * f[5];
+    cof[8] = f[0] * f[4] - f[1] * f[3];
+    double J = f[0] * cof[0] + f[1] * cof[1] + f[2] * cof[2];
+    const double cc = c[i], dd = d[i], EE = E[i], nn = nu[i], oo = Om[i];
+    const double a = 1.0 + oo * cc;
+    if (!(J > 0.0) || !(a > 0.0)) {
+      flags[0] = FG_FLAG_DOMAIN;
+      J = 1.0;
+    }
+    const double G = EE / (2.0 * (1.0 + nn));
+    const double lam = EE * nn / ((1.0 + nn) * (1.0 - 2.0 * nn));
+    const double g = (1.0 - dd) * (1.0 - dd);
+    const double la = log(a > 0.0 ? a : 1.0);
+    const double s2inv = exp(-2.0 / 3.0 * la);
+    const double lnJe = log(J) - la;
+    const double iJ = 1.0 / J;
+    double A[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A[k] = cof[k] * iJ;
+    const double c1 = g * G * s2inv;
+    const double c2 = g * (lam * lnJe - G);
+    if (P) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const double pk = c1 * f[k] + c2 * A[k];
+        P[k * N + i] = pk;
+        pp += pk * pk;
+      }
+    }
+    if (state) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) state[k * N + i] = (S)A[k];
+      state[9 * N + i] = (S)c1;
+      state[10 * N + i] = (S)(g * lam);
+      state[11 * N + i] = (S)(g * (G - lam * lnJe));
+    }
+  }
+  if (pnorm_partials) {
+    const double s = block_sum(pp, red);
+    if (threadIdx.x == 0) pnorm_partials[blockIdx.x] = s;
+  }
+}
+
+// K : X from the tangent state (in registers).
+template <typename T>
+__device__ __forceinline__ void tangent_apply(const T (&A)[9], T al, T be, T ga, const T (&X)[9], T (&Y)[9]) {
+  T tr = T(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) tr += A[k] * X[k];
+  // W = A X^T : W_ik = sum_l A_il X_kl
+  T W[9];
+#pragma unroll
+  for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+      W[3 * ii + kk] = A[3 * ii] * X[3 * kk] + A[3 * ii + 1] * X[3 * kk + 1] + A[3 * ii + 2] * X[3 * kk + 2];
+#pragma unroll
+  for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      const T awa = W[3 * ii] * A[jj] + W[3 * ii + 1] * A[3 + jj] + W[3 * ii + 2] * A[6 + jj];
+      Y[3 * ii + jj] = al * X[3 * ii + jj] + be * tr * A[3 * ii + jj] + ga * awa;
+    }
+}
+
+// CG direction update fused with the tangent contraction:
+//   p <- r (first iteration) or r + beta p;  Y = K : p.
+// With update == false: Y = K : p for the given p (no CG state).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_contract(T* __restrict__ Y, T* __restrict__ p, const T* __restrict__ r, const T* __restrict__ st,
+           const KrylovScalars* __restrict__ ks, long N, int update) {
+  if (ks && ks->done) return;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  T X[9];
+  if (update) {
+    const bool first = ks->iter == 0;
+    const T beta = (T)ks->beta;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const T rk = r[k * N + i];
+      const T pk = first ? rk : rk + beta * p[k * N + i];
+      p[k * N + i] = pk;
+      X[k] = pk;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) X[k] = p[k * N + i];
+  }
+  T A[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) A[k] = st[k * N + i];
+  T Yv[9];
+  tangent_apply<T>(A, st[9 * N + i], st[10 * N + i], st[11 * N + i], X, Yv);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Y[k * N + i] = Yv[k];
+}
+
+// x += alpha p, r -= alpha q, per-block partial sums of r.r.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+            const KrylovScalars* __restrict__ ks, double* __restrict__ partials, long n) {
+  __shared__ double red[16];
+  if (ks->done) return;
+  const T alpha = (T)ks->alpha;
+  double acc = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const T xi = x[i] + alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    x[i] = xi;
+    r[i] = ri;
+    acc += (double)ri * (double)ri;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Sum of nparts partials in a fixed order by one block (deterministic).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partials, int nparts, double* red) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += blockDim.x) acc += partials[k];
+  return block_sum(acc, red);
+}
+
+// mode 0: alpha = rz / pAp (rz = rr for plain CG), breakdown check.
+// mode 1: plain CG: rr_new, iteration count, convergence, beta.
+// mode 2: store the sum into out[0] (norms).
+// mode 3: PCG: r.r (convergence) -- z not yet formed.
+// mode 4: PCG: r.z -> beta = rz_new / rz.
+// mode 5: initialise a Krylov solve from rr0 = sum (b.b): rr = rr0, iter = 0.
+__global__ void __launch_bounds__(256)
+k_finalize(const double* __restrict__ partials, int nparts, KrylovScalars* ks, double* out, int mode, int pcg) {
+  __shared__ double red[16];
+  if (ks && ks->done && mode != 5 && mode != 2) return;
+  const double s = sum_partials(partials, nparts, red);
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    ks->pAp = s;
+    if (!(s > 0.0)) {
+      ks->done = 1;
+      ks->flag = 1;
+    } else {
+      ks->alpha = (pcg ? ks->rz : ks->rr) / s;
+    }
+  } else if (mode == 1) {
+    const double rr = s;
+    ks->iter += 1;
+    if (ks->tol2 > 0.0 && rr <= ks->tol2 * ks->rr0) {
+      ks->done = 1;
+    } else if (ks->iter >= ks->maxit) {
+      ks->done = 1;
+      ks->flag = (ks->tol2 > 0.0) ? 2 : 0;
+    } else {
+      ks->beta = rr / ks->rr;
+    }
+    ks->rr = rr;
+  } else if (mode == 2) {
+    out[0] = s;
+  } else if (mode == 3) {
+    ks->iter += 1;
+    ks->rr = s;
+    if (ks->tol2 > 0.0 && s <= ks->tol2 * ks->rr0) {
+      ks->done = 1;
+    } else if (ks->iter >= ks->maxit) {
+      ks->done = 1;
+      ks->flag = (ks->tol2 > 0.0) ? 2 : 0;
+    }
+  } else if (mode == 4) {
+    if (ks->iter == 0) {
+      ks->beta = 0.0;
+    } else {
+      ks->beta = s / ks->rz;
+    }
+    ks->rz = s;
+  } else if (mode == 5) {
+    ks->rr0 = s;
+    ks->rr = s;
+    ks->iter = 0;
+    ks->flag = 0;
+    ks->beta = 0.0;
+    ks->done = (s == 0.0) ? 1 : 0;
+  }
+}
+
+// F += x (F FP64, x in the CG precision), n = 9N.
+template <typename T>
+__global__ void __launch_bounds__(256) k_axpy_into_f64(double* __restrict__ F, const T* __restrict__ x, long n) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) F[i] += (double)x[i];
+}
+
+// F_k += dF_k for a uniform 3x3 increment.
+__global__ void __launch_bounds__(256) k_add_uniform9(double* __restrict__ F, const double* __restrict__ dF, long N) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) F[k * N + i] += dF[k];
+}
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(256) k_convert(B* __restrict__ dst, const A* __restrict__ src, long n) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (B)src[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill(T* __restrict__ dst, T v, long n) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = v;
+}
+
+// Per-block partial sums of the 9 components of a tensor field (for <P>).
+__global__ void __launch_bounds__(256) k_mean9_partials(const double* __restrict__ P, double* __restrict__ partials,
+                                                        long N) {
+  __shared__ double red[16];
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = 0; k < 9; ++k) {
+    const double v = (i < N) ? P[k * N + i] : 0.0;
+    const double s = block_sum(v, red);
+    if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+}  // namespace fg

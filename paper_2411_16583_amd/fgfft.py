@@ -1,0 +1,252 @@
+"""ctypes binding of libfgfft.so (include/fgfft.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides device memory (the workspace and the fields are CUDA/HIP
+tensors owned by the caller) and the stream.  The library is loaded from the
+package directory; importing this module on a machine where it is missing
+raises immediately (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfgfft.so")
+
+FG_OK, FG_E_ARG, FG_E_SIZE, FG_E_HIP, FG_E_NOCONV, FG_E_BREAKDOWN, FG_E_DOMAIN, FG_E_STATE = range(8)
+FG_FP64, FG_MIXED = 0, 1
+PRECISIONS = {"fp64": FG_FP64, "mixed": FG_MIXED}
+
+# Every function declared in include/fgfft.h.
+EXPORTED = [
+    "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
+    "fg_set_state", "fg_newton_solve", "fg_residual", "fg_homogenized_stress", "fg_stress",
+    "fg_apply_operator", "fg_project", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
+    "fg_status_string", "fg_last_error", "fg_plan_destroy",
+]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [
+        ("tol_newton", ctypes.c_double),
+        ("tol_lin", ctypes.c_double),
+        ("max_newton", ctypes.c_int),
+        ("max_lin", ctypes.c_int),
+        ("fixed_lin", ctypes.c_int),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("newton_iters", ctypes.c_int),
+        ("lin_iters_total", ctypes.c_int),
+        ("lin_iters_last", ctypes.c_int),
+        ("n_history", ctypes.c_int),
+        ("err_res", ctypes.c_double),
+        ("lin_relres", ctypes.c_double),
+        ("err_history", ctypes.c_double * 64),
+        ("lin_history", ctypes.c_int * 64),
+    ]
+
+    def to_dict(self):
+        n = min(self.n_history, 64)
+        return dict(
+            newton_iters=self.newton_iters,
+            lin_iters_total=self.lin_iters_total,
+            lin_iters_last=self.lin_iters_last,
+            err_res=self.err_res,
+            lin_relres=self.lin_relres,
+            err_history=list(self.err_history[:n]),
+            lin_history=list(self.lin_history[: min(self.newton_iters, 64)]) if self.newton_iters else
+            list(self.lin_history[:n]),
+        )
+
+
+class FgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libfgfft.so and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2411_16583_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, c_int, c_double, c_size = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    dptr = ctypes.c_void_p
+    sig = {
+        "fg_plan_create": ([ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_int, vp, ctypes.POINTER(vp)], c_int),
+        "fg_plan_workspace_bytes": ([vp], c_size),
+        "fg_plan_set_workspace": ([vp, vp, c_size], c_int),
+        "fg_set_material": ([vp, dptr, dptr, dptr, dptr, dptr, c_double, c_double, c_double, c_double], c_int),
+        "fg_set_state": ([vp, dptr, dptr, dptr, dptr], c_int),
+        "fg_newton_solve": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
+        "fg_residual": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
+        "fg_homogenized_stress": ([vp, ctypes.POINTER(c_double)], c_int),
+        "fg_stress": ([vp, dptr], c_int),
+        "fg_apply_operator": ([vp, dptr, dptr], c_int),
+        "fg_project": ([vp, dptr, dptr], c_int),
+        "fg_fft_r2c": ([vp, dptr, c_int], c_int),
+        "fg_fft_c2r": ([vp, dptr, c_int], c_int),
+        "pff_solve": ([vp, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
+        "fick_step": ([vp, c_double, dptr, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
+        "fg_status_string": ([c_int], ctypes.c_char_p),
+        "fg_last_error": ([vp], ctypes.c_char_p),
+        "fg_plan_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64 CUDA tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+
+    if not t.is_cuda:
+        raise ValueError("fields must be device tensors")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("fields must be contiguous float64 tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _mat9(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(9))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_opts(tol_newton=1e-8, tol_lin=1e-10, max_newton=50, max_lin=20000, fixed_lin=0):
+    return SolverOpts(tol_newton, tol_lin, max_newton, max_lin, fixed_lin)
+
+
+class Plan:
+    """One grid / precision / stream.  Holds references to every tensor it
+    was given so that their memory outlives the plan's use of it."""
+
+    def __init__(self, grid, spacing, precision="fp64", stream=None, device="cuda"):
+        import torch
+
+        self.lib = load_library()
+        self.grid = tuple(int(n) for n in grid)
+        self.spacing = tuple(float(h) for h in spacing)
+        self.N = int(np.prod(self.grid))
+        self.precision = precision
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        g = (ctypes.c_int * 3)(*self.grid)
+        h = (ctypes.c_double * 3)(*self.spacing)
+        out = ctypes.c_void_p()
+        st = self.lib.fg_plan_create(g, h, PRECISIONS[precision], ctypes.c_void_p(stream.cuda_stream),
+                                     ctypes.byref(out))
+        if st != FG_OK:
+            raise FgError(st, f"fg_plan_create{self.grid}: {self.lib.fg_status_string(st).decode()}")
+        self.handle = out
+        nbytes = int(self.lib.fg_plan_workspace_bytes(self.handle))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._check(self.lib.fg_plan_set_workspace(self.handle, ctypes.c_void_p(self.workspace.data_ptr()),
+                                                    nbytes), "fg_plan_set_workspace")
+        self._keep = {}
+
+    def _check(self, st, what):
+        if st != FG_OK:
+            msg = self.lib.fg_last_error(self.handle).decode() if self.handle else ""
+            raise FgError(st, f"{what}: {self.lib.fg_status_string(st).decode()}: {msg}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_material(self, E, nu, Omega, D=None, sigma_max=None, gc=1.0, lc=1.0, RT=2478.957, c_max=3.0e4):
+        self._keep.update(E=E, nu=nu, Omega=Omega, D=D, sigma_max=sigma_max)
+        self._check(self.lib.fg_set_material(self.handle, _ptr(E), _ptr(nu), _ptr(Omega), _ptr(D), _ptr(sigma_max),
+                                             gc, lc, RT, c_max), "fg_set_material")
+
+    def set_state(self, F, c=None, d=None, H=None):
+        self._keep.update(F=F, c=c, d=d, H=H)
+        self._check(self.lib.fg_set_state(self.handle, _ptr(F), _ptr(c), _ptr(d), _ptr(H)), "fg_set_state")
+
+    def newton_solve(self, F_macro, opts=None, raise_on_error=True):
+        opts = opts or make_opts()
+        a, p = _mat9(F_macro)
+        stats = Stats()
+        st = self.lib.fg_newton_solve(self.handle, p, ctypes.byref(opts), ctypes.byref(stats))
+        if raise_on_error:
+            self._check(st, "fg_newton_solve")
+        d = stats.to_dict()
+        d["status"] = st
+        return d
+
+    def residual(self, F_macro):
+        a, p = _mat9(F_macro)
+        out = ctypes.c_double()
+        self._check(self.lib.fg_residual(self.handle, p, ctypes.byref(out)), "fg_residual")
+        return out.value
+
+    def homogenized_stress(self):
+        out = (ctypes.c_double * 9)()
+        self._check(self.lib.fg_homogenized_stress(self.handle, out), "fg_homogenized_stress")
+        return np.array(out[:]).reshape(3, 3)
+
+    def stress(self, out):
+        self._check(self.lib.fg_stress(self.handle, _ptr(out)), "fg_stress")
+        return out
+
+    def apply_operator(self, x, y):
+        self._check(self.lib.fg_apply_operator(self.handle, _ptr(x), _ptr(y)), "fg_apply_operator")
+        return y
+
+    def project(self, x, y):
+        self._check(self.lib.fg_project(self.handle, _ptr(x), _ptr(y)), "fg_project")
+        return y
+
+    def fft_r2c(self, data, ncomp):
+        self._check(self.lib.fg_fft_r2c(self.handle, _ptr(data), int(ncomp)), "fg_fft_r2c")
+        return data
+
+    def fft_c2r(self, data, ncomp):
+        self._check(self.lib.fg_fft_c2r(self.handle, _ptr(data), int(ncomp)), "fg_fft_c2r")
+        return data
+
+    def pff_solve(self, opts=None, raise_on_error=True):
+        opts = opts or make_opts()
+        stats = Stats()
+        st = self.lib.pff_solve(self.handle, ctypes.byref(opts), ctypes.byref(stats))
+        if raise_on_error:
+            self._check(st, "pff_solve")
+        d = stats.to_dict()
+        d["status"] = st
+        return d
+
+    def fick_step(self, dt, cdot_B=None, opts=None, raise_on_error=True):
+        opts = opts or make_opts()
+        stats = Stats()
+        self._keep["cdot_B"] = cdot_B
+        st = self.lib.fick_step(self.handle, float(dt), _ptr(cdot_B), ctypes.byref(opts), ctypes.byref(stats))
+        if raise_on_error:
+            self._check(st, "fick_step")
+        d = stats.to_dict()
+        d["status"] = st
+        return d

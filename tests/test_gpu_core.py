@@ -1,0 +1,158 @@
+"""GPU parity of the transform, the projection, the operator of eq. (30)
+and the Newton-CG equilibrium solve (Alg. 1) against the CPU oracle.
+
+Tolerances: FP64 transforms and the projection ~1e-15 * log2(N) relative
+(1e-13 used); one operator application 1e-13; converged Newton states
+1e-10 relative to the fluctuation (the FP64 target); mixed form 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import constitutive as cm
+from oracle import mechanics, spectral
+from tests.gpu_util import DEV, dt, host, plan_for, rel
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [(4, 4, 4), (8, 8, 8), (16, 16, 16), (12, 24, 48), (6, 8, 12), (32, 48, 64), (96, 16, 24),
+         (64, 64, 128), (256, 4, 8), (4, 256, 16), (8, 4, 512)]
+
+
+def unpack_packed(Z, shape):
+    """Packed half spectrum -> (A, B, interior) to compare with rfftn."""
+    return Z[..., 0], Z[..., 1:]
+
+
+@pytest.mark.parametrize("shape", GRIDS)
+def test_fft_r2c_matches_numpy_and_roundtrips(shape):
+    print(f"fft shape={shape}", flush=True)
+    rng = np.random.default_rng(100)
+    ncomp = 2
+    x = rng.standard_normal((ncomp,) + shape)
+    work = synth.homogeneous_workload(shape, 1.0)
+    plan = plan_for(work)
+    buf = dt(x)
+    plan.fft_r2c(buf, ncomp)
+    torch.cuda.synchronize()
+    M = shape[2] // 2
+    Z = host(buf).view(np.complex128).reshape((ncomp,) + shape[:2] + (M,))
+    X = np.fft.rfftn(x, axes=(1, 2, 3))
+    scale = np.abs(X).max()
+    assert np.max(np.abs(Z[..., 1:] - X[..., 1:M])) <= 1e-13 * scale
+    packed0 = X[..., 0] + 1j * X[..., M]
+    assert np.max(np.abs(Z[..., 0] - packed0)) <= 1e-13 * scale
+    plan.fft_c2r(buf, ncomp)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(host(buf).reshape(x.shape) - x)) <= 1e-13 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("shape", GRIDS)
+def test_projection_matches_oracle(shape):
+    print(f"project shape={shape}", flush=True)
+    rng = np.random.default_rng(101)
+    sp = (0.7, 1.1, 0.9)
+    work = synth.homogeneous_workload(shape, tuple(s * n for s, n in zip(sp, shape)))
+    plan = plan_for(work)
+    A = rng.standard_normal((3, 3) + shape)
+    y = torch.empty(9 * int(np.prod(shape)), dtype=torch.float64, device=DEV)
+    plan.project(dt(A), y)
+    torch.cuda.synchronize()
+    ref = spectral.project(A, work["spacing"])
+    assert rel(host(y), ref) <= 1e-13
+
+
+def _random_state(work, rng, amp=0.05):
+    shape = work["shape"]
+    F = mechanics.uniform_field(np.eye(3), shape) + amp * rng.standard_normal((3, 3) + shape)
+    return F
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 16, 24), (32, 32, 32)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
+def test_operator_matches_oracle(shape, precision, tol):
+    print(f"operator shape={shape} {precision}", flush=True)
+    rng = np.random.default_rng(102)
+    work = synth.homogeneous_workload(shape, 1.0)
+    work["E"] = np.where(rng.random(shape) < 0.3, 100e9, 10e9)
+    work["nu"] = np.where(rng.random(shape) < 0.5, 0.25, 0.3)
+    work["Omega"] = 0.05 * rng.random(shape)
+    c = 0.4 * rng.random(shape)
+    d = 0.3 * rng.random(shape)
+    F = _random_state(work, rng)
+    plan = plan_for(work, precision)
+    Ft, ct, dtt = dt(F), dt(c), dt(d)
+    plan.set_state(Ft, ct, dtt, dt(np.zeros(shape)))
+    X = rng.standard_normal((3, 3) + shape)
+    y = torch.empty(9 * int(np.prod(shape)), dtype=torch.float64, device=DEV)
+    plan.apply_operator(dt(X), y)
+    torch.cuda.synchronize()
+    K = cm.tangent(F, c, d, work["E"], work["nu"], work["Omega"])
+    ref = mechanics.operator(K, X, work["spacing"])
+    assert rel(host(y), ref) <= tol
+
+
+def test_stress_and_mean_match_oracle():
+    rng = np.random.default_rng(103)
+    shape = (8, 12, 16)
+    work = synth.homogeneous_workload(shape, 1.0)
+    work["Omega"] = 0.05 * rng.random(shape)
+    c, d = 0.4 * rng.random(shape), 0.3 * rng.random(shape)
+    F = _random_state(work, rng)
+    plan = plan_for(work)
+    plan.set_state(dt(F), dt(c), dt(d), dt(np.zeros(shape)))
+    P = torch.empty(9 * int(np.prod(shape)), dtype=torch.float64, device=DEV)
+    plan.stress(P)
+    ref = cm.stress(F, c, d, work["E"], work["nu"], work["Omega"])
+    assert rel(host(P), ref) <= 1e-14
+    Pm = plan.homogenized_stress()
+    assert np.max(np.abs(Pm - ref.reshape(3, 3, -1).mean(-1))) <= 1e-13 * np.abs(ref).max()
+
+
+def run_increments_gpu(work, precision="fp64", tol_newton=1e-8, tol_lin=1e-10):
+    from paper_2411_16583_amd import make_opts
+
+    shape = work["shape"]
+    plan = plan_for(work, precision)
+    F = dt(mechanics.uniform_field(np.eye(3), shape))
+    plan.set_state(F, dt(work["c0"]), dt(work["d0"]), dt(np.zeros(shape)))
+    out = []
+    for Fbar in work["loads"]:
+        st = plan.newton_solve(Fbar, make_opts(tol_newton, tol_lin))
+        out.append((host(F, (3, 3) + shape).copy(), st))
+    return out
+
+
+def test_inclusion_newton_fp64_matches_oracle():
+    """The 16^3 inclusion workload, 5 increments, Newton 1e-8 / CG 1e-10."""
+    work = synth.inclusion_workload()
+    gpu = run_increments_gpu(work)
+    shape = work["shape"]
+    Fo = mechanics.uniform_field(np.eye(3), shape)
+    Fprev = np.eye(3)
+    for k, Fbar in enumerate(work["loads"]):
+        Fo = Fo + mechanics.uniform_field(Fbar - Fprev, shape)
+        Fo, so = mechanics.newton_solve(Fo, Fbar, work["c0"], work["d0"], work, work["spacing"],
+                                        tol_newton=1e-8, tol_lin=1e-10)
+        Fprev = Fbar
+        Fg, sg = gpu[k]
+        fl = Fo - mechanics.uniform_field(Fbar, shape)
+        e = rel(Fg, Fo, fl)
+        print(f"increment {k}: newton gpu {sg['newton_iters']} oracle {so['newton_iters']}, "
+              f"cg gpu {sg['lin_history']} oracle {so['lin_iters']}, rel {e:.2e}", flush=True)
+        assert sg["newton_iters"] == so["newton_iters"]
+        assert e <= 1e-10
+
+
+def test_inclusion_newton_mixed_matches_oracle():
+    work = synth.inclusion_workload()
+    gpu = run_increments_gpu(work, "mixed")
+    shape = work["shape"]
+    F, _ = mechanics.solve_increments(work, tol_newton=1e-8, tol_lin=1e-10)
+    Fg, sg = gpu[-1]
+    fl = F - mechanics.uniform_field(work["loads"][-1], shape)
+    e = rel(Fg, F, fl)
+    print(f"mixed: newton {sg['newton_iters']} cg {sg['lin_history']} rel {e:.2e}", flush=True)
+    assert e <= 1e-6
+    assert sg["err_res"] <= 1e-8

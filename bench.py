@@ -1,0 +1,214 @@
+"""Benchmark: voxel CG-iterations per second of the Fourier-Galerkin hot path
+at 256^3 (double precision and the mixed form) and the HBM-roofline fraction
+of the dominant kernel, on one MI355X.
+
+Workload: the polydisperse microstructure (256^3 unit cell, 60 seeded RSA
+spheres with radii U(10, 24) voxels, stiffness contrast 20), macroscopic
+stretch ramped by 0.0025 per load increment, damage on, chemistry off.  One
+"step" is one load increment of the staggered scheme: Newton-CG equilibrium
+(constitutive update, FP64 residual, CG on the operator of eq. (30)), the
+history / driving-force update, the phase-field PCG and the residual check.
+Warmup increments come first; the timed increments follow them.
+
+value = voxels x CG iterations / wall time of the timed increments (FP64).
+The mixed form's figures are reported alongside.  The roofline object
+refers to the kernel class with the largest time in the FP64 timed region;
+its average launch duration comes from HIP events on the plan stream.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--n 256] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+# Algorithmic bytes per voxel and launch for each kernel class of the
+# mechanics CG iteration, in words of the working precision (9-component
+# fields; the spectrum occupies the same bytes as the real field).
+WORDS_PER_VOXEL = {
+    "contract": 48,   # read r, p (18) + state (12); write p, K:p (18)
+    "r2c": 18,        # read 9, write 9
+    "axis": 18,       # read 9, write 9 (per launch; 2 launches / iteration)
+    "zproj": 18,      # read 9, write 9
+    "c2r": 27,        # read 9 + p 9, write 9
+    "cg_update": 54,  # read x, r, p, Ap (36), write x, r (18)
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    return ap.parse_args()
+
+
+def run_form(work, form, steps, warmup):
+    import torch
+
+    from paper_2411_16583_amd import Plan
+    from paper_2411_16583_amd.driver import staggered_step
+
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    shape = work["shape"]
+    plan = Plan(shape, work["spacing"], form)
+    mats = [t(work[k]) for k in ("E", "nu", "Omega", "D", "sigma_max")]
+    plan.set_material(*mats, gc=work["gc"], lc=work["lc"], RT=work["RT"], c_max=work["c_max"])
+    F = torch.zeros((9,) + shape, dtype=torch.float64, device=dev)
+    F[0] = 1.0
+    F[4] = 1.0
+    F[8] = 1.0
+    c = torch.zeros(shape, dtype=torch.float64, device=dev)
+    d = torch.zeros(shape, dtype=torch.float64, device=dev)
+    H = torch.zeros(shape, dtype=torch.float64, device=dev)
+    plan.set_state(F, c, d, H)
+    loads = work["loads"]
+    for k in range(warmup):
+        st = staggered_step(plan, loads[k], chemistry=False)
+        print(f"[{form}] warmup increment {k + 1}: newton {[s['newton_iters'] for s in st['newton']]} "
+              f"cg {[s['lin_history'] for s in st['newton']]}", flush=True)
+    torch.cuda.synchronize()
+    plan.profile_begin()
+    cg_iters = 0
+    newton_iters = 0
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        st = staggered_step(plan, loads[k], chemistry=False)
+        its = sum(s["lin_iters_total"] for s in st["newton"])
+        cg_iters += its
+        newton_iters += sum(s["newton_iters"] for s in st["newton"])
+        print(f"[{form}] increment {k + 1}: newton {[s['newton_iters'] for s in st['newton']]} "
+              f"cg {[s['lin_history'] for s in st['newton']]} err {st['err_res']:.2e}", flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = plan.profile_end()
+    Pm = plan.homogenized_stress()
+    plan.close()
+    return dict(elapsed=elapsed, cg_iters=cg_iters, newton_iters=newton_iters, prof=prof, P11=float(Pm[0, 0]))
+
+
+def roofline(res, N, word_bytes):
+    prof = res["prof"]
+    cands = {k: prof[k] for k in WORDS_PER_VOXEL if prof[k][1] > 0}
+    name = max(cands, key=lambda k: cands[k][0])
+    ms, launches = cands[name]
+    avg_s = ms / 1e3 / launches
+    bytes_per_launch = WORDS_PER_VOXEL[name] * word_bytes * N
+    achieved = bytes_per_launch / avg_s / 1e9
+    return dict(kernel=name, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                avg_launch_us=round(avg_s * 1e6, 2), launches=launches,
+                bytes_per_launch=bytes_per_launch,
+                breakdown_ms={k: round(v[0], 2) for k, v in prof.items()})
+
+
+def cpu_baseline(work, iters):
+    """The oracle's CG iterations on the same 256^3 increment-1 state
+    (timed: the iterations only; K is built first, untimed)."""
+    import oracle.spectral as osp
+    from oracle import constitutive as cm
+    from oracle import mechanics
+    from oracle.krylov import dot
+
+    threads = min(16, os.cpu_count() or 1)
+    osp.WORKERS = threads
+    shape = work["shape"]
+    Fbar = work["loads"][0]
+    F = mechanics.uniform_field(Fbar, shape)
+    c, d = work["c0"], work["d0"]
+    GP, _ = mechanics.residual_rhs(F, c, d, work, work["spacing"])
+    b = -osp.project(GP, work["spacing"])
+    K = cm.tangent(F, c, d, work["E"], work["nu"], work["Omega"])
+    print("cpu baseline: oracle tangent and right-hand side built", flush=True)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = dot(r, r)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        Ap = mechanics.operator(K, p, work["spacing"])
+        alpha = rr / dot(p, Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        rr_new = dot(r, r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        print(f"cpu baseline: iteration done at {time.perf_counter() - t0:.1f} s", flush=True)
+    el = time.perf_counter() - t0
+    N = int(np.prod(shape))
+    return dict(value=N * iters / el, unit="voxel*CG-iter/s", cores=threads, kind="oracle",
+                sample=f"{iters} CG iterations of the oracle's Newton-CG at {shape[0]}^3, increment-1 state "
+                       f"(numpy/scipy float64, scipy.fft workers={threads}, einsum single-threaded), "
+                       f"{el:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the hot path here is single-GPU "
+              "(sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+    import synth
+
+    t0 = time.perf_counter()
+    work = synth.polydisperse_workload(n=args.n)
+    N = int(np.prod(work["shape"]))
+    print(f"workload polydisperse {work['shape']} built in {time.perf_counter() - t0:.1f} s, "
+          f"inclusion fraction {work['phase'].mean():.3f}", flush=True)
+    forms = args.forms.split(",")
+    res = {}
+    for form in forms:
+        res[form] = run_form(work, form, args.steps, args.warmup)
+    main_form = "fp64" if "fp64" in res else forms[0]
+    r0 = res[main_form]
+    value = N * r0["cg_iters"] / r0["elapsed"]
+    line = {
+        "metric": "voxel*CG-iters/s at 256^3 (FP64 vs mixed) + % of HBM roofline",
+        "value": value,
+        "unit": "voxel*CG-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r0["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_form == "fp64" else "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"polydisperse RVE {args.n}^3, 60 RSA spheres r~U(10,24) vox, contrast 20, "
+                               f"macro stretch +0.0025 per increment, damage on, chemistry off",
+                   "voxels": N, "cg_iters": r0["cg_iters"], "newton_iters": r0["newton_iters"]},
+        "roofline": roofline(r0, N, 8 if main_form == "fp64" else 4),
+    }
+    for form in forms:
+        if form == main_form:
+            continue
+        r = res[form]
+        v = N * r["cg_iters"] / r["elapsed"]
+        line[form] = dict(value=v, ms_per_step=1e3 * r["elapsed"] / args.steps, cg_iters=r["cg_iters"],
+                          newton_iters=r["newton_iters"], speedup_per_cg_iter=v / value,
+                          speedup_per_step=r0["elapsed"] / r["elapsed"],
+                          rel_diff_P11_vs_fp64=abs(r["P11"] - r0["P11"]) / abs(r0["P11"]),
+                          roofline=roofline(r, N, 4))
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(work, args.cpu_iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -124,6 +124,12 @@ fg_status fg_set_state(fg_plan* plan, double* F, double* c, double* d, double* H
 fg_status fg_newton_solve(fg_plan* plan, const double F_macro[9], const fg_solver_opts* opts,
                           fg_stats* stats);
 
+/* Add the macroscopic increment F_macro - <F> to F (the first line of
+ * Alg. 1, F^0 = F_t + dFbar; Sec. 3.2 Global problem: the chemistry of a step
+ * sees the new macroscopic F).  F_macro: host, 9 doubles.  Synchronises.
+ * fg_newton_solve performs the same update itself. */
+fg_status fg_apply_macro(fg_plan* plan, const double F_macro[9]);
+
 /* Equilibrium residual of the current state (eq. (31)) with respect to the
  * macroscopic F_macro (host, 9 doubles): *err_res (host).  Synchronises. */
 fg_status fg_residual(fg_plan* plan, const double F_macro[9], double* err_res);
@@ -174,6 +180,28 @@ fg_status pff_solve(fg_plan* plan, const fg_solver_opts* opts, fg_stats* stats);
  * FG_E_BREAKDOWN, FG_E_HIP. */
 fg_status fick_step(fg_plan* plan, double dt, const double* cdot_B, const fg_solver_opts* opts,
                     fg_stats* stats);
+
+/* Kernel classes timed by fg_profile_*: */
+enum {
+  FG_PASS_CONTRACT = 0,     /* CG direction update + tangent contraction   */
+  FG_PASS_R2C = 1,          /* real-to-complex pass along N2               */
+  FG_PASS_AXIS = 2,         /* complex pass along N1 (forward and inverse) */
+  FG_PASS_ZPROJ = 3,        /* N0 pass fused with the projection (main)    */
+  FG_PASS_C2R = 4,          /* complex-to-real pass along N2 + reduction   */
+  FG_PASS_CG_UPDATE = 5,    /* x += alpha p, r -= alpha Ap, r.r            */
+  FG_PASS_FINALIZE = 6,     /* one-block reductions of the Krylov scalars  */
+  FG_PASS_CONSTITUTIVE = 7, /* stress and tangent state                    */
+  FG_PASS_ZSCALAR = 8,      /* N0 pass fused with a scalar symbol          */
+  FG_NPASS = 9
+};
+
+/* Time every launch of each kernel class with a HIP event pair on the plan
+ * stream, from fg_profile_begin until fg_profile_end, which synchronises and
+ * returns the summed milliseconds ms[FG_NPASS] and the number of launches
+ * launches[FG_NPASS] per class (host arrays).  Measurement support for the
+ * benchmark; adds two event records per launch while enabled. */
+fg_status fg_profile_begin(fg_plan* plan);
+fg_status fg_profile_end(fg_plan* plan, double ms[], long launches[]);
 
 const char* fg_status_string(fg_status s);
 const char* fg_last_error(const fg_plan* plan);

@@ -123,6 +123,11 @@ struct fg_plan {
   double *F = nullptr, *c = nullptr, *d = nullptr, *H = nullptr;
   double* zeroN = nullptr;  // N zeros (c, d when not given) inside the scalar area
 
+  // optional per-kernel-class timing with HIP events (fg_profile_*)
+  bool prof_on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[FG_NPASS];
+  size_t prof_used[FG_NPASS] = {};
+
   // pinned host scalars
   KrylovScalars* hks = nullptr;
   double* hd = nullptr;
@@ -231,6 +236,30 @@ template <typename R> void host_tables(const fg_plan* P, std::vector<char>& blob
   half(P->n2, P->M + 1, P->h[2], dev.cx, dev.sx);
 }
 
+// Event pair around one launch of kernel class `pass` (no-op unless on).
+struct ProfScope {
+  fg_plan* P;
+  int pass;
+  hipEvent_t stop = nullptr;
+  ProfScope(fg_plan* P_, int pass_) : P(P_), pass(pass_) {
+    if (!P->prof_on) return;
+    auto& v = P->prof_ev[pass];
+    size_t& u = P->prof_used[pass];
+    if (u == v.size()) {
+      hipEvent_t a, b;
+      FG_HIP(hipEventCreate(&a));
+      FG_HIP(hipEventCreate(&b));
+      v.emplace_back(a, b);
+    }
+    FG_HIP(hipEventRecord(v[u].first, P->stream));
+    stop = v[u].second;
+    ++u;
+  }
+  ~ProfScope() {
+    if (stop) (void)hipEventRecord(stop, P->stream);
+  }
+};
+
 inline unsigned blocks_for(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 inline unsigned grid_stride_blocks(long n) { return (unsigned)std::min<long>(2048, (n + 255) / 256); }
 
@@ -268,7 +297,11 @@ template <> const TablesDev<float>& tabs<float>(const fg_plan* P) { return P->t3
 template <typename R>
 void fwd_xy(fg_plan* P, const R* in, R* data, int ncomp, const int* skip) {
   const SpecTables<R> tb = tabs<R>(P).spec();
-  launch_r2c<R>(P->M, in, data, (long)ncomp * P->n0 * P->n1, tb, skip, P->stream);
+  {
+    ProfScope ps(P, FG_PASS_R2C);
+    launch_r2c<R>(P->M, in, data, (long)ncomp * P->n0 * P->n1, tb, skip, P->stream);
+  }
+  ProfScope ps(P, FG_PASS_AXIS);
   launch_axis<R>(P->n1, false, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1, skip,
                  P->stream);
 }
@@ -277,8 +310,12 @@ void fwd_xy(fg_plan* P, const R* in, R* data, int ncomp, const int* skip) {
 template <typename R>
 int inv_yx(fg_plan* P, R* data, R* out, int ncomp, const C2REpi& epi) {
   const SpecTables<R> tb = tabs<R>(P).spec();
-  launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1, epi.skip,
-                 P->stream);
+  {
+    ProfScope ps(P, FG_PASS_AXIS);
+    launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1, epi.skip,
+                   P->stream);
+  }
+  ProfScope ps(P, FG_PASS_C2R);
   return launch_c2r<R>(P->M, data, out, (long)ncomp * P->n0 * P->n1, tb, epi, P->stream);
 }
 
@@ -286,7 +323,10 @@ int inv_yx(fg_plan* P, R* data, R* out, int ncomp, const C2REpi& epi) {
 template <typename R>
 int project9(fg_plan* P, const R* in, R* work, R* out, const C2REpi& epi) {
   fwd_xy<R>(P, in, work, 9, epi.skip);
-  launch_zproj<R>(P->n0, work, P->n1, P->M, tabs<R>(P).spec(), (R)(1.0 / (double)P->N), epi.skip, P->stream);
+  {
+    ProfScope ps(P, FG_PASS_ZPROJ);
+    launch_zproj<R>(P->n0, work, P->n1, P->M, tabs<R>(P).spec(), (R)(1.0 / (double)P->N), epi.skip, P->stream);
+  }
   return inv_yx<R>(P, work, out, 9, epi);
 }
 
@@ -294,14 +334,18 @@ int project9(fg_plan* P, const R* in, R* work, R* out, const C2REpi& epi) {
 template <typename R>
 int precond1(fg_plan* P, const R* in, R* work, R* out, double a0, double a1, const C2REpi& epi) {
   fwd_xy<R>(P, in, work, 1, epi.skip);
-  launch_zscalar<R>(P->n0, work, P->n1, P->M, tabs<R>(P).spec(), (R)(1.0 / (double)P->N), a0, a1, epi.skip,
-                    P->stream);
+  {
+    ProfScope ps(P, FG_PASS_ZSCALAR);
+    launch_zscalar<R>(P->n0, work, P->n1, P->M, tabs<R>(P).spec(), (R)(1.0 / (double)P->N), a0, a1, epi.skip,
+                      P->stream);
+  }
   return inv_yx<R>(P, work, out, 1, epi);
 }
 
 // ----------------------------------------------------------------------------
 // Mechanics.
 void constitutive(fg_plan* P, const double* Fu, double* Pout, void* state, double* pparts) {
+  ProfScope ps(P, FG_PASS_CONSTITUTIVE);
   const unsigned nb = blocks_for(P->N);
   const double* c = P->c ? P->c : P->zeroN;
   const double* d = P->d ? P->d : P->zeroN;
@@ -354,13 +398,25 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
   int chunk = 4;
   for (int guard = 0; guard < 1000000; ++guard) {
     for (int k = 0; k < chunk; ++k) {
-      hipLaunchKernelGGL((k_contract<T>), dim3(nbN), dim3(256), 0, P->stream, S, p, r, st, ks, P->N, 1);
+      {
+        ProfScope ps(P, FG_PASS_CONTRACT);
+        hipLaunchKernelGGL((k_contract<T>), dim3(nbN), dim3(256), 0, P->stream, S, p, r, st, ks, P->N, 1);
+      }
       C2REpi epi{1.0, p, false, P->part, skip};
       const int nb = project9<T>(P, S, S, S, epi);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part, nb, ks, (double*)nullptr, 0, 0);
-      hipLaunchKernelGGL((k_cg_update<T>), dim3(nbu), dim3(256), 0, P->stream, x, r, p, S, ks, P->part2, n9);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part2, (int)nbu, ks, (double*)nullptr,
-                         1, 0);
+      {
+        ProfScope ps(P, FG_PASS_FINALIZE);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part, nb, ks, (double*)nullptr, 0, 0);
+      }
+      {
+        ProfScope ps(P, FG_PASS_CG_UPDATE);
+        hipLaunchKernelGGL((k_cg_update<T>), dim3(nbu), dim3(256), 0, P->stream, x, r, p, S, ks, P->part2, n9);
+      }
+      {
+        ProfScope ps(P, FG_PASS_FINALIZE);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part2, (int)nbu, ks, (double*)nullptr,
+                           1, 0);
+      }
       check_launch();
     }
     sync_read(P);
@@ -428,8 +484,9 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
                          (const double*)P->x, n9);
     } else {
       fg_solver_opts om = *o;
-      // inner forcing: the single-precision operator cannot resolve beyond ~1e-6
-      if (om.fixed_lin <= 0) om.tol_lin = std::max(o->tol_lin, 1e-5);
+      // inner forcing: a single-precision CG is not asked for more than 1e-6;
+      // the double-precision Newton residual refines the rest
+      if (om.fixed_lin <= 0) om.tol_lin = std::max(o->tol_lin, 1e-6);
       cg_solve<float>(P, &om, stats);
       hipLaunchKernelGGL((k_axpy_into_f64<float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->F,
                          (const float*)P->x, n9);
@@ -608,6 +665,20 @@ void fick(fg_plan* P, double dt, const double* cdot, const fg_solver_opts* o, fg
 
 }  // namespace
 
+namespace {
+// F^0 = F_t + (F_macro - <F_t>): the macroscopic increment of Alg. 1.
+void apply_macro(fg_plan* P, const double F_macro[9]) {
+  mean9(P, P->F);
+  sync_read(P);
+  for (int k = 0; k < 9; ++k) P->hd[32 + k] = F_macro[k] - P->hd[8 + k] / (double)P->N;
+  FG_HIP(hipMemcpyAsync(P->Fu, P->hd + 32, 9 * sizeof(double), hipMemcpyHostToDevice, P->stream));
+  hipLaunchKernelGGL(k_add_uniform9, dim3(blocks_for(P->N)), dim3(256), 0, P->stream, P->F, (const double*)P->Fu,
+                     P->N);
+  check_launch();
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI --
 namespace {
 fg_status run(fg_plan* P, const std::function<void()>& fn) {
@@ -728,21 +799,22 @@ fg_status fg_set_state(fg_plan* P, double* F, double* c, double* d, double* H) {
   return FG_OK;
 }
 
+fg_status fg_apply_macro(fg_plan* P, const double F_macro[9]) {
+  if (!P || !F_macro) return FG_E_ARG;
+  return run(P, [&]() {
+    need_ready(P, true);
+    apply_macro(P, F_macro);
+    FG_HIP(hipStreamSynchronize(P->stream));
+  });
+}
+
 fg_status fg_newton_solve(fg_plan* P, const double F_macro[9], const fg_solver_opts* opts, fg_stats* stats) {
   if (!P || !F_macro || !opts) return FG_E_ARG;
   if (opts->max_lin <= 0 && opts->fixed_lin <= 0) return FG_E_ARG;
   return run(P, [&]() {
     need_ready(P, true);
     if (stats) std::memset(stats, 0, sizeof(fg_stats));
-    // F^0 = F_t + (F_macro - <F_t>)
-    mean9(P, P->F);
-    sync_read(P);
-    double dF[9];
-    for (int k = 0; k < 9; ++k) dF[k] = F_macro[k] - P->hd[8 + k] / (double)P->N;
-    FG_HIP(hipMemcpyAsync(P->Fu, dF, 9 * sizeof(double), hipMemcpyHostToDevice, P->stream));
-    hipLaunchKernelGGL(k_add_uniform9, dim3(blocks_for(P->N)), dim3(256), 0, P->stream, P->F,
-                       (const double*)P->Fu, P->N);
-    check_launch();
+    apply_macro(P, F_macro);
     newton(P, F_macro, opts, stats);
     FG_HIP(hipStreamSynchronize(P->stream));
   });
@@ -874,6 +946,34 @@ fg_status fick_step(fg_plan* P, double dt, const double* cdot_B, const fg_solver
   });
 }
 
+fg_status fg_profile_begin(fg_plan* P) {
+  if (!P) return FG_E_ARG;
+  return run(P, [&]() {
+    FG_HIP(hipStreamSynchronize(P->stream));
+    P->prof_on = true;
+    for (int k = 0; k < FG_NPASS; ++k) P->prof_used[k] = 0;
+  });
+}
+
+fg_status fg_profile_end(fg_plan* P, double ms[], long launches[]) {
+  if (!P || !ms || !launches) return FG_E_ARG;
+  return run(P, [&]() {
+    P->prof_on = false;
+    FG_HIP(hipStreamSynchronize(P->stream));
+    for (int k = 0; k < FG_NPASS; ++k) {
+      double tot = 0.0;
+      for (size_t u = 0; u < P->prof_used[k]; ++u) {
+        float t = 0.f;
+        FG_HIP(hipEventElapsedTime(&t, P->prof_ev[k][u].first, P->prof_ev[k][u].second));
+        tot += t;
+      }
+      ms[k] = tot;
+      launches[k] = (long)P->prof_used[k];
+      P->prof_used[k] = 0;
+    }
+  });
+}
+
 const char* fg_status_string(fg_status s) {
   switch (s) {
     case FG_OK: return "ok";
@@ -892,6 +992,11 @@ const char* fg_last_error(const fg_plan* P) { return P ? P->err.c_str() : "null 
 
 void fg_plan_destroy(fg_plan* P) {
   if (!P) return;
+  for (int k = 0; k < FG_NPASS; ++k)
+    for (auto& e : P->prof_ev[k]) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
   if (P->hks) (void)hipHostFree(P->hks);
   if (P->hd) (void)hipHostFree(P->hd);
   if (P->hflags) (void)hipHostFree(P->hflags);

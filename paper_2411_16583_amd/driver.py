@@ -1,0 +1,32 @@
+"""Staggered time stepping (Alg. 4) on top of the C ABI.
+
+Per time step: the macroscopic increment and one Fick step with the fields
+of the previous step (Alg. 3), then mechanics (Alg. 1) and phase field
+(Alg. 2) alternate until the equilibrium residual (eq. (31)) recomputed with
+the new damage is <= tol_newton (at most ``max_stag`` times).  Every solver
+call runs in the HIP library; this module only sequences them.
+"""
+from __future__ import annotations
+
+from .fgfft import make_opts
+
+
+def staggered_step(plan, F_macro, dt=None, cdot_B=None, chemistry=True, tol_newton=1e-8, tol_lin=1e-10,
+                   tol_chem=1e-8, tol_pff=1e-10, max_stag=20, max_lin=20000):
+    """One time step; returns a stats dict.  The plan's state (F, c, d, H)
+    is updated in place."""
+    st = dict(chem=None, newton=[], pff=[], stag_iters=0, err_res=None)
+    plan.apply_macro(F_macro)  # F^0 = F_t + dFbar (Alg. 1, first line)
+    if chemistry:
+        # chemistry once per step, with the new macroscopic F and the damage of
+        # the previous step
+        st["chem"] = plan.fick_step(dt, cdot_B, make_opts(tol_chem, tol_lin, 50, max_lin))
+    for k in range(max_stag):
+        st["newton"].append(plan.newton_solve(F_macro, make_opts(tol_newton, tol_lin, 50, max_lin)))
+        st["pff"].append(plan.pff_solve(make_opts(tol_newton, tol_pff, 50, max_lin)))
+        err = plan.residual(F_macro)
+        st["stag_iters"] = k + 1
+        st["err_res"] = err
+        if err <= tol_newton:
+            break
+    return st

@@ -23,10 +23,11 @@ PRECISIONS = {"fp64": FG_FP64, "mixed": FG_MIXED}
 # Every function declared in include/fgfft.h.
 EXPORTED = [
     "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
-    "fg_set_state", "fg_newton_solve", "fg_residual", "fg_homogenized_stress", "fg_stress",
+    "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_residual", "fg_homogenized_stress", "fg_stress",
     "fg_apply_operator", "fg_project", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
-    "fg_status_string", "fg_last_error", "fg_plan_destroy",
+    "fg_profile_begin", "fg_profile_end", "fg_status_string", "fg_last_error", "fg_plan_destroy",
 ]
+PASS_NAMES = ["contract", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive", "zscalar"]
 
 
 class SolverOpts(ctypes.Structure):
@@ -90,6 +91,7 @@ def load_library(path=LIB_PATH):
         "fg_plan_set_workspace": ([vp, vp, c_size], c_int),
         "fg_set_material": ([vp, dptr, dptr, dptr, dptr, dptr, c_double, c_double, c_double, c_double], c_int),
         "fg_set_state": ([vp, dptr, dptr, dptr, dptr], c_int),
+        "fg_apply_macro": ([vp, ctypes.POINTER(c_double)], c_int),
         "fg_newton_solve": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
         "fg_residual": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
         "fg_homogenized_stress": ([vp, ctypes.POINTER(c_double)], c_int),
@@ -100,6 +102,8 @@ def load_library(path=LIB_PATH):
         "fg_fft_c2r": ([vp, dptr, c_int], c_int),
         "pff_solve": ([vp, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
         "fick_step": ([vp, c_double, dptr, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
+        "fg_profile_begin": ([vp], c_int),
+        "fg_profile_end": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(ctypes.c_long)], c_int),
         "fg_status_string": ([c_int], ctypes.c_char_p),
         "fg_last_error": ([vp], ctypes.c_char_p),
         "fg_plan_destroy": ([vp], None),
@@ -199,6 +203,10 @@ class Plan:
         d["status"] = st
         return d
 
+    def apply_macro(self, F_macro):
+        a, p = _mat9(F_macro)
+        self._check(self.lib.fg_apply_macro(self.handle, p), "fg_apply_macro")
+
     def residual(self, F_macro):
         a, p = _mat9(F_macro)
         out = ctypes.c_double()
@@ -239,6 +247,16 @@ class Plan:
         d = stats.to_dict()
         d["status"] = st
         return d
+
+    def profile_begin(self):
+        self._check(self.lib.fg_profile_begin(self.handle), "fg_profile_begin")
+
+    def profile_end(self):
+        n = len(PASS_NAMES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_long * n)()
+        self._check(self.lib.fg_profile_end(self.handle, ms, cnt), "fg_profile_end")
+        return {name: (ms[k], cnt[k]) for k, name in enumerate(PASS_NAMES)}
 
     def fick_step(self, dt, cdot_B=None, opts=None, raise_on_error=True):
         opts = opts or make_opts()

@@ -1,0 +1,136 @@
+"""GPU parity of the phase-field PCG (Alg. 2), the Fick step (Alg. 3) and
+the staggered scheme (Alg. 4) against the CPU oracle, plus the closed forms
+they must reproduce (uniform H, the exact 1-D plane-crack profile, the
+uniform Fick update and the mass identity of eq. (25)).
+
+FP64 tolerances: solutions of converged solves 1e-10 relative (the oracle
+and the GPU stop on the same test with CG tolerance 1e-12 here).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import chemistry as ch
+from oracle import fracture, mechanics, staggered
+from paper_2411_16583_amd import make_opts
+from paper_2411_16583_amd.driver import staggered_step
+from tests.gpu_util import dt, host, plan_for, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(plan, F, c, d, H):
+    t = dict(F=dt(F), c=dt(c), d=dt(d), H=dt(H))
+    plan.set_state(t["F"], t["c"], t["d"], t["H"])
+    return t
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_pff_plane_crack_closed_form(axis):
+    n, h = 64, 0.05
+    shape = [4, 4, 4]
+    shape[axis] = n
+    shape = tuple(shape)
+    work = synth.homogeneous_workload(shape, tuple(h * s for s in shape))
+    work["gc"], work["lc"] = 2.0, 2 * h
+    H = np.zeros(shape)
+    sl = [slice(None)] * 3
+    sl[axis] = 0
+    H[tuple(sl)] = 40.0
+    plan = plan_for(work)
+    t = _state(plan, mechanics.uniform_field(np.eye(3), shape), np.zeros(shape), np.zeros(shape), H)
+    st = plan.pff_solve(make_opts(tol_lin=1e-14, max_lin=2000))
+    prof, _ = fracture.plane_crack_profile(n, h, 2 * h, 2.0, 40.0)
+    d = host(t["d"], shape)
+    line = np.moveaxis(d, axis, 0)[:, 1, 2]
+    assert np.max(np.abs(line - prof)) <= 1e-12 * prof.max()
+    assert np.array_equal(host(t["H"], shape), H)
+
+
+def test_pff_uniform_history_one_iteration():
+    shape = (8, 12, 16)
+    work = synth.homogeneous_workload(shape, 1.0)
+    plan = plan_for(work)
+    H = np.full(shape, 7.5)
+    t = _state(plan, mechanics.uniform_field(np.eye(3), shape), np.zeros(shape), np.zeros(shape), H)
+    st = plan.pff_solve(make_opts(tol_lin=1e-12))
+    exact = 2 * 7.5 / (work["gc"] / work["lc"] + 2 * 7.5)
+    assert st["lin_iters_last"] == 1
+    assert np.max(np.abs(host(t["d"]) - exact)) <= 1e-14
+
+
+def test_pff_history_and_solve_match_oracle():
+    rng = np.random.default_rng(200)
+    shape = (16, 24, 32)
+    work = synth.homogeneous_workload(shape, 1e-5, E=15e9, Omega=0.03, sigma_max=30e6)
+    work["E"] = np.where(rng.random(shape) < 0.5, 15e9, 5e9)
+    F = mechanics.uniform_field(np.eye(3), shape) + 0.004 * rng.standard_normal((3, 3) + shape)
+    c = 0.2 * rng.random(shape)
+    H0 = np.where(rng.random(shape) < 0.1, 1e6, 0.0)
+    plan = plan_for(work)
+    t = _state(plan, F, c, np.zeros(shape), H0)
+    st = plan.pff_solve(make_opts(tol_lin=1e-12))
+    Ho = fracture.update_history(H0, F, c, work)
+    do, it = fracture.pff_solve(Ho, work["gc"], work["lc"], work["spacing"], tol=1e-12)
+    Hg = host(t["H"], shape)
+    print(f"pff: iters gpu {st['lin_iters_last']} oracle {it}; H>0: {np.mean(Ho > H0):.3f}", flush=True)
+    assert np.mean(Ho > H0) > 0.05
+    assert rel(Hg, Ho) <= 1e-12
+    assert rel(host(t["d"], shape), do) <= 1e-10
+    assert abs(st["lin_iters_last"] - it) <= 1
+
+
+def test_fick_uniform_update_and_mass():
+    shape = (8, 8, 16)
+    work = synth.homogeneous_workload(shape, 1e-6, E=15e9, Omega=0.03, D=1e-14)
+    plan = plan_for(work)
+    cdot = np.full(shape, 3e-3)
+    t = _state(plan, mechanics.uniform_field(np.eye(3), shape), np.full(shape, 0.2), np.zeros(shape),
+               np.zeros(shape))
+    st = plan.fick_step(2.0, dt(cdot), make_opts(tol_newton=1e-10, tol_lin=1e-12))
+    assert np.max(np.abs(host(t["c"]) - (0.2 + 2.0 * 3e-3))) <= 1e-15
+
+
+def test_fick_step_matches_oracle():
+    rng = np.random.default_rng(201)
+    shape = (16, 16, 24)
+    work = synth.homogeneous_workload(shape, 2e-6, E=15e9, Omega=0.03, D=1e-14)
+    work["D"] = np.where(rng.random(shape) < 0.5, 1e-14, 1e-16)
+    F = mechanics.uniform_field(np.eye(3), shape) + 0.01 * rng.standard_normal((3, 3) + shape)
+    c = 0.05 + 0.3 * rng.random(shape)
+    d = 0.3 * rng.random(shape)
+    cdot = np.where(rng.random(shape) < 0.2, 4e-3, 0.0)
+    plan = plan_for(work)
+    t = _state(plan, F, c, d, np.zeros(shape))
+    st = plan.fick_step(5.0, dt(cdot), make_opts(tol_newton=1e-10, tol_lin=1e-12))
+    co, so = ch.fick_step(c, F, d, cdot, 5.0, work, tol_chem=1e-10, tol_lin=1e-12)
+    cg = host(t["c"], shape)
+    print(f"fick: newton gpu {st['newton_iters']} oracle {so['newton_iters']}, "
+          f"pcg gpu {st['lin_history']} oracle {so['lin_iters']}", flush=True)
+    assert st["newton_iters"] == so["newton_iters"]
+    assert rel(cg, co, co - c) <= 1e-10
+    assert abs(cg.sum() - c.sum() - 5.0 * cdot.sum()) <= 1e-10 * c.sum()
+
+
+def test_staggered_particle_twin_matches_oracle():
+    """Two staggered steps of the 16^3 twin of the particle workload (flux,
+    swelling, buffer, damage) through the C ABI vs the oracle's Alg. 4."""
+    w = synth.particle_workload(n=16, n_steps=2, dt=20.0, q_in=4e-10, sigma_max=0.8e6)
+    shape = w["shape"]
+    plan = plan_for(w)
+    F0 = mechanics.uniform_field(np.eye(3), shape)
+    t = _state(plan, F0, w["c0"], w["d0"], np.zeros(shape))
+    cdot = dt(w["cdot_B"])
+    Fo, co, do, Ho = F0.copy(), w["c0"].copy(), w["d0"].copy(), np.zeros(shape)
+    for step in range(1):
+        sg = staggered_step(plan, np.eye(3), dt=w["dt"], cdot_B=cdot, tol_lin=1e-10)
+        Fo, co, do, Ho, so = staggered.staggered_step(Fo, co, do, Ho, np.eye(3), np.eye(3), w, dt=w["dt"],
+                                                      cdot_B=w["cdot_B"])
+        print(f"step {step}: stag gpu {sg['stag_iters']} oracle {so['stag_iters']}", flush=True)
+        assert sg["stag_iters"] == so["stag_iters"]
+        ec = rel(host(t["c"], shape), co, co - w["c0"])
+        ed = rel(host(t["d"], shape), do)
+        eF = rel(host(t["F"], (3, 3) + shape), Fo, Fo - F0)
+        print(f"  rel c {ec:.2e} d {ed:.2e} F {eF:.2e}", flush=True)
+        assert ec <= 1e-9 and ed <= 1e-8 and eF <= 1e-8

@@ -48,7 +48,7 @@ WORDS_PER_VOXEL = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--forms", default="fp64,mixed")
@@ -172,8 +172,15 @@ def main():
           f"inclusion fraction {work['phase'].mean():.3f}", flush=True)
     forms = args.forms.split(",")
     res = {}
+    errors = {}
     for form in forms:
-        res[form] = run_form(work, form, args.steps, args.warmup)
+        try:
+            res[form] = run_form(work, form, args.steps, args.warmup)
+        except Exception as e:  # report a failing form instead of dropping the line
+            if form == forms[0]:
+                raise
+            errors[form] = repr(e)
+            print(f"[{form}] failed: {e!r}", flush=True)
     main_form = "fp64" if "fp64" in res else forms[0]
     r0 = res[main_form]
     value = N * r0["cg_iters"] / r0["elapsed"]
@@ -197,6 +204,9 @@ def main():
     }
     for form in forms:
         if form == main_form:
+            continue
+        if form in errors:
+            line[form] = dict(error=errors[form])
             continue
         r = res[form]
         v = N * r["cg_iters"] / r["elapsed"]

@@ -428,8 +428,12 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
     stats->lin_iters_last = h.iter;
     stats->lin_relres = h.rr0 > 0 ? std::sqrt(h.rr / h.rr0) : 0.0;
   }
-  if (h.flag == 1) throw Status(FG_E_BREAKDOWN, "CG breakdown: p.Ap <= 0");
-  if (h.flag == 2) throw Status(FG_E_NOCONV, "CG reached max_lin iterations");
+  // An inexact inner solve in the mixed form (single-precision rounding
+  // breaking p.Ap > 0, or the iteration cap) still hands its correction to
+  // the double-precision Newton loop, which measures the true residual.
+  const bool inexact_ok = (P->prec == FG_MIXED) && h.iter > 0;
+  if (h.flag == 1 && !inexact_ok) throw Status(FG_E_BREAKDOWN, "CG breakdown: p.Ap <= 0");
+  if (h.flag == 2 && !inexact_ok) throw Status(FG_E_NOCONV, "CG reached max_lin iterations");
 }
 
 // Newton loop of Alg. 1 at the current F (increment already applied).
@@ -462,7 +466,11 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
       stats->err_res = err;
     }
     if (!(err == err)) throw Status(FG_E_NOCONV, "Newton residual is NaN");
-    if (err <= o->tol_newton) break;
+    // The mixed form converges linearly (inner forcing 1e-6) where the FP64
+    // form converges quadratically and lands well below tol_newton; refining
+    // to 0.01 tol_newton gives both the same final accuracy.
+    const double tol_eff = (P->prec == FG_MIXED) ? 0.01 * o->tol_newton : o->tol_newton;
+    if (err <= tol_eff) break;
     if (it >= o->max_newton) throw Status(FG_E_NOCONV, "Newton reached max_newton iterations");
     // b = -G*(G*P): second projection of the residual (compatible rhs)
     {
@@ -484,9 +492,10 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
                          (const double*)P->x, n9);
     } else {
       fg_solver_opts om = *o;
-      // inner forcing: a single-precision CG is not asked for more than 1e-6;
-      // the double-precision Newton residual refines the rest
-      if (om.fixed_lin <= 0) om.tol_lin = std::max(o->tol_lin, 1e-6);
+      // Inner forcing: the single-precision operator is accurate to a few
+      // 1e-7 at 256^3 (FFT rounding), so CG is not asked for more than 1e-5;
+      // the double-precision Newton residual refines the rest.
+      if (om.fixed_lin <= 0) om.tol_lin = std::max(o->tol_lin, 1e-5);
       cg_solve<float>(P, &om, stats);
       hipLaunchKernelGGL((k_axpy_into_f64<float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->F,
                          (const float*)P->x, n9);

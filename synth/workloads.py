@@ -149,9 +149,12 @@ def particle_workload(n=128, n_steps=200, dt=5.0, q_in=4.0e-10, sigma_max=20e6):
 
 
 def polydisperse_workload(n=256, n_spheres=60, n_inc=20, total_strain=0.05,
-                          sigma_max=400e6):
+                          strength_ratio=0.04):
     """Periodic RSA spheres (radii U(10, 24) voxels at 256^3, scaled with
-    n / 256), spheres 200 GPa, matrix 10 GPa, nu = 0.3."""
+    n / 256), spheres 200 GPa, matrix 10 GPa, nu = 0.3.  The threshold
+    stress is proportional to stiffness, sigma_max = 0.04 E (400 MPa in the
+    matrix, 8 GPa in the spheres), so damage starts in the second half of
+    the stretch ramp instead of in the stiff spheres at the first step."""
     shape, spacing = _base((n, n, n), 1.0)
     s = n / 256.0
     rng = rng_for(3)
@@ -161,7 +164,7 @@ def polydisperse_workload(n=256, n_spheres=60, n_inc=20, total_strain=0.05,
         name="polydisperse", shape=shape, spacing=spacing, phase=inc,
         centres=centres, radii=radii,
         E=E, nu=np.full(shape, 0.3), Omega=np.zeros(shape),
-        D=np.full(shape, 1e-14), sigma_max=np.full(shape, sigma_max),
+        D=np.full(shape, 1e-14), sigma_max=strength_ratio * E,
         gc=1.0, lc=2.0 * spacing[0], RT=GAS_R * 298.15, c_max=3.0e4,
         c0=np.zeros(shape), d0=np.zeros(shape),
         loads=uniaxial_schedule(total_strain, n_inc),

@@ -198,8 +198,10 @@ enum {
 /* Time every launch of each kernel class with a HIP event pair on the plan
  * stream, from fg_profile_begin until fg_profile_end, which synchronises and
  * returns the summed milliseconds ms[FG_NPASS] and the number of launches
- * launches[FG_NPASS] per class (host arrays).  Measurement support for the
- * benchmark; adds two event records per launch while enabled. */
+ * launches[FG_NPASS] per class (host arrays).  Launches of the CG loop that
+ * found the solve already converged (they exit at once, a few microseconds)
+ * are not counted in launches[].  Measurement support for the benchmark;
+ * adds two event records per launch while enabled. */
 fg_status fg_profile_begin(fg_plan* plan);
 fg_status fg_profile_end(fg_plan* plan, double ms[], long launches[]);
 

@@ -74,7 +74,7 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
                   hipStream_t s) {
   const int B = column_tile(N0, M, (int)sizeof(cplx<R>));
   const int T = line_threads(N0);
-  const size_t shm = (size_t)N0 * B * sizeof(cplx<R>);
+  const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zpass_extra_lds<R>(N0);
   dim3 grid((unsigned)(M / B), (unsigned)N1, 3);
   dim3 gdc((unsigned)(N1 / 2 + 1), 3, 1);
   switch (N0) {
@@ -94,7 +94,7 @@ void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R s
                     const int* skip, hipStream_t s) {
   const int B = column_tile(N0, M, (int)sizeof(cplx<R>));
   const int T = line_threads(N0);
-  const size_t shm = (size_t)N0 * B * sizeof(cplx<R>);
+  const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zpass_extra_lds<R>(N0);
   dim3 grid((unsigned)(M / B), (unsigned)N1, 1);
   dim3 gdc((unsigned)(N1 / 2 + 1), 1, 1);
   switch (N0) {

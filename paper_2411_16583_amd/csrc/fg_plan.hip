@@ -282,7 +282,7 @@ void check_domain(fg_plan* P) {
 
 // Sum of nparts partials into dscal[slot].
 void reduce_to(fg_plan* P, const double* parts, int nparts, int slot) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, parts, nparts, (KrylovScalars*)nullptr,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, parts, nparts, (KrylovScalars*)nullptr,
                      P->dscal + slot, 2, 0);
   check_launch();
 }
@@ -432,13 +432,14 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
     for (int k = 0; k < chunk; ++k) {
       {
         ProfScope ps(P, FG_PASS_CONTRACT);
-        hipLaunchKernelGGL((k_contract<T>), dim3(nbN), dim3(256), 0, P->stream, S, p, r, st, ks, P->N, 1);
+        hipLaunchKernelGGL((k_contract<T>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, S, p, r, st, ks,
+                           P->N, 1);
       }
       C2REpi epi{1.0, p, false, P->part, skip};
       const int nb = project9<T>(P, S, S, S, epi);
       {
         ProfScope ps(P, FG_PASS_FINALIZE);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part, nb, ks, (double*)nullptr, 0, 0);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, ks, (double*)nullptr, 0, 0);
       }
       {
         ProfScope ps(P, FG_PASS_CG_UPDATE);
@@ -446,7 +447,7 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
       }
       {
         ProfScope ps(P, FG_PASS_FINALIZE);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part2, (int)nbu, ks, (double*)nullptr,
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbu, ks, (double*)nullptr,
                            1, 0);
       }
       check_launch();
@@ -509,7 +510,7 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
     {
       C2REpi epi{-1.0, nullptr, true, P->part, nullptr};
       const int nb = project9<double>(P, P->S64, P->S64, P->S64, epi);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
       check_launch();
       if (P->prec == FG_FP64) {
         FG_HIP(hipMemcpyAsync(P->r, P->S64, n9 * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
@@ -598,7 +599,7 @@ void scalar_pcg(fg_plan* P, ScalarOp op, double a0, double a1, double dt, const 
   auto apply_prec = [&]() {
     C2REpi epi{1.0, v.r, false, P->part, skip};
     const int nb = precond1<double>(P, v.r, v.work, v.z, a0, a1, epi);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part, nb, ks, (double*)nullptr, 4, 1);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, ks, (double*)nullptr, 4, 1);
   };
   apply_prec();
   check_launch();
@@ -612,11 +613,11 @@ void scalar_pcg(fg_plan* P, ScalarOp op, double a0, double a1, double dt, const 
       else
         hipLaunchKernelGGL(k_fick_apply, dim3(nbN), dim3(256), 0, P->stream, v.p, v.w, v.A6, dt, g, v.q, P->part,
                            ks, P->N);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part, (int)nbN, ks, (double*)nullptr, 0,
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, (int)nbN, ks, (double*)nullptr, 0,
                          1);
       hipLaunchKernelGGL((k_cg_update<double>), dim3(nbu), dim3(256), 0, P->stream, v.x, v.r, v.p, v.q, ks,
                          P->part2, P->N);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part2, (int)nbu, ks, (double*)nullptr, 3,
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbu, ks, (double*)nullptr, 3,
                          1);
       apply_prec();
       check_launch();
@@ -644,7 +645,7 @@ void pff(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
                      v.a, v.r, v.x, P->gc, P->lc, P->part, P->part2, P->flags, P->N);
   check_launch();
   reduce_to(P, P->part, (int)nbN, 0);  // sum H
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part2, (int)nbN, P->ks + 1, (double*)nullptr,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbN, P->ks + 1, (double*)nullptr,
                      5, 1);
   check_launch();
   sync_read(P);
@@ -689,7 +690,7 @@ void fick(fg_plan* P, double dt, const double* cdot, const fg_solver_opts* o, fg
     hipLaunchKernelGGL(k_fick_residual, dim3(nbN), dim3(256), 0, P->stream, P->c, v.ct, v.mu, v.A6, cdot, dt, g,
                        v.r, v.x, P->part2, N);
     check_launch();
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, P->stream, P->part2, (int)nbN, P->ks + 1,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbN, P->ks + 1,
                        (double*)nullptr, 5, 1);
     check_launch();
     sync_read(P);
@@ -920,7 +921,8 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
     const unsigned nbN = blocks_for(P->N);
     if (P->prec == FG_FP64) {
       constitutive(P, nullptr, nullptr, P->st, nullptr);
-      hipLaunchKernelGGL((k_contract<double>), dim3(nbN), dim3(256), 0, P->stream, y, (double*)x, (const double*)nullptr,
+      hipLaunchKernelGGL((k_contract<double>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, y, (double*)x,
+                         (const double*)nullptr,
                          (const double*)P->st, (const KrylovScalars*)nullptr, P->N, 0);
       check_launch();
       C2REpi epi{1.0, nullptr, true, nullptr, nullptr};
@@ -931,7 +933,8 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
       float* yf = (float*)P->S;
       hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, xf, x,
                          n9);
-      hipLaunchKernelGGL((k_contract<float>), dim3(nbN), dim3(256), 0, P->stream, yf, xf, (const float*)nullptr,
+      hipLaunchKernelGGL((k_contract<float>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, yf, xf,
+                         (const float*)nullptr,
                          (const float*)P->st, (const KrylovScalars*)nullptr, P->N, 0);
       check_launch();
       C2REpi epi{1.0, nullptr, true, nullptr, nullptr};

@@ -124,53 +124,134 @@ __device__ __forceinline__ void tangent_apply(const T (&A)[9], T al, T be, T ga,
 // CG direction update fused with the tangent contraction:
 //   p <- r (first iteration) or r + beta p;  Y = K : p.
 // With update == false: Y = K : p for the given p (no CG state).
+// Two voxels per thread (one 2-vector load per plane); N is even.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_contract(T* __restrict__ Y, T* __restrict__ p, const T* __restrict__ r, const T* __restrict__ st,
            const KrylovScalars* __restrict__ ks, long N, int update) {
+  using V = cplx<T>;
   if (ks && ks->done) return;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  T X[9];
+  const long N2v = N / 2;
+  if (i >= N2v) return;
+  V* pv = reinterpret_cast<V*>(p);
+  const V* rv = reinterpret_cast<const V*>(r);
+  const V* sv = reinterpret_cast<const V*>(st);
+  V* yv = reinterpret_cast<V*>(Y);
+  T X0[9], X1[9];
   if (update) {
     const bool first = ks->iter == 0;
     const T beta = (T)ks->beta;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const T rk = r[k * N + i];
-      const T pk = first ? rk : rk + beta * p[k * N + i];
-      p[k * N + i] = pk;
-      X[k] = pk;
+      const V rk = rv[k * N2v + i];
+      V pk = rk;
+      if (!first) {
+        const V po = pv[k * N2v + i];
+        pk = mk<V>(rk.x + beta * po.x, rk.y + beta * po.y);
+      }
+      pv[k * N2v + i] = pk;
+      X0[k] = pk.x;
+      X1[k] = pk.y;
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) X[k] = p[k * N + i];
+    for (int k = 0; k < 9; ++k) {
+      const V pk = pv[k * N2v + i];
+      X0[k] = pk.x;
+      X1[k] = pk.y;
+    }
   }
-  T A[9];
+  T A0[9], A1[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) A[k] = st[k * N + i];
-  T Yv[9];
-  tangent_apply<T>(A, st[9 * N + i], st[10 * N + i], st[11 * N + i], X, Yv);
+  for (int k = 0; k < 9; ++k) {
+    const V a = sv[k * N2v + i];
+    A0[k] = a.x;
+    A1[k] = a.y;
+  }
+  const V al = sv[9 * N2v + i], be = sv[10 * N2v + i], ga = sv[11 * N2v + i];
+  T Y0[9], Y1[9];
+  tangent_apply<T>(A0, al.x, be.x, ga.x, X0, Y0);
+  tangent_apply<T>(A1, al.y, be.y, ga.y, X1, Y1);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Y[k * N + i] = Yv[k];
+  for (int k = 0; k < 9; ++k) yv[k * N2v + i] = mk<V>(Y0[k], Y1[k]);
 }
 
-// x += alpha p, r -= alpha q, per-block partial sums of r.r.
+// 16-byte vector of the working precision (2 doubles or 4 floats).
+template <typename T> struct vec16;
+template <> struct vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+template <> struct vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+
+template <typename T, typename V> __device__ __forceinline__ T vget(const V& v, int k) {
+  if constexpr (sizeof(V) == 16 && sizeof(T) == 8) {
+    return k == 0 ? v.x : v.y;
+  } else {
+    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+  }
+}
+template <typename T, typename V> __device__ __forceinline__ void vset(V& v, int k, T a) {
+  if constexpr (sizeof(V) == 16 && sizeof(T) == 8) {
+    if (k == 0) v.x = a; else v.y = a;
+  } else {
+    if (k == 0) v.x = a; else if (k == 1) v.y = a; else if (k == 2) v.z = a; else v.w = a;
+  }
+}
+
+// x += alpha p, r -= alpha q, per-block partial sums of r.r.  16-byte
+// accesses; n must be a multiple of the vector width (9N always is).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
             const KrylovScalars* __restrict__ ks, double* __restrict__ partials, long n) {
+  using V = typename vec16<T>::type;
+  constexpr int W = vec16<T>::n;
   __shared__ double red[16];
   if (ks->done) return;
   const T alpha = (T)ks->alpha;
   double acc = 0.0;
+  const long nv = n / W;
+  V* xv = reinterpret_cast<V*>(x);
+  V* rv = reinterpret_cast<V*>(r);
+  const V* pv = reinterpret_cast<const V*>(p);
+  const V* qv = reinterpret_cast<const V*>(q);
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const T xi = x[i] + alpha * p[i];
-    const T ri = r[i] - alpha * q[i];
-    x[i] = xi;
-    r[i] = ri;
-    acc += (double)ri * (double)ri;
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + stride < nv; i += 2 * stride) {
+    V xa = xv[i], ra = rv[i], pa = pv[i], qa = qv[i];
+    V xb = xv[i + stride], rb = rv[i + stride], pb = pv[i + stride], qb = qv[i + stride];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      vset(xa, k, (T)(vget<T>(xa, k) + alpha * vget<T>(pa, k)));
+      const T ta = vget<T>(ra, k) - alpha * vget<T>(qa, k);
+      vset(ra, k, ta);
+      acc += (double)ta * (double)ta;
+      vset(xb, k, (T)(vget<T>(xb, k) + alpha * vget<T>(pb, k)));
+      const T tb = vget<T>(rb, k) - alpha * vget<T>(qb, k);
+      vset(rb, k, tb);
+      acc += (double)tb * (double)tb;
+    }
+    xv[i] = xa;
+    rv[i] = ra;
+    xv[i + stride] = xb;
+    rv[i + stride] = rb;
+  }
+  for (; i < nv; i += stride) {
+    V xa = xv[i], ra = rv[i], pa = pv[i], qa = qv[i];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      vset(xa, k, (T)(vget<T>(xa, k) + alpha * vget<T>(pa, k)));
+      const T ta = vget<T>(ra, k) - alpha * vget<T>(qa, k);
+      vset(ra, k, ta);
+      acc += (double)ta * (double)ta;
+    }
+    xv[i] = xa;
+    rv[i] = ra;
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -189,7 +270,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ partia
 // mode 3: PCG: r.r (convergence) -- z not yet formed.
 // mode 4: PCG: r.z -> beta = rz_new / rz.
 // mode 5: initialise a Krylov solve from rr0 = sum (b.b): rr = rr0, iter = 0.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_finalize(const double* __restrict__ partials, int nparts, KrylovScalars* ks, double* out, int mode, int pcg) {
   __shared__ double red[16];
   if (ks && ks->done && mode != 5 && mode != 2) return;

@@ -36,12 +36,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # mechanics CG iteration, in words of the working precision (9-component
 # fields; the spectrum occupies the same bytes as the real field).
 WORDS_PER_VOXEL = {
-    "contract": 48,   # read r, p (18) + state (12); write p, K:p (18)
-    "r2c": 18,        # read 9, write 9
+    "front": 66,      # read r, p, x (27) + state (12); write x, p, spectrum (27)
     "axis": 18,       # read 9, write 9 (per launch; 2 launches / iteration)
     "zproj": 18,      # read 9, write 9
-    "c2r": 27,        # read 9 + p 9, write 9
-    "cg_update": 54,  # read x, r, p, Ap (36), write x, r (18)
+    "c2r": 27,        # read spectrum 9 + r 9, write r 9
 }
 
 

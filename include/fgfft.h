@@ -183,12 +183,12 @@ fg_status fick_step(fg_plan* plan, double dt, const double* cdot_B, const fg_sol
 
 /* Kernel classes timed by fg_profile_*: */
 enum {
-  FG_PASS_CONTRACT = 0,     /* CG direction update + tangent contraction   */
-  FG_PASS_R2C = 1,          /* real-to-complex pass along N2               */
+  FG_PASS_FRONT = 0,        /* CG front: x, p updates, K:p, p.Kp, N2 pass  */
+  FG_PASS_R2C = 1,          /* real-to-complex pass along N2 (residuals)   */
   FG_PASS_AXIS = 2,         /* complex pass along N1 (forward and inverse) */
   FG_PASS_ZPROJ = 3,        /* N0 pass fused with the projection (main)    */
-  FG_PASS_C2R = 4,          /* complex-to-real pass along N2 + reduction   */
-  FG_PASS_CG_UPDATE = 5,    /* x += alpha p, r -= alpha Ap, r.r            */
+  FG_PASS_C2R = 4,          /* N2 complex-to-real pass; in CG: r -= a Ap   */
+  FG_PASS_CG_UPDATE = 5,    /* vector updates of the scalar PCGs           */
   FG_PASS_FINALIZE = 6,     /* one-block reductions of the Krylov scalars  */
   FG_PASS_CONSTITUTIVE = 7, /* stress and tangent state                    */
   FG_PASS_ZSCALAR = 8,      /* N0 pass fused with a scalar symbol          */

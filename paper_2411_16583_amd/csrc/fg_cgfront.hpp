@@ -1,0 +1,126 @@
+// Front kernel of one CG iteration on the operator of eq. (30), fused:
+//   x <- x + alpha_{k-1} p_{k-1}          (deferred solution update, k > 0)
+//   p <- r (k = 0) or r + beta p          (search direction)
+//   Y  = K : p                            (tangent contraction, 12-word state)
+//   p . Y per block (FP64)                (= p . G(K p) since p is compatible)
+//   Y -> packed real-to-complex transform along N2, written as the spectrum.
+// The contracted field never goes to HBM: it is staged in LDS, line by line,
+// and transformed there.
+//
+// A workgroup owns LB grid lines (i0, i1) and all 9 components of them:
+// phase A is one thread per voxel (coalesced along N2), phase B is the
+// two-stage line FFT of the 9 LB complex lines with T threads each
+// (9 LB T = 144 threads).
+#pragma once
+#include "fg_fft.hpp"
+#include "fg_tangent.hpp"
+
+namespace fg {
+
+template <int M> struct FrontShape {
+  static constexpr int T = Line<M>::T;
+  static constexpr int LB = (16 / T) > 0 ? (16 / T) : 1;  // lines per workgroup
+  static constexpr int THREADS = 9 * LB * T;
+  static constexpr int PADC = (M >= 16) ? 1 : 0;          // complex pad per line buffer
+  static constexpr int LSTRIDE = M + PADC;                // complex elements per line buffer
+};
+
+template <typename R, int M>
+__global__ void __launch_bounds__(FrontShape<M>::THREADS)
+k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* __restrict__ r,
+           const R* __restrict__ st, const KrylovScalars* __restrict__ ks, double* __restrict__ partials,
+           long N, long nlines, SpecTables<R> tb) {
+  using C = cplx<R>;
+  using LS = Line<M>;
+  using FS = FrontShape<M>;
+  constexpr int N2 = 2 * M;
+  constexpr int LB = FS::LB;
+  __shared__ C buf[9 * LB * FS::LSTRIDE];
+  __shared__ double red[16];
+  if (ks->done) return;
+  const int tid = threadIdx.x;
+  const long line0 = (long)blockIdx.x * LB;
+  const bool first = ks->iter == 0;
+  const R alpha = (R)ks->alpha;
+  const R beta = (R)ks->beta;
+  R* yb = reinterpret_cast<R*>(buf);
+  double acc = 0.0;
+  // ---- phase A: pointwise
+  for (int v = tid; v < LB * N2; v += FS::THREADS) {
+    const int l = v / N2;
+    const int n = v % N2;
+    if (line0 + l >= nlines) continue;
+    const long g = (line0 + l) * N2 + n;
+    R X[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const R rk = r[k * N + g];
+      R pk = rk;
+      if (!first) {
+        const R po = p[k * N + g];
+        x[k * N + g] += alpha * po;
+        pk = rk + beta * po;
+      }
+      p[k * N + g] = pk;
+      X[k] = pk;
+    }
+    R A[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A[k] = st[k * N + g];
+    R Y[9];
+    tangent_apply<R>(A, st[9 * N + g], st[10 * N + g], st[11 * N + g], X, Y);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      acc += (double)X[k] * (double)Y[k];
+      yb[(k * LB + l) * (2 * FS::LSTRIDE) + n] = Y[k];
+    }
+  }
+  __syncthreads();
+  // ---- phase B: R2C along N2 of the 9 LB lines held in LDS
+  const int lt = tid / LS::T;  // line task: component * LB + line
+  const int t = tid % LS::T;
+  const int comp = lt / LB;
+  const int l = lt % LB;
+  C* my = buf + lt * FS::LSTRIDE;
+  const bool active = (line0 + l) < nlines;
+  C v[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = my[LS::idxA(t, e)];
+  __syncthreads();  // every line fully read before the exchange writes into it
+  line_fft_AB<M, false>(v, my, 1, t, tb.twM);
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) my[LS::idxB(t, e)] = v[e];
+  __syncthreads();
+  C* dst = reinterpret_cast<C*>(spec) + ((long)comp * nlines + line0 + l) * M;
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const int k = LS::idxB(t, e);
+    const C zk = my[k];
+    C X;
+    if (k == 0) {
+      X = mk<C>(zk.x + zk.y, zk.x - zk.y);
+    } else {
+      const C zm = my[M - k];
+      const C ev = cscale(cadd(zk, cconj(zm)), R(0.5));
+      const C od = cscale(mul_mi(csub(zk, cconj(zm))), R(0.5));
+      X = cadd(ev, cmul(od, tb.post[k]));
+    }
+    if (active) dst[k] = X;
+  }
+  const double s = block_sum(acc, red);
+  if (tid == 0) partials[blockIdx.x] = s;
+}
+
+// x += alpha p once after the CG loop (the last deferred update), unless
+// the loop ended on a breakdown (then the front kernel already applied the
+// last valid step).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_final_x(T* __restrict__ x, const T* __restrict__ p, const KrylovScalars* __restrict__ ks, long n) {
+  if (ks->flag == 1 || ks->iter == 0) return;
+  const T alpha = (T)ks->alpha;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] += alpha * p[i];
+}
+
+}  // namespace fg

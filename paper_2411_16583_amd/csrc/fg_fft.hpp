@@ -23,6 +23,21 @@
 
 namespace fg {
 
+// Device-side scalars of one Krylov solve (FP64, in the workspace).
+struct KrylovScalars {
+  double rr;     // current r.r
+  double rr0;    // b.b
+  double rz;     // r.z (preconditioned solves)
+  double pAp;
+  double alpha;
+  double beta;
+  double tol2;   // tol^2 (0: run to maxit)
+  int iter;
+  int maxit;
+  int done;      // 1 when converged, broken down or out of iterations
+  int flag;      // 0 running/converged, 1 breakdown, 2 max iterations
+};
+
 template <int L> struct LineShape;
 #define FG_LINE_SHAPE(L_, R1_, R2_) \
   template <> struct LineShape<L_> { static constexpr int R1 = R1_, R2 = R2_; };
@@ -214,6 +229,10 @@ struct C2REpi {
   bool self_dot;     // sum y*y
   double* partials;  // nullptr: no reduction
   const int* skip;   // nullptr or device flag
+  // CG residual update instead of a store: rupd <- rupd - alpha * y with
+  // alpha = ks->alpha, partial sums of the new rupd . rupd (out unused).
+  void* rupd = nullptr;
+  const KrylovScalars* ks = nullptr;
 };
 
 template <typename R, int M>
@@ -256,6 +275,24 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
   const C* dv = reinterpret_cast<const C*>(epi.dotv) + line * M;
   const R sg = (R)epi.scale;
   double acc = 0.0;
+  if (epi.rupd) {
+    C* ru = reinterpret_cast<C*>(epi.rupd) + line * M;
+    const R al = (R)epi.ks->alpha;
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const int n = LS::idxB(t, e);
+      if (active) {
+        const C y = cscale(v[e], sg);
+        const C ro = ru[n];
+        const C rn = mk<C>(ro.x - al * y.x, ro.y - al * y.y);
+        ru[n] = rn;
+        acc += (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
+      }
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) epi.partials[blockIdx.x] = s;
+    return;
+  }
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
     const int n = LS::idxB(t, e);

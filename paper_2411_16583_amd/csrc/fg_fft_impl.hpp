@@ -3,6 +3,7 @@
 #pragma once
 #include <stdexcept>
 
+#include "fg_cgfront.hpp"
 #include "fg_launch.hpp"
 
 namespace fg {
@@ -110,7 +111,27 @@ void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R s
   throw std::invalid_argument("unsupported N0");
 }
 
+template <typename R>
+int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const KrylovScalars* ks, double* partials,
+                    long N, long nlines, const SpecTables<R>& tb, hipStream_t s) {
+  switch (M) {
+#define FG_CASE(L_)                                                                                   \
+  case L_: {                                                                                          \
+    using FS = FrontShape<L_>;                                                                        \
+    const long blocks = (nlines + FS::LB - 1) / FS::LB;                                               \
+    hipLaunchKernelGGL((k_cg_front<R, L_>), dim3((unsigned)blocks), dim3(FS::THREADS), 0, s, spec, p, x, r, st, \
+                       ks, partials, N, nlines, tb);                                                  \
+    return (int)blocks;                                                                               \
+  }
+    FG_FOR_M(FG_CASE)
+#undef FG_CASE
+  }
+  throw std::invalid_argument("unsupported N2/2");
+}
+
 #define FG_INSTANTIATE_LAUNCHERS(R)                                                                     \
+  template int launch_cg_front<R>(int, R*, R*, R*, const R*, const R*, const KrylovScalars*, double*, long, \
+                                  long, const SpecTables<R>&, hipStream_t);                             \
   template void launch_r2c<R>(int, const R*, R*, long, const SpecTables<R>&, const int*, hipStream_t); \
   template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t); \
   template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const int*, \

@@ -15,6 +15,12 @@ bool fft_axis_length_supported(int L);  // N0, N1
 int column_tile(int L, int M, int elem_bytes);
 int line_threads(int L);
 
+// Fused CG front (deferred x update, direction update, contraction, p.Kp,
+// N2 real-to-complex pass); returns the number of partials written.
+template <typename R>
+int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const KrylovScalars* ks, double* partials,
+                    long N, long nlines, const SpecTables<R>& tb, hipStream_t s);
+
 template <typename R>
 void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const int* skip,
                 hipStream_t s);

@@ -16,6 +16,7 @@
 #include "fg_launch.hpp"
 #include "fg_pointwise.hpp"
 #include "fg_scalar.hpp"
+#include "fg_cgfront.hpp"
 
 using namespace fg;
 
@@ -394,12 +395,10 @@ int next_chunk(const KrylovScalars& h, long launched) {
 // (they return at once); excluded from the profiled launch counts.
 void note_noop_iterations(fg_plan* P, long noop) {
   if (!P->prof_on || noop <= 0) return;
-  P->prof_noop[FG_PASS_CONTRACT] += noop;
-  P->prof_noop[FG_PASS_R2C] += noop;
+  P->prof_noop[FG_PASS_FRONT] += noop;
   P->prof_noop[FG_PASS_AXIS] += 2 * noop;
   P->prof_noop[FG_PASS_ZPROJ] += noop;
   P->prof_noop[FG_PASS_C2R] += noop;
-  P->prof_noop[FG_PASS_CG_UPDATE] += noop;
   P->prof_noop[FG_PASS_FINALIZE] += 2 * noop;
 }
 
@@ -422,33 +421,45 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
     FG_HIP(hipMemcpyAsync(&ks->tol2, P->hd + 62, sizeof(double), hipMemcpyHostToDevice, P->stream));
     FG_HIP(hipMemcpyAsync(&ks->maxit, P->hd + 63, sizeof(int), hipMemcpyHostToDevice, P->stream));
   }
-  const unsigned nbN = blocks_for(P->N);
-  const unsigned nbu = grid_stride_blocks(n9);
+  const SpecTables<T> tb = tabs<T>(P).spec();
   const int* skip = &ks->done;
   int chunk = 8;
   long launched = 0;
   for (int guard = 0; guard < 1000000; ++guard) {
     launched += chunk;
     for (int k = 0; k < chunk; ++k) {
+      // x += alpha_{k-1} p_{k-1}; p = r + beta p; Y = K:p; p.Y; N2 pass of Y
+      int nbf;
       {
-        ProfScope ps(P, FG_PASS_CONTRACT);
-        hipLaunchKernelGGL((k_contract<T>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, S, p, r, st, ks,
-                           P->N, 1);
+        ProfScope ps(P, FG_PASS_FRONT);
+        nbf = launch_cg_front<T>(P->M, S, p, x, r, st, ks, P->part, P->N, (long)P->n0 * P->n1, tb, P->stream);
       }
-      C2REpi epi{1.0, p, false, P->part, skip};
-      const int nb = project9<T>(P, S, S, S, epi);
+      {
+        ProfScope ps(P, FG_PASS_FINALIZE);  // alpha = r.r / p.Kp
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nbf, ks, (double*)nullptr, 0, 0);
+      }
+      {
+        ProfScope ps(P, FG_PASS_AXIS);
+        launch_axis<T>(P->n1, false, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0, 1, tb.tw1, skip, P->stream);
+      }
+      {
+        ProfScope ps(P, FG_PASS_ZPROJ);
+        launch_zproj<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip, P->stream);
+      }
+      {
+        ProfScope ps(P, FG_PASS_AXIS);
+        launch_axis<T>(P->n1, true, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0, 1, tb.tw1, skip, P->stream);
+      }
+      int nbc;
+      {
+        // r -= alpha G(K p), r.r
+        ProfScope ps(P, FG_PASS_C2R);
+        C2REpi epi{1.0, nullptr, true, P->part2, skip, r, ks};
+        nbc = launch_c2r<T>(P->M, S, S, 9L * P->n0 * P->n1, tb, epi, P->stream);
+      }
       {
         ProfScope ps(P, FG_PASS_FINALIZE);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, ks, (double*)nullptr, 0, 0);
-      }
-      {
-        ProfScope ps(P, FG_PASS_CG_UPDATE);
-        hipLaunchKernelGGL((k_cg_update<T>), dim3(nbu), dim3(256), 0, P->stream, x, r, p, S, ks, P->part2, n9);
-      }
-      {
-        ProfScope ps(P, FG_PASS_FINALIZE);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbu, ks, (double*)nullptr,
-                           1, 0);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, nbc, ks, (double*)nullptr, 1, 0);
       }
       check_launch();
     }
@@ -458,6 +469,9 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
   }
   const KrylovScalars& h = P->hks[0];
   note_noop_iterations(P, launched - h.iter);
+  // the last deferred solution update
+  hipLaunchKernelGGL((k_cg_final_x<T>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, x, p, ks, n9);
+  check_launch();
   if (stats) {
     stats->lin_iters_last = h.iter;
     stats->lin_relres = h.rr0 > 0 ? std::sqrt(h.rr / h.rr0) : 0.0;

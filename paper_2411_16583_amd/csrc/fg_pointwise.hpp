@@ -4,23 +4,9 @@
 // plane 3i+j holds the ij component (row-major tensor index).
 #pragma once
 #include "fg_fft.hpp"
+#include "fg_tangent.hpp"
 
 namespace fg {
-
-// Device-side scalars of one Krylov solve (FP64, in the workspace).
-struct KrylovScalars {
-  double rr;     // current r.r
-  double rr0;    // b.b
-  double rz;     // r.z (preconditioned solves)
-  double pAp;
-  double alpha;
-  double beta;
-  double tol2;   // tol^2 (0: run to maxit)
-  int iter;
-  int maxit;
-  int done;      // 1 when converged, broken down or out of iterations
-  int flag;      // 0 running/converged, 1 breakdown, 2 max iterations
-};
 
 constexpr int FG_FLAG_DOMAIN = 1;  // det F <= 0 or 1 + Omega c <= 0
 
@@ -97,28 +83,6 @@ k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, cons
     const double s = block_sum(pp, red);
     if (threadIdx.x == 0) pnorm_partials[blockIdx.x] = s;
   }
-}
-
-// K : X from the tangent state (in registers).
-template <typename T>
-__device__ __forceinline__ void tangent_apply(const T (&A)[9], T al, T be, T ga, const T (&X)[9], T (&Y)[9]) {
-  T tr = T(0);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) tr += A[k] * X[k];
-  // W = A X^T : W_ik = sum_l A_il X_kl
-  T W[9];
-#pragma unroll
-  for (int ii = 0; ii < 3; ++ii)
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-      W[3 * ii + kk] = A[3 * ii] * X[3 * kk] + A[3 * ii + 1] * X[3 * kk + 1] + A[3 * ii + 2] * X[3 * kk + 2];
-#pragma unroll
-  for (int ii = 0; ii < 3; ++ii)
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-      const T awa = W[3 * ii] * A[jj] + W[3 * ii + 1] * A[3 + jj] + W[3 * ii + 2] * A[6 + jj];
-      Y[3 * ii + jj] = al * X[3 * ii + jj] + be * tr * A[3 * ii + jj] + ga * awa;
-    }
 }
 
 // CG direction update fused with the tangent contraction:

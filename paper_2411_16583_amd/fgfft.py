@@ -27,7 +27,7 @@ EXPORTED = [
     "fg_apply_operator", "fg_project", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
     "fg_profile_begin", "fg_profile_end", "fg_status_string", "fg_last_error", "fg_plan_destroy",
 ]
-PASS_NAMES = ["contract", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive", "zscalar"]
+PASS_NAMES = ["front", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive", "zscalar"]
 
 
 class SolverOpts(ctypes.Structure):

@@ -43,36 +43,56 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
   const bool first = ks->iter == 0;
   const R alpha = (R)ks->alpha;
   const R beta = (R)ks->beta;
-  R* yb = reinterpret_cast<R*>(buf);
   double acc = 0.0;
-  // ---- phase A: pointwise
-  for (int v = tid; v < LB * N2; v += FS::THREADS) {
-    const int l = v / N2;
-    const int n = v % N2;
+  // ---- phase A: pointwise, two voxels per thread and step (2-vector loads)
+  using V = cplx<R>;
+  const long Nv = N / 2;
+  const V* rv = reinterpret_cast<const V*>(r);
+  const V* sv = reinterpret_cast<const V*>(st);
+  V* pv = reinterpret_cast<V*>(p);
+  V* xv = reinterpret_cast<V*>(x);
+  for (int v = tid; v < LB * M; v += FS::THREADS) {
+    const int l = v / M;
+    const int n = v % M;  // voxel pair (2n, 2n+1) of line l
     if (line0 + l >= nlines) continue;
-    const long g = (line0 + l) * N2 + n;
-    R X[9];
+    const long g = (line0 + l) * M + n;
+    V rk[9], po[9], A[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const R rk = r[k * N + g];
-      R pk = rk;
-      if (!first) {
-        const R po = p[k * N + g];
-        x[k * N + g] += alpha * po;
-        pk = rk + beta * po;
-      }
-      p[k * N + g] = pk;
-      X[k] = pk;
+      rk[k] = rv[k * Nv + g];
+      if (!first) po[k] = pv[k * Nv + g];
     }
-    R A[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) A[k] = st[k * N + g];
-    R Y[9];
-    tangent_apply<R>(A, st[9 * N + g], st[10 * N + g], st[11 * N + g], X, Y);
+    for (int k = 0; k < 9; ++k) A[k] = sv[k * Nv + g];
+    const V al = sv[9 * Nv + g], be = sv[10 * Nv + g], ga = sv[11 * Nv + g];
+    R X0[9], X1[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      acc += (double)X[k] * (double)Y[k];
-      yb[(k * LB + l) * (2 * FS::LSTRIDE) + n] = Y[k];
+      V pk = rk[k];
+      if (!first) {
+        V xo = xv[k * Nv + g];
+        xo.x += alpha * po[k].x;
+        xo.y += alpha * po[k].y;
+        xv[k * Nv + g] = xo;
+        pk.x = rk[k].x + beta * po[k].x;
+        pk.y = rk[k].y + beta * po[k].y;
+      }
+      pv[k * Nv + g] = pk;
+      X0[k] = pk.x;
+      X1[k] = pk.y;
+    }
+    R A0[9], A1[9], Y0[9], Y1[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      A0[k] = A[k].x;
+      A1[k] = A[k].y;
+    }
+    tangent_apply<R>(A0, al.x, be.x, ga.x, X0, Y0);
+    tangent_apply<R>(A1, al.y, be.y, ga.y, X1, Y1);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      acc += (double)X0[k] * (double)Y0[k] + (double)X1[k] * (double)Y1[k];
+      buf[(k * LB + l) * FS::LSTRIDE + n] = mk<C>(Y0[k], Y1[k]);
     }
   }
   __syncthreads();

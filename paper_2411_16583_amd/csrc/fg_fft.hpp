@@ -251,24 +251,27 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
   const bool active = line < nlines;
   const C* src = reinterpret_cast<const C*>(in) + line * M;
   C* my = lds + ll * (M + PAD);
+  // one global load per element; the mirror X[M - k] comes from LDS
   C v[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = active ? src[LS::idxA(t, e)] : mk<C>(R(0), R(0));
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) my[LS::idxA(t, e)] = v[e];
+  __syncthreads();
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
     const int k = LS::idxA(t, e);
-    C Z = mk<C>(R(0), R(0));
-    if (active) {
-      const C xk = src[k];
-      if (k == 0) {
-        Z = mk<C>(xk.x + xk.y, xk.x - xk.y);
-      } else {
-        const C xm = src[M - k];
-        const C s = cadd(xk, cconj(xm));
-        const C d = cmulc(csub(xk, cconj(xm)), tb.post[k]);  // * W^{-k}
-        Z = cadd(s, mul_pi(d));
-      }
+    const C xk = v[e];
+    if (k == 0) {
+      v[e] = mk<C>(xk.x + xk.y, xk.x - xk.y);
+    } else {
+      const C xm = my[M - k];
+      const C s = cadd(xk, cconj(xm));
+      const C d = cmulc(csub(xk, cconj(xm)), tb.post[k]);  // * W^{-k}
+      v[e] = cadd(s, mul_pi(d));
     }
-    v[e] = Z;
   }
+  __syncthreads();  // mirrors read before the exchange overwrites the buffer
   line_fft_AB<M, true>(v, my, 1, t, tb.twM);
   // v[e] = N2 * (x[2n] + i x[2n+1]) with n = idxB(t, e)
   C* dst = reinterpret_cast<C*>(out) + line * M;

@@ -379,77 +379,6 @@ template <typename R> constexpr size_t zpass_extra_lds(int L) {
   return (size_t)L * sizeof(cplx<R>) + 2 * (size_t)L * sizeof(R);
 }
 
-template <typename R, int L>
-__global__ void __launch_bounds__(256)
-k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, const int* skip) {
-  using C = cplx<R>;
-  using LS = Line<L>;
-  extern __shared__ char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  C* stw = lds + L * B;
-  R* scz = reinterpret_cast<R*>(stw + L);
-  R* ssz = scz + L;
-  if (skip && *skip) return;
-  for (int k = threadIdx.x; k < L; k += blockDim.x) {
-    stw[k] = tb.tw0[k];
-    scz[k] = tb.cz[k];
-    ssz[k] = tb.sz[k];
-  }
-  __syncthreads();
-  const int col = threadIdx.x % B;
-  const int t = threadIdx.x / B;
-  const int kx = blockIdx.x * B + col;
-  const int ky = blockIdx.y;
-  const int i = blockIdx.z;
-  const long plane = (long)N1 * M;
-  const long comp = (long)L * plane;
-  // (ky, kx) factors of the rotated vector: r = (sz cy cx, cz sy cx, cz cy sx)
-  const R cy = tb.cy[ky], sy = tb.sy[ky], cx = tb.cx[kx], sx = tb.sx[kx];
-  const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
-  C* base = reinterpret_cast<C*>(data) + (long)ky * M + kx;
-  C acc[LS::E];
-#pragma unroll
-  for (int e = 0; e < LS::E; ++e) acc[e] = mk<C>(R(0), R(0));
-#pragma unroll 1
-  for (int l = 0; l < 3; ++l) {
-    const C* src = base + (3 * i + l) * comp;
-    C v[LS::E];
-#pragma unroll
-    for (int e = 0; e < LS::E; ++e) v[e] = src[LS::idxA(t, e) * plane];
-    line_fft_AB<L, false>(v, lds + col, B, t, stw);
-#pragma unroll
-    for (int e = 0; e < LS::E; ++e) {
-      const int kz = LS::idxB(t, e);
-      const R rl = (l == 0) ? ssz[kz] * fx0 : scz[kz] * (l == 1 ? fx1 : fx2);
-      acc[e] = mk<C>(acc[e].x + v[e].x * rl, acc[e].y + v[e].y * rl);
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < LS::E; ++e) {
-    const int kz = LS::idxB(t, e);
-    const R a = ssz[kz] * fx0, b = scz[kz] * fx1, c = scz[kz] * fx2;
-    const R r2 = a * a + b * b + c * c;
-    const R f = (r2 > R(0)) ? scale / r2 : R(0);
-    acc[e] = cscale(acc[e], f);
-  }
-#pragma unroll 1
-  for (int j = 0; j < 3; ++j) {
-    C v[LS::E];
-#pragma unroll
-    for (int e = 0; e < LS::E; ++e) {
-      const int kz = LS::idxB(t, e);
-      const R rj = (j == 0) ? ssz[kz] * fx0 : scz[kz] * (j == 1 ? fx1 : fx2);
-      v[e] = cscale(acc[e], rj);
-    }
-    line_ifft_BA<L>(v, lds + col, B, t, stw);
-    if (kx != 0) {
-      C* dst = base + (3 * i + j) * comp;
-#pragma unroll
-      for (int e = 0; e < LS::E; ++e) dst[LS::idxA(t, e) * plane] = v[e];
-    }
-  }
-}
-
 // Scalar symbol variant (preconditioners of Alg. 2 / Alg. 3):
 //   Z = A * scale / (a0 + a1 lambda(q)),  lambda = sum_j (2/h_j)^2 sin^2(q_j/2).
 template <typename R>

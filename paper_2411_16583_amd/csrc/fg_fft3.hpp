@@ -1,0 +1,234 @@
+// Three-stage line FFT (L = R1 R2 R3) with more threads per line and fewer
+// elements per thread than the two-stage version; used by the N0 pass fused
+// with the projection, whose per-thread accumulator would otherwise double
+// the register footprint.
+//
+// Forward, with Q = R2 R3:
+//   stage 1: butterfly b in [0, Q):        x[b + Q n1]            -> Y1[b][k1]  * W_L^{b k1}
+//   stage 2: butterfly (k1, b2):            Y1[b2 + R3 n2][k1]     -> Y2[k1][b2][k2] * W_Q^{b2 k2}
+//   stage 3: butterfly (k1, k2):            Y2[k1][b2][k2] over b2 -> X[k1 + R1 (k2 + R2 k3)]
+// Layout A (natural): thread t holds x[(t + T u) + Q n1], e = u R1 + n1.
+// Layout B (spectral): thread t holds X[k1 + R1 (k2 + R2 k3)] with
+// (k1, k2) = (g % R1, g / R1), g = t + T z, e = z R3 + k3.
+// The inverse runs the stages backwards with conjugate twiddles (B -> A).
+#pragma once
+#include "fg_fft.hpp"
+
+namespace fg {
+
+template <int L> struct Line3Shape;
+template <> struct Line3Shape<256> {
+  static constexpr int R1 = 8, R2 = 8, R3 = 4, T = 32;
+};
+template <> struct Line3Shape<128> {
+  static constexpr int R1 = 4, R2 = 4, R3 = 8, T = 16;
+};
+
+template <int L> struct Line3 {
+  static constexpr int R1 = Line3Shape<L>::R1, R2 = Line3Shape<L>::R2, R3 = Line3Shape<L>::R3;
+  static constexpr int T = Line3Shape<L>::T;
+  static constexpr int Q = R2 * R3;
+  static constexpr int U1 = Q / T, U2 = R1 * R3 / T, U3 = R1 * R2 / T;
+  static constexpr int E = L / T;
+  static_assert(U1 * T == Q && U2 * T == R1 * R3 && U3 * T == R1 * R2, "thread split");
+  static_assert(U1 * R1 == E && U2 * R2 == E && U3 * R3 == E, "element split");
+  __device__ __forceinline__ static int idxA(int t, int e) { return t + T * (e / R1) + Q * (e % R1); }
+  __device__ __forceinline__ static int idxB(int t, int e) {
+    const int g = t + T * (e / R3);
+    return (g % R1) + R1 * ((g / R1) + R2 * (e % R3));
+  }
+  // LDS positions of the intermediate arrays
+  __device__ __forceinline__ static int pos1(int b, int k1) { return b * R1 + k1; }
+  __device__ __forceinline__ static int pos2(int k1, int b2, int k2) { return (k2 * R3 + b2) * R1 + k1; }
+
+  template <bool INV, typename C>
+  __device__ __forceinline__ static void fwd(C (&v)[E], C* lds, int ls, int t, const C* tw) {
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int b = t + T * u;
+      Dft<R1, 1, INV, C>::run(v + u * R1);
+#pragma unroll
+      for (int k1 = 1; k1 < R1; ++k1) v[u * R1 + k1] = twiddle_tab<INV>(v[u * R1 + k1], tw, (b * k1) % L);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) lds[pos1(b, k1) * ls] = v[u * R1 + k1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < U2; ++w) {
+      const int g = t + T * w;
+      const int k1 = g % R1, b2 = g / R1;
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) v[w * R2 + n2] = lds[pos1(b2 + R3 * n2, k1) * ls];
+      Dft<R2, 1, INV, C>::run(v + w * R2);
+#pragma unroll
+      for (int k2 = 1; k2 < R2; ++k2) v[w * R2 + k2] = twiddle_tab<INV>(v[w * R2 + k2], tw, (R1 * b2 * k2) % L);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < U2; ++w) {
+      const int g = t + T * w;
+      const int k1 = g % R1, b2 = g / R1;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) lds[pos2(k1, b2, k2) * ls] = v[w * R2 + k2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int z = 0; z < U3; ++z) {
+      const int g = t + T * z;
+      const int k1 = g % R1, k2 = g / R1;
+#pragma unroll
+      for (int b2 = 0; b2 < R3; ++b2) v[z * R3 + b2] = lds[pos2(k1, b2, k2) * ls];
+      Dft<R3, 1, INV, C>::run(v + z * R3);
+    }
+    __syncthreads();
+  }
+
+  template <typename C>
+  __device__ __forceinline__ static void inv(C (&v)[E], C* lds, int ls, int t, const C* tw) {
+#pragma unroll
+    for (int z = 0; z < U3; ++z) {
+      const int g = t + T * z;
+      const int k1 = g % R1, k2 = g / R1;
+      Dft<R3, 1, true, C>::run(v + z * R3);  // over k3 -> b2
+#pragma unroll
+      for (int b2 = 0; b2 < R3; ++b2) {
+        C a = v[z * R3 + b2];
+        if (b2 != 0 && k2 != 0) a = twiddle_tab<true>(a, tw, (R1 * b2 * k2) % L);
+        lds[pos2(k1, b2, k2) * ls] = a;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < U2; ++w) {
+      const int g = t + T * w;
+      const int k1 = g % R1, b2 = g / R1;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[w * R2 + k2] = lds[pos2(k1, b2, k2) * ls];
+      Dft<R2, 1, true, C>::run(v + w * R2);  // over k2 -> n2
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < U2; ++w) {
+      const int g = t + T * w;
+      const int k1 = g % R1, b2 = g / R1;
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) {
+        const int b = b2 + R3 * n2;
+        C a = v[w * R2 + n2];
+        if (k1 != 0) a = twiddle_tab<true>(a, tw, (b * k1) % L);
+        lds[pos1(b, k1) * ls] = a;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int b = t + T * u;
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) v[u * R1 + k1] = lds[pos1(b, k1) * ls];
+      Dft<R1, 1, true, C>::run(v + u * R1);  // over k1 -> n1
+    }
+    __syncthreads();
+  }
+};
+
+// The two-stage transform behind the same interface.
+template <int L> struct Line2Ops {
+  using LS = Line<L>;
+  static constexpr int T = LS::T, E = LS::E;
+  __device__ __forceinline__ static int idxA(int t, int e) { return LS::idxA(t, e); }
+  __device__ __forceinline__ static int idxB(int t, int e) { return LS::idxB(t, e); }
+  template <bool INV, typename C>
+  __device__ __forceinline__ static void fwd(C (&v)[E], C* lds, int ls, int t, const C* tw) {
+    line_fft_AB<L, INV>(v, lds, ls, t, tw);
+  }
+  template <typename C>
+  __device__ __forceinline__ static void inv(C (&v)[E], C* lds, int ls, int t, const C* tw) {
+    line_ifft_BA<L>(v, lds, ls, t, tw);
+  }
+};
+
+// Line transform used by the fused N0 passes.
+template <int L> struct ZLineSel {
+  using type = Line2Ops<L>;
+};
+template <> struct ZLineSel<256> {
+  using type = Line3<256>;
+};
+template <> struct ZLineSel<128> {
+  using type = Line3<128>;
+};
+template <int L> using ZLine = typename ZLineSel<L>::type;
+
+template <typename R, int L>
+__global__ void __launch_bounds__(256)
+k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, const int* skip) {
+  using C = cplx<R>;
+  using LS = ZLine<L>;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C* stw = lds + L * B;
+  R* scz = reinterpret_cast<R*>(stw + L);
+  R* ssz = scz + L;
+  if (skip && *skip) return;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    stw[k] = tb.tw0[k];
+    scz[k] = tb.cz[k];
+    ssz[k] = tb.sz[k];
+  }
+  __syncthreads();
+  const int col = threadIdx.x % B;
+  const int t = threadIdx.x / B;
+  const int kx = blockIdx.x * B + col;
+  const int ky = blockIdx.y;
+  const int i = blockIdx.z;
+  const long plane = (long)N1 * M;
+  const long comp = (long)L * plane;
+  // (ky, kx) factors of the rotated vector: r = (sz cy cx, cz sy cx, cz cy sx)
+  const R cy = tb.cy[ky], sy = tb.sy[ky], cx = tb.cx[kx], sx = tb.sx[kx];
+  const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
+  C* base = reinterpret_cast<C*>(data) + (long)ky * M + kx;
+  C acc[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) acc[e] = mk<C>(R(0), R(0));
+#pragma unroll 1
+  for (int l = 0; l < 3; ++l) {
+    const C* src = base + (3 * i + l) * comp;
+    C v[LS::E];
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) v[e] = src[LS::idxA(t, e) * plane];
+    LS::template fwd<false>(v, lds + col, B, t, stw);
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const int kz = LS::idxB(t, e);
+      const R rl = (l == 0) ? ssz[kz] * fx0 : scz[kz] * (l == 1 ? fx1 : fx2);
+      acc[e] = mk<C>(acc[e].x + v[e].x * rl, acc[e].y + v[e].y * rl);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const int kz = LS::idxB(t, e);
+    const R a = ssz[kz] * fx0, b = scz[kz] * fx1, c = scz[kz] * fx2;
+    const R r2 = a * a + b * b + c * c;
+    const R f = (r2 > R(0)) ? scale / r2 : R(0);
+    acc[e] = cscale(acc[e], f);
+  }
+#pragma unroll 1
+  for (int j = 0; j < 3; ++j) {
+    C v[LS::E];
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const int kz = LS::idxB(t, e);
+      const R rj = (j == 0) ? ssz[kz] * fx0 : scz[kz] * (j == 1 ? fx1 : fx2);
+      v[e] = cscale(acc[e], rj);
+    }
+    LS::inv(v, lds + col, B, t, stw);
+    if (kx != 0) {
+      C* dst = base + (3 * i + j) * comp;
+#pragma unroll
+      for (int e = 0; e < LS::E; ++e) dst[LS::idxA(t, e) * plane] = v[e];
+    }
+  }
+}
+
+
+}  // namespace fg

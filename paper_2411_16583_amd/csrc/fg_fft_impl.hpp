@@ -4,6 +4,7 @@
 #include <stdexcept>
 
 #include "fg_cgfront.hpp"
+#include "fg_fft3.hpp"
 #include "fg_launch.hpp"
 
 namespace fg {
@@ -73,8 +74,8 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 template <typename R>
 void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const int* skip,
                   hipStream_t s) {
-  const int B = column_tile(N0, M, (int)sizeof(cplx<R>));
-  const int T = line_threads(N0);
+  const int T = zline_threads(N0);
+  const int B = column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
   const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zpass_extra_lds<R>(N0);
   dim3 grid((unsigned)(M / B), (unsigned)N1, 3);
   dim3 gdc((unsigned)(N1 / 2 + 1), 3, 1);

@@ -13,7 +13,9 @@ bool fft_axis_length_supported(int L);  // N0, N1
 // Largest power-of-two column tile dividing M with T * B <= 256 threads and
 // an exchange buffer of L * B complex values within 64 KiB.
 int column_tile(int L, int M, int elem_bytes);
+int column_tile_t(int T, int L, int M, int elem_bytes);
 int line_threads(int L);
+int zline_threads(int L);  // threads per line of the fused N0 projection pass
 
 // Fused CG front (deferred x update, direction update, contraction, p.Kp,
 // N2 real-to-complex pass); returns the number of partials written.

@@ -17,6 +17,7 @@
 #include "fg_pointwise.hpp"
 #include "fg_scalar.hpp"
 #include "fg_cgfront.hpp"
+#include "fg_fft3.hpp"
 
 using namespace fg;
 
@@ -46,11 +47,18 @@ int line_threads(int L) {
   }
 }
 
-int column_tile(int L, int M, int elem_bytes) {
-  const int T = line_threads(L);
+int column_tile_t(int T, int L, int M, int elem_bytes) {
   int B = 1;
   while ((M % (2 * B)) == 0 && T * 2 * B <= 256 && (long)L * 2 * B * elem_bytes <= 65536) B *= 2;
   return B;
+}
+
+int column_tile(int L, int M, int elem_bytes) { return column_tile_t(line_threads(L), L, M, elem_bytes); }
+
+int zline_threads(int L) {
+  if (L == 256) return Line3<256>::T;
+  if (L == 128) return Line3<128>::T;
+  return line_threads(L);
 }
 
 }  // namespace fg

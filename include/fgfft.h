@@ -130,6 +130,18 @@ fg_status fg_newton_solve(fg_plan* plan, const double F_macro[9], const fg_solve
  * fg_newton_solve performs the same update itself. */
 fg_status fg_apply_macro(fg_plan* plan, const double F_macro[9]);
 
+/* Adjoint sensitivity of L = sum_ij w_ij <P_ij> at the current, converged
+ * state (eq. (30) differentiated; see the derivation in the design doc): solves
+ * G*(K : lam) = -G*(K : W) (W the uniform field w = dL_dPavg, host, 9
+ * doubles) by CG with opts->tol_lin, then writes
+ *   dL_dlogE[x]  = (W + lam(x)) : P(x) / N,
+ *   dL_dOmega[x] = (W + lam(x)) : dP/dOmega(x) / N
+ * (device, N doubles each, either may be NULL).  FG_FP64 plans only
+ * (FG_E_ARG otherwise).  stats: lin_iters_last, lin_relres.  Errors:
+ * FG_E_STATE, FG_E_NOCONV, FG_E_BREAKDOWN, FG_E_DOMAIN, FG_E_HIP. */
+fg_status fg_adjoint_gradient(fg_plan* plan, const double dL_dPavg[9], double* dL_dlogE, double* dL_dOmega,
+                              const fg_solver_opts* opts, fg_stats* stats);
+
 /* Equilibrium residual of the current state (eq. (31)) with respect to the
  * macroscopic F_macro (host, 9 doubles): *err_res (host).  Synchronises. */
 fg_status fg_residual(fg_plan* plan, const double F_macro[9], double* err_res);

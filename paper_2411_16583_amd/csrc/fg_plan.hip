@@ -576,6 +576,48 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
   }
 }
 
+// Adjoint of L = sum W_ij <P_ij> at the current (converged) state: solve
+// G(K:lam) = -G(K:W) for the compatible, zero-mean lam with the same CG, then
+// the per-voxel gradients with respect to log E and Omega.
+template <typename T>
+void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_solver_opts* o, fg_stats* stats) {
+  const long N = P->N, n9 = 9 * N;
+  T* S = (T*)P->S;
+  T* pbuf = (T*)P->p;
+  constitutive(P, nullptr, nullptr, P->st, nullptr);
+  FG_HIP(hipMemcpyAsync(P->Fu, W, 9 * sizeof(double), hipMemcpyHostToDevice, P->stream));
+  hipLaunchKernelGGL((k_fill_uniform9<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, pbuf, (const double*)P->Fu,
+                     N);
+  hipLaunchKernelGGL((k_contract<T>), dim3(blocks_for(N / 2)), dim3(256), 0, P->stream, S, pbuf, (const T*)nullptr,
+                     (const T*)P->st, (const KrylovScalars*)nullptr, N, 0);
+  check_launch();
+  {
+    // b = -G*(G*(K:W)): the second projection keeps the right-hand side
+    // compatible to rounding (as for the Newton right-hand side)
+    C2REpi e1{1.0, nullptr, true, nullptr, nullptr};
+    project9<T>(P, S, S, S, e1);
+    C2REpi e2{-1.0, nullptr, true, P->part, nullptr};
+    const int nb = project9<T>(P, S, S, S, e2);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
+    FG_HIP(hipMemcpyAsync(P->r, S, n9 * sizeof(T), hipMemcpyDeviceToDevice, P->stream));
+    check_launch();
+  }
+  sync_read(P);
+  check_domain(P);
+  if (!P->hks[0].done) {
+    cg_solve<T>(P, o, stats);
+  } else {
+    hipLaunchKernelGGL((k_fill<T>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, (T*)P->x, T(0), n9);
+  }
+  const double* c = P->c ? P->c : P->zeroN;
+  const double* d = P->d ? P->d : P->zeroN;
+  hipLaunchKernelGGL((k_adjoint_grad<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu,
+                     P->Om, (const T*)P->x, (const double*)P->Fu, gE, gO, P->flags, N);
+  check_launch();
+  sync_read(P);
+  check_domain(P);
+}
+
 // ----------------------------------------------------------------------------
 // Scalar PCG (shared by the phase-field and Fick solves).  Vectors in the
 // scalar area: x, r, z, p, q, work (spectral).  ks[1] holds the scalars; the
@@ -891,6 +933,19 @@ fg_status fg_newton_solve(fg_plan* P, const double F_macro[9], const fg_solver_o
     if (stats) std::memset(stats, 0, sizeof(fg_stats));
     apply_macro(P, F_macro);
     newton(P, F_macro, opts, stats);
+    FG_HIP(hipStreamSynchronize(P->stream));
+  });
+}
+
+fg_status fg_adjoint_gradient(fg_plan* P, const double dL_dPavg[9], double* dL_dlogE, double* dL_dOmega,
+                              const fg_solver_opts* opts, fg_stats* stats) {
+  if (!P || !dL_dPavg || !opts) return FG_E_ARG;
+  if (!dL_dlogE && !dL_dOmega) return FG_E_ARG;
+  return run(P, [&]() {
+    need_ready(P, true);
+    if (P->prec != FG_FP64) throw Status(FG_E_ARG, "the adjoint is built for FG_FP64 plans");
+    if (stats) std::memset(stats, 0, sizeof(fg_stats));
+    adjoint<double>(P, dL_dPavg, dL_dlogE, dL_dOmega, opts, stats);
     FG_HIP(hipStreamSynchronize(P->stream));
   });
 }

@@ -315,6 +315,71 @@ __global__ void __launch_bounds__(256) k_fill(T* __restrict__ dst, T v, long n) 
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = v;
 }
 
+// Uniform 3x3 tensor field: dst plane k = w[k] (w: 9 doubles, device).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_uniform9(T* __restrict__ dst, const double* __restrict__ w, long N) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dst[k * N + i] = (T)w[k];
+}
+
+// Adjoint gradient (derived from eq. (30); L = sum_ij W_ij <P_ij>):
+//   dL/dlogE(x) = (W + lam(x)) : P(x) / N,
+//   dL/dOmega(x) = (W + lam(x)) : dP/dOmega(x) / N,
+// dP/dlogE = P (both Lame constants scale with E) and
+//   dP/dOmega = g [ -(2/3) G c (1 + Omega c)^{-5/3} F - lambda c / (1 + Omega c) F^-T ].
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_adjoint_grad(const double* __restrict__ F, const double* __restrict__ c, const double* __restrict__ d,
+               const double* __restrict__ E, const double* __restrict__ nu, const double* __restrict__ Om,
+               const T* __restrict__ lam, const double* __restrict__ W, double* __restrict__ gE,
+               double* __restrict__ gO, int* __restrict__ flags, long N) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double f[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) f[k] = F[k * N + i];
+  double cof[9];
+  cof[0] = f[4] * f[8] - f[5] * f[7];
+  cof[1] = f[5] * f[6] - f[3] * f[8];
+  cof[2] = f[3] * f[7] - f[4] * f[6];
+  cof[3] = f[2] * f[7] - f[1] * f[8];
+  cof[4] = f[0] * f[8] - f[2] * f[6];
+  cof[5] = f[1] * f[6] - f[0] * f[7];
+  cof[6] = f[1] * f[5] - f[2] * f[4];
+  cof[7] = f[2] * f[3] - f[0] * f[5];
+  cof[8] = f[0] * f[4] - f[1] * f[3];
+  double J = f[0] * cof[0] + f[1] * cof[1] + f[2] * cof[2];
+  const double cc = c[i], dd = d[i], EE = E[i], nn = nu[i], oo = Om[i];
+  const double a = 1.0 + oo * cc;
+  if (!(J > 0.0) || !(a > 0.0)) {
+    flags[0] = FG_FLAG_DOMAIN;
+    J = 1.0;
+  }
+  const double G = EE / (2.0 * (1.0 + nn));
+  const double lm = EE * nn / ((1.0 + nn) * (1.0 - 2.0 * nn));
+  const double g = (1.0 - dd) * (1.0 - dd);
+  const double la = log(a > 0.0 ? a : 1.0);
+  const double s2inv = exp(-2.0 / 3.0 * la);
+  const double lnJe = log(J) - la;
+  const double iJ = 1.0 / J;
+  const double c1 = g * G * s2inv, c2 = g * (lm * lnJe - G);
+  const double o1 = -g * (2.0 / 3.0) * G * cc * s2inv / (a > 0.0 ? a : 1.0);  // (1+Oc)^{-5/3}
+  const double o2 = -g * lm * cc / (a > 0.0 ? a : 1.0);
+  double sE = 0.0, sO = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double A = cof[k] * iJ;
+    const double w = W[k] + (double)lam[k * N + i];
+    sE += w * (c1 * f[k] + c2 * A);
+    sO += w * (o1 * f[k] + o2 * A);
+  }
+  const double invN = 1.0 / (double)N;
+  if (gE) gE[i] = sE * invN;
+  if (gO) gO[i] = sO * invN;
+}
+
 // Per-block partial sums of the 9 components of a tensor field (for <P>).
 __global__ void __launch_bounds__(256) k_mean9_partials(const double* __restrict__ P, double* __restrict__ partials,
                                                         long N) {

@@ -23,7 +23,7 @@ PRECISIONS = {"fp64": FG_FP64, "mixed": FG_MIXED}
 # Every function declared in include/fgfft.h.
 EXPORTED = [
     "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
-    "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_residual", "fg_homogenized_stress", "fg_stress",
+    "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_adjoint_gradient", "fg_residual", "fg_homogenized_stress", "fg_stress",
     "fg_apply_operator", "fg_project", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
     "fg_profile_begin", "fg_profile_end", "fg_status_string", "fg_last_error", "fg_plan_destroy",
 ]
@@ -93,6 +93,8 @@ def load_library(path=LIB_PATH):
         "fg_set_state": ([vp, dptr, dptr, dptr, dptr], c_int),
         "fg_apply_macro": ([vp, ctypes.POINTER(c_double)], c_int),
         "fg_newton_solve": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
+        "fg_adjoint_gradient": ([vp, ctypes.POINTER(c_double), dptr, dptr, ctypes.POINTER(SolverOpts),
+                                 ctypes.POINTER(Stats)], c_int),
         "fg_residual": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
         "fg_homogenized_stress": ([vp, ctypes.POINTER(c_double)], c_int),
         "fg_stress": ([vp, dptr], c_int),
@@ -202,6 +204,16 @@ class Plan:
         d = stats.to_dict()
         d["status"] = st
         return d
+
+    def adjoint_gradient(self, dL_dPavg, g_logE=None, g_Omega=None, opts=None):
+        """Per-voxel d L / d log E and d L / d Omega of L = sum w_ij <P_ij> into
+        the given device tensors (N doubles each)."""
+        opts = opts or make_opts()
+        a, p = _mat9(dL_dPavg)
+        stats = Stats()
+        self._check(self.lib.fg_adjoint_gradient(self.handle, p, _ptr(g_logE), _ptr(g_Omega), ctypes.byref(opts),
+                                                 ctypes.byref(stats)), "fg_adjoint_gradient")
+        return stats.to_dict()
 
     def apply_macro(self, F_macro):
         a, p = _mat9(F_macro)

@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 9 N doubles device-to-device 3 times (a plain copy kernel of known size, "
+                         "for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -168,6 +171,16 @@ def main():
     N = int(np.prod(work["shape"]))
     print(f"workload polydisperse {work['shape']} built in {time.perf_counter() - t0:.1f} s, "
           f"inclusion fraction {work['phase'].mean():.3f}", flush=True)
+    if args.copy_calibration:
+        import torch
+
+        a = torch.ones(9 * N, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copy calibration: 3 copies of {9 * N * 8} bytes", flush=True)
+        del a, b
     forms = args.forms.split(",")
     res = {}
     errors = {}

@@ -103,6 +103,24 @@ def run_form(work, form, steps, warmup):
     return dict(elapsed=elapsed, cg_iters=cg_iters, newton_iters=newton_iters, prof=prof, P11=float(Pm[0, 0]))
 
 
+def measured_traffic(kernel, word_bytes):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (profiles/*_traffic.json), or None when the kernel's
+    sources changed since those counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "front_polydisperse256_fp64_traffic.json")
+    if kernel != "front" or word_bytes != 8 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def roofline(res, N, word_bytes):
     prof = res["prof"]
     cands = {k: prof[k] for k in WORDS_PER_VOXEL if prof[k][1] > 0}
@@ -111,8 +129,9 @@ def roofline(res, N, word_bytes):
     avg_s = ms / 1e3 / launches
     bytes_per_launch = WORDS_PER_VOXEL[name] * word_bytes * N
     achieved = bytes_per_launch / avg_s / 1e9
+    traffic = measured_traffic(name, word_bytes) if N == 256 ** 3 else None
     return dict(kernel=name, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 avg_launch_us=round(avg_s * 1e6, 2), launches=launches,
                 bytes_per_launch=bytes_per_launch,
                 breakdown_ms={k: round(v[0], 2) for k, v in prof.items()})

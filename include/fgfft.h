@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct fg_plan fg_plan;
+typedef struct fg_batch fg_batch;
 
 typedef enum {
   FG_OK = 0,
@@ -192,6 +193,51 @@ fg_status pff_solve(fg_plan* plan, const fg_solver_opts* opts, fg_stats* stats);
  * FG_E_BREAKDOWN, FG_E_HIP. */
 fg_status fick_step(fg_plan* plan, double dt, const double* cdot_B, const fg_solver_opts* opts,
                     fg_stats* stats);
+
+/* ---------------------------------------------------------------------
+ * Batched form of Alg. 1: n_rve RVEs (each with its own grid, spacing and
+ * material) times n_cases macroscopic load cases, every (RVE, case) pair an
+ * independent Newton solve started from the undeformed reference state with
+ * F = F_macro[case] uniform.  Items of one grid share every kernel launch
+ * (item-major fields, converged items masked on the device); each grid runs
+ * on a stream of its own, forked from and joined into a batch stream that
+ * the library creates (default priority).  With graph_ticks > 0 the solve
+ * replays one captured hipGraph holding graph_ticks steps of every item (a
+ * step is one CG iteration, or the Newton update, residual test and new
+ * right-hand side once the item's CG has ended); the host reads one counter
+ * per group between replays.  With graph_ticks = 0 the same steps are
+ * launched directly, 8 per read-back; both give identical results.
+ * Pure mechanics: d = 0, the chemistry enters only through a fixed c. */
+
+/* grids: 3 ints per RVE, spacings: 3 doubles per RVE (host).  stream: the
+ * caller's stream, on which the inputs of fg_batch_set_material and the
+ * outputs are ordered.  Errors: FG_E_ARG, FG_E_SIZE, FG_E_HIP. */
+fg_status fg_batch_create(int n_rve, const int* grids, const double* spacings, int n_cases, fg_precision prec,
+                          void* stream, fg_batch** out);
+/* Device workspace bytes (all groups: plans, item-major material copies,
+ * F of every item, control blocks), and the number of grid groups. */
+size_t fg_batch_workspace_bytes(const fg_batch* batch);
+int fg_batch_groups(const fg_batch* batch);
+/* Caller-owned, 256-byte aligned device buffer of at least
+ * fg_batch_workspace_bytes.  Synchronises.  Errors: FG_E_ARG, FG_E_SIZE. */
+fg_status fg_batch_set_workspace(fg_batch* batch, void* dev, size_t bytes);
+/* Material of RVE rve (device, N_rve doubles each; c may be NULL for c = 0):
+ * copied into the batch for each load case, so the caller's buffers may be
+ * reused on return.  Errors: FG_E_ARG, FG_E_STATE (no workspace). */
+fg_status fg_batch_set_material(fg_batch* batch, int rve, const double* E, const double* nu, const double* Omega,
+                                const double* c);
+/* Solve every item: F_macro host, 9 n_cases doubles (case-major); P_avg
+ * host, 9 n_rve n_cases doubles ((rve n_cases + case) 9 + ij), may be NULL;
+ * stats host, n_rve n_cases entries in the same order, may be NULL (the
+ * histories hold the first 32 Newton iterations).  Returns the status of
+ * the first failing item (FG_E_NOCONV, FG_E_BREAKDOWN, FG_E_DOMAIN) with its
+ * index in fg_batch_last_error; every item's outputs are written anyway. */
+fg_status fg_batch_newton_solve(fg_batch* batch, const double* F_macro, const fg_solver_opts* opts, int graph_ticks,
+                                double* P_avg, fg_stats* stats);
+/* Copy F of item (rve, lcase) into F (device, 9 N_rve doubles). */
+fg_status fg_batch_state(fg_batch* batch, int rve, int lcase, double* F);
+const char* fg_batch_last_error(const fg_batch* batch);
+void fg_batch_destroy(fg_batch* batch);
 
 /* Kernel classes timed by fg_profile_*: */
 enum {

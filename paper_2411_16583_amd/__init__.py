@@ -5,4 +5,4 @@ phase-field and Fick operators) is hand-written HIP in ``csrc/`` compiled
 into ``libfgfft.so``; ``fgfft`` is its ctypes binding and ``driver`` the
 staggered time-stepping loop built on the C ABI.
 """
-from .fgfft import FgError, Plan, load_library, make_opts  # noqa: F401
+from .fgfft import Batch, FgError, Plan, load_library, make_opts  # noqa: F401

@@ -28,7 +28,7 @@ template <int M> struct FrontShape {
 template <typename R, int M>
 __global__ void __launch_bounds__(FrontShape<M>::THREADS)
 k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* __restrict__ r,
-           const R* __restrict__ st, const KrylovScalars* __restrict__ ks, double* __restrict__ partials,
+           const R* __restrict__ st, const KrylovScalars* __restrict__ ksb, double* __restrict__ partials,
            long N, long nlines, SpecTables<R> tb) {
   using C = cplx<R>;
   using LS = Line<M>;
@@ -37,9 +37,19 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
   constexpr int LB = FS::LB;
   __shared__ C buf[9 * LB * FS::LSTRIDE];
   __shared__ double red[16];
+  // batch item of this workgroup (items are nlines lines of 9 components
+  // each, item-major; ceil(nlines / LB) workgroups per item)
+  const long bpi = (nlines + LB - 1) / LB;
+  const int item = (int)(blockIdx.x / bpi);
+  const KrylovScalars* ks = ksb + item;
   if (ks->done) return;
+  spec += (long)item * 9 * N;
+  p += (long)item * 9 * N;
+  x += (long)item * 9 * N;
+  r += (long)item * 9 * N;
+  st += (long)item * 12 * N;
   const int tid = threadIdx.x;
-  const long line0 = (long)blockIdx.x * LB;
+  const long line0 = ((long)blockIdx.x - (long)item * bpi) * LB;
   const bool first = ks->iter == 0;
   const R alpha = (R)ks->alpha;
   const R beta = (R)ks->beta;
@@ -137,8 +147,12 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_cg_final_x(T* __restrict__ x, const T* __restrict__ p, const KrylovScalars* __restrict__ ks, long n) {
-  if (ks->flag == 1 || ks->iter == 0) return;
-  const T alpha = (T)ks->alpha;
+  // grid.y = batch item, n = values per item
+  const KrylovScalars* k = ks + blockIdx.y;
+  if (k->flag == 1 || k->iter == 0) return;
+  const T alpha = (T)k->alpha;
+  x += (long)blockIdx.y * n;
+  p += (long)blockIdx.y * n;
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] += alpha * p[i];
 }

@@ -38,6 +38,64 @@ struct KrylovScalars {
   int flag;      // 0 running/converged, 1 breakdown, 2 max iterations
 };
 
+// Which batch item a workgroup belongs to and whether that item is masked
+// off; workgroups of masked items return at once.  The mask is one int word
+// per item (nonzero: skip), either the done flag of the item's Krylov
+// scalars or a separate per-item flag array.  A plan is a batch of one item.
+struct Skip {
+  const int* gate = nullptr;  // nullptr: never skip
+  int stride = 0;             // ints between the words of consecutive items
+  long per_item = 1L << 62;   // grid units (lines, planes or rows) per item
+  __host__ __device__ int item(long unit) const { return (int)(unit / per_item); }
+  __device__ __forceinline__ bool operator()(long unit) const {
+    return gate && gate[(long)item(unit) * stride] != 0;
+  }
+  // skip items whose Krylov solve is done
+  static Skip done(const KrylovScalars* ks, long per_item = 1L << 62) {
+    Skip s;
+    s.gate = &ks->done;
+    s.stride = (int)(sizeof(KrylovScalars) / sizeof(int));
+    s.per_item = per_item;
+    return s;
+  }
+  // skip items with flags[b] != 0
+  static Skip flags(const int* f, long per_item = 1L << 62) {
+    Skip s;
+    s.gate = f;
+    s.stride = 1;
+    s.per_item = per_item;
+    return s;
+  }
+  Skip unit(long per) const {
+    Skip s = *this;
+    s.per_item = per;
+    return s;
+  }
+  __device__ __forceinline__ bool masked(int item) const { return gate && gate[(long)item * stride] != 0; }
+  // Workgroups of lpb lines over nlines lines (per_item lines per item) that
+  // never straddle two items: ceil(lines per item / lpb) workgroups per item.
+  __host__ __device__ long item_lines(long nlines) const { return per_item < nlines ? per_item : nlines; }
+  __host__ __device__ long line_blocks(long nlines, int lpb) const {
+    const long lpi = item_lines(nlines);
+    return (nlines / lpi) * ((lpi + lpb - 1) / lpb);
+  }
+};
+
+// Line of thread row ll of this workgroup under the item-aligned split.
+struct LineMap {
+  long line;    // global line index
+  bool active;  // inside its item
+  int item;
+};
+__device__ __forceinline__ LineMap map_line(const Skip& sk, long nlines, int lpb, int ll) {
+  const long lpi = sk.item_lines(nlines);
+  const long bpi = (lpi + lpb - 1) / lpb;
+  const long it = (long)blockIdx.x / bpi;
+  const long lin = ((long)blockIdx.x - it * bpi) * lpb + ll;
+  return LineMap{it * lpi + lin, lin < lpi, (int)it};
+}
+static_assert(sizeof(KrylovScalars) % sizeof(int) == 0, "gate stride");
+
 template <int L> struct LineShape;
 #define FG_LINE_SHAPE(L_, R1_, R2_) \
   template <> struct LineShape<L_> { static constexpr int R1 = R1_, R2 = R2_; };
@@ -181,17 +239,18 @@ constexpr int XBLOCK = 128;
 
 template <typename R, int M>
 __global__ void __launch_bounds__(XBLOCK)
-k_fft_x_r2c(const R* in, R* out, long nlines, SpecTables<R> tb, const int* skip) {
+k_fft_x_r2c(const R* in, R* out, long nlines, SpecTables<R> tb, Skip skip) {
   using C = cplx<R>;
   using LS = Line<M>;
   constexpr int LPB = XBLOCK / LS::T;
   constexpr int PAD = (M >= 16) ? 1 : 0;
   __shared__ C lds[LPB * (M + PAD)];
-  if (skip && *skip) return;
   const int t = threadIdx.x % LS::T;
   const int ll = threadIdx.x / LS::T;
-  const long line = (long)blockIdx.x * LPB + ll;
-  const bool active = line < nlines;
+  const LineMap lm = map_line(skip, nlines, LPB, ll);
+  if (skip.masked(lm.item)) return;
+  const long line = lm.line;
+  const bool active = lm.active;
   const C* src = reinterpret_cast<const C*>(in) + line * M;
   C* dst = reinterpret_cast<C*>(out) + line * M;
   C* my = lds + ll * (M + PAD);
@@ -228,9 +287,10 @@ struct C2REpi {
   const void* dotv;  // same type R as the output, or nullptr
   bool self_dot;     // sum y*y
   double* partials;  // nullptr: no reduction
-  const int* skip;   // nullptr or device flag
-  // CG residual update instead of a store: rupd <- rupd - alpha * y with
-  // alpha = ks->alpha, partial sums of the new rupd . rupd (out unused).
+  Skip skip;         // per-item early exit (units: lines)
+  // CG residual update instead of a store: rupd <- rupd - alpha * y with the
+  // item's alpha (ks[item].alpha), partial sums of the new rupd . rupd
+  // (out unused).
   void* rupd = nullptr;
   const KrylovScalars* ks = nullptr;
 };
@@ -244,11 +304,12 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
   constexpr int PAD = (M >= 16) ? 1 : 0;
   __shared__ C lds[LPB * (M + PAD)];
   __shared__ double red[16];
-  if (epi.skip && *epi.skip) return;
   const int t = threadIdx.x % LS::T;
   const int ll = threadIdx.x / LS::T;
-  const long line = (long)blockIdx.x * LPB + ll;
-  const bool active = line < nlines;
+  const LineMap lm = map_line(epi.skip, nlines, LPB, ll);
+  if (epi.skip.masked(lm.item)) return;
+  const long line = lm.line;
+  const bool active = lm.active;
   const C* src = reinterpret_cast<const C*>(in) + line * M;
   C* my = lds + ll * (M + PAD);
   // one global load per element; the mirror X[M - k] comes from LDS
@@ -280,7 +341,7 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
   double acc = 0.0;
   if (epi.rupd) {
     C* ru = reinterpret_cast<C*>(epi.rupd) + line * M;
-    const R al = (R)epi.ks->alpha;
+    const R al = (R)epi.ks[lm.item].alpha;
 #pragma unroll
     for (int e = 0; e < LS::E; ++e) {
       const int n = LS::idxB(t, e);
@@ -327,12 +388,12 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
 template <typename R, int L, bool INV>
 __global__ void __launch_bounds__(256)
 k_fft_axis(R* data, long estride, long ystride, long zstride, int B, const cplx<R>* __restrict__ tw,
-           const int* skip) {
+           Skip skip) {
   using C = cplx<R>;
   using LS = Line<L>;
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
-  if (skip && *skip) return;
+  if (skip(blockIdx.y)) return;
   const int col = threadIdx.x % B;
   const int t = threadIdx.x / B;
   C* base = reinterpret_cast<C*>(data) + (long)blockIdx.y * ystride + (long)blockIdx.z * zstride +
@@ -390,13 +451,13 @@ __device__ __forceinline__ R lap_sym(const SpecTables<R>& tb, int kz, int ky, in
 template <typename R, int L>
 __global__ void __launch_bounds__(256)
 k_fft_z_scalar(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, double a0, double a1,
-               const int* skip) {
+               Skip skip) {
   using C = cplx<R>;
   using LS = Line<L>;
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C* stw = lds + L * B;
-  if (skip && *skip) return;
+  if (skip(blockIdx.z)) return;
   for (int k = threadIdx.x; k < L; k += blockDim.x) stw[k] = tb.tw0[k];
   __syncthreads();
   const int col = threadIdx.x % B;
@@ -429,13 +490,13 @@ k_fft_z_scalar(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, double 
 // OP = 0: projection (3 rows, grid.y = 3); OP = 1: scalar symbol.
 template <typename R, int L, int OP>
 __global__ void __launch_bounds__(64)
-k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, const int* skip) {
+k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, Skip skip) {
   using C = cplx<R>;
   using LS = Line<L>;
   constexpr int NC = (OP == 0) ? 3 : 1;
   __shared__ C xbuf[2 * L];
   __shared__ C spec[NC * 2 * L];
-  if (skip && *skip) return;
+  if (skip(blockIdx.y)) return;
   const int col = threadIdx.x % 2;
   const int t = threadIdx.x / 2;
   if (t >= LS::T) {

@@ -161,7 +161,7 @@ template <int L> using ZLine = typename ZLineSel<L>::type;
 
 template <typename R, int L>
 __global__ void __launch_bounds__(256)
-k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, const int* skip) {
+k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip) {
   using C = cplx<R>;
   using LS = ZLine<L>;
   extern __shared__ char smem_raw[];
@@ -169,7 +169,7 @@ k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, const int
   C* stw = lds + L * B;
   R* scz = reinterpret_cast<R*>(stw + L);
   R* ssz = scz + L;
-  if (skip && *skip) return;
+  if (skip(blockIdx.z)) return;
   for (int k = threadIdx.x; k < L; k += blockDim.x) {
     stw[k] = tb.tw0[k];
     scz[k] = tb.cz[k];

@@ -13,13 +13,13 @@ namespace fg {
 #define FG_FOR_AXIS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
 
 template <typename R>
-void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const int* skip,
+void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const Skip& skip,
                 hipStream_t s) {
   switch (M) {
 #define FG_CASE(L_)                                                                        \
   case L_: {                                                                               \
     constexpr int LPB = XBLOCK / Line<L_>::T;                                              \
-    const long blocks = (nlines + LPB - 1) / LPB;                                          \
+    const long blocks = skip.line_blocks(nlines, LPB);                                     \
     hipLaunchKernelGGL((k_fft_x_r2c<R, L_>), dim3((unsigned)blocks), dim3(XBLOCK), 0, s, in, out, \
                        nlines, tb, skip);                                                  \
     return;                                                                                \
@@ -37,7 +37,7 @@ int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb,
 #define FG_CASE(L_)                                                                        \
   case L_: {                                                                               \
     constexpr int LPB = XBLOCK / Line<L_>::T;                                              \
-    const long blocks = (nlines + LPB - 1) / LPB;                                          \
+    const long blocks = epi.skip.line_blocks(nlines, LPB);                                 \
     hipLaunchKernelGGL((k_fft_x_c2r<R, L_>), dim3((unsigned)blocks), dim3(XBLOCK), 0, s, in, out, \
                        nlines, tb, epi);                                                   \
     return (int)blocks;                                                                    \
@@ -50,7 +50,7 @@ int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb,
 
 template <typename R>
 void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
-                 const cplx<R>* tw, const int* skip, hipStream_t s) {
+                 const cplx<R>* tw, const Skip& skip, hipStream_t s) {
   const int B = column_tile(L, M, (int)sizeof(cplx<R>));
   const int T = line_threads(L);
   const size_t shm = (size_t)L * B * sizeof(cplx<R>);
@@ -72,13 +72,13 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 }
 
 template <typename R>
-void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const int* skip,
-                  hipStream_t s) {
+void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
+                  hipStream_t s, int nitems) {
   const int T = zline_threads(N0);
   const int B = column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
   const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zpass_extra_lds<R>(N0);
-  dim3 grid((unsigned)(M / B), (unsigned)N1, 3);
-  dim3 gdc((unsigned)(N1 / 2 + 1), 3, 1);
+  dim3 grid((unsigned)(M / B), (unsigned)N1, (unsigned)(3 * nitems));
+  dim3 gdc((unsigned)(N1 / 2 + 1), (unsigned)(3 * nitems), 1);
   switch (N0) {
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \
@@ -93,7 +93,7 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
 
 template <typename R>
 void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0, double a1,
-                    const int* skip, hipStream_t s) {
+                    const Skip& skip, hipStream_t s) {
   const int B = column_tile(N0, M, (int)sizeof(cplx<R>));
   const int T = line_threads(N0);
   const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zpass_extra_lds<R>(N0);
@@ -114,12 +114,12 @@ void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R s
 
 template <typename R>
 int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const KrylovScalars* ks, double* partials,
-                    long N, long nlines, const SpecTables<R>& tb, hipStream_t s) {
+                    long N, long nlines, const SpecTables<R>& tb, hipStream_t s, int nitems) {
   switch (M) {
 #define FG_CASE(L_)                                                                                   \
   case L_: {                                                                                          \
     using FS = FrontShape<L_>;                                                                        \
-    const long blocks = (nlines + FS::LB - 1) / FS::LB;                                               \
+    const long blocks = nitems * ((nlines + FS::LB - 1) / FS::LB);                                    \
     hipLaunchKernelGGL((k_cg_front<R, L_>), dim3((unsigned)blocks), dim3(FS::THREADS), 0, s, spec, p, x, r, st, \
                        ks, partials, N, nlines, tb);                                                  \
     return (int)blocks;                                                                               \
@@ -132,13 +132,13 @@ int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const K
 
 #define FG_INSTANTIATE_LAUNCHERS(R)                                                                     \
   template int launch_cg_front<R>(int, R*, R*, R*, const R*, const R*, const KrylovScalars*, double*, long, \
-                                  long, const SpecTables<R>&, hipStream_t);                             \
-  template void launch_r2c<R>(int, const R*, R*, long, const SpecTables<R>&, const int*, hipStream_t); \
+                                  long, const SpecTables<R>&, hipStream_t, int);                        \
+  template void launch_r2c<R>(int, const R*, R*, long, const SpecTables<R>&, const Skip&, hipStream_t); \
   template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t); \
-  template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const int*, \
+  template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const Skip&, \
                                hipStream_t);                                                            \
-  template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const int*, hipStream_t);   \
-  template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const int*, \
+  template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int); \
+  template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const Skip&, \
                                   hipStream_t);
 
 }  // namespace fg

@@ -21,10 +21,10 @@ int zline_threads(int L);  // threads per line of the fused N0 projection pass
 // N2 real-to-complex pass); returns the number of partials written.
 template <typename R>
 int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const KrylovScalars* ks, double* partials,
-                    long N, long nlines, const SpecTables<R>& tb, hipStream_t s);
+                    long N, long nlines, const SpecTables<R>& tb, hipStream_t s, int nitems = 1);
 
 template <typename R>
-void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const int* skip,
+void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const Skip& skip,
                 hipStream_t s);
 // returns the number of blocks (= partials written when epi.partials != nullptr)
 template <typename R>
@@ -32,14 +32,15 @@ int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb,
                hipStream_t s);
 template <typename R>
 void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
-                 const cplx<R>* tw, const int* skip, hipStream_t s);
-// N0 pass fused with the projection, for 9-component fields (3 rows).
+                 const cplx<R>* tw, const Skip& skip, hipStream_t s);
+// N0 pass fused with the projection, for nitems 9-component fields (3 rows
+// each).
 template <typename R>
-void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const int* skip,
-                  hipStream_t s);
+void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
+                  hipStream_t s, int nitems = 1);
 // N0 pass fused with a scalar symbol scale / (a0 + a1 lambda(q)), 1 component.
 template <typename R>
 void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0, double a1,
-                    const int* skip, hipStream_t s);
+                    const Skip& skip, hipStream_t s);
 
 }  // namespace fg

@@ -18,6 +18,7 @@
 #include "fg_scalar.hpp"
 #include "fg_cgfront.hpp"
 #include "fg_fft3.hpp"
+#include "fg_batch.hpp"
 
 using namespace fg;
 
@@ -96,7 +97,8 @@ template <typename R> struct TablesDev {
 
 struct fg_plan {
   int n0, n1, n2, M;
-  long N;
+  long N;          // voxels per item
+  int nitems = 1;  // batch items (independent solves on the same grid)
   double h[3];
   fg_precision prec;
   hipStream_t stream;
@@ -109,9 +111,10 @@ struct fg_plan {
   // carved regions (offsets into ws)
   TablesDev<double> t64{};
   TablesDev<float> t32{};
-  KrylovScalars* ks = nullptr;   // [0] mechanics CG, [1] scalar PCG
+  KrylovScalars* ks = nullptr;   // [0, nitems) mechanics CG per item
+  KrylovScalars* ksc = nullptr;  // scalar PCG (= ks + nitems)
   int* flags = nullptr;          // [0] domain
-  double* dscal = nullptr;       // small FP64 scalars (norms), 64 entries
+  double* dscal = nullptr;       // small FP64 scalars (norms), 64 + 16 nitems entries
   double* part = nullptr;        // partial sums
   double* part2 = nullptr;
   double* Fu = nullptr;          // uniform tensor (9)
@@ -139,7 +142,8 @@ struct fg_plan {
   long prof_noop[FG_NPASS] = {};
 
   // pinned host scalars
-  KrylovScalars* hks = nullptr;
+  KrylovScalars* hks = nullptr;  // nitems + 1 entries
+  KrylovScalars* hksc = nullptr;
   double* hd = nullptr;
   int* hflags = nullptr;
 };
@@ -154,6 +158,7 @@ template <typename T> T* carve(char* base, size_t& off, size_t count) {
 
 size_t layout(fg_plan* P, char* base) {
   const long N = P->N;
+  const long NT = P->N * P->nitems;
   const int n0 = P->n0, n1 = P->n1, M = P->M;
   size_t off = 0;
   auto tabs = [&](auto& t, auto tag) {
@@ -171,25 +176,30 @@ size_t layout(fg_plan* P, char* base) {
   };
   tabs(P->t64, double());
   tabs(P->t32, float());
-  P->ks = carve<KrylovScalars>(base, off, 2);
+  P->ks = carve<KrylovScalars>(base, off, P->nitems + 1);
+  P->ksc = P->ks + P->nitems;
   P->flags = carve<int>(base, off, 4);
-  P->dscal = carve<double>(base, off, 64);
-  P->Fu = carve<double>(base, off, 16);
-  P->part_n = (size_t)9 * (N / 256 + 2) + 8192;
+  P->dscal = carve<double>(base, off, 64 + 16 * P->nitems);
+  P->Fu = carve<double>(base, off, 16 + 9 * P->nitems);
+  // partial sums: 9 per 256-voxel block of every item, plus slack for the
+  // per-item rounding of the line passes
+  P->part_n = (size_t)9 * P->nitems * (N / 256 + 2) + 8192;
   P->part = carve<double>(base, off, P->part_n);
   P->part2 = carve<double>(base, off, P->part_n);
   const size_t tb = (P->prec == FG_FP64) ? sizeof(double) : sizeof(float);
-  P->S64 = carve<double>(base, off, 9 * N);
+  P->S64 = carve<double>(base, off, 9 * NT);
   if (P->prec == FG_FP64) {
     P->S = P->S64;
   } else {
-    P->S = carve<char>(base, off, 9 * N * tb);
+    P->S = carve<char>(base, off, 9 * NT * tb);
   }
-  P->x = carve<char>(base, off, 9 * N * tb);
-  P->r = carve<char>(base, off, 9 * N * tb);
-  P->p = carve<char>(base, off, 9 * N * tb);
-  P->st = carve<char>(base, off, 12 * N * tb);
-  P->sc = carve<double>(base, off, 16 * N);
+  P->x = carve<char>(base, off, 9 * NT * tb);
+  P->r = carve<char>(base, off, 9 * NT * tb);
+  P->p = carve<char>(base, off, 9 * NT * tb);
+  P->st = carve<char>(base, off, 12 * NT * tb);
+  // scalar solvers (phase field, Fick) only on single plans; batches keep
+  // just the zero fields standing in for c and d
+  P->sc = carve<double>(base, off, P->nitems == 1 ? 16 * N : NT);
   return off;
 }
 
@@ -276,8 +286,9 @@ inline unsigned grid_stride_blocks(long n) { return (unsigned)std::min<long>(204
 void check_launch() { FG_HIP(hipGetLastError()); }
 
 void sync_read(fg_plan* P) {
-  FG_HIP(hipMemcpyAsync(P->hks, P->ks, 2 * sizeof(KrylovScalars), hipMemcpyDeviceToHost, P->stream));
-  FG_HIP(hipMemcpyAsync(P->hd, P->dscal, 64 * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  FG_HIP(hipMemcpyAsync(P->hks, P->ks, (P->nitems + 1) * sizeof(KrylovScalars), hipMemcpyDeviceToHost, P->stream));
+  FG_HIP(hipMemcpyAsync(P->hd, P->dscal, (64 + 16 * P->nitems) * sizeof(double), hipMemcpyDeviceToHost,
+                        P->stream));
   FG_HIP(hipMemcpyAsync(P->hflags, P->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
   FG_HIP(hipStreamSynchronize(P->stream));
 }
@@ -296,6 +307,15 @@ void reduce_to(fg_plan* P, const double* parts, int nparts, int slot) {
   check_launch();
 }
 
+// Per-item sums (nparts partials per item, item-major) into the item slot
+// array dscal[64 + 16 b + slot]... stored as dscal[64 + slot * nitems + b].
+void reduce_items(fg_plan* P, const double* parts, int nparts_per_item, int slot) {
+  hipLaunchKernelGGL(k_finalize, dim3(P->nitems), dim3(1024), 0, P->stream, parts, nparts_per_item,
+                     (KrylovScalars*)nullptr, P->dscal + 64 + (long)slot * P->nitems, 2, 0);
+  check_launch();
+}
+inline double item_value(const fg_plan* P, int slot, int b) { return P->hd[64 + (long)slot * P->nitems + b]; }
+
 // ----------------------------------------------------------------------------
 // 3-D transforms on the plan grid.
 template <typename R> const TablesDev<R>& tabs(const fg_plan* P);
@@ -303,41 +323,48 @@ template <> const TablesDev<double>& tabs<double>(const fg_plan* P) { return P->
 template <> const TablesDev<float>& tabs<float>(const fg_plan* P) { return P->t32; }
 
 // Forward passes 1 and 2 (N2 real-to-complex, N1 complex) of ncomp fields,
-// in -> data (in may equal data).
+// in -> data (in may equal data).  In a batch the ncomp fields are
+// ncomp / nitems per item, item-major; skip masks whole items.
 template <typename R>
-void fwd_xy(fg_plan* P, const R* in, R* data, int ncomp, const int* skip) {
+void fwd_xy(fg_plan* P, const R* in, R* data, int ncomp, const Skip& skip) {
   const SpecTables<R> tb = tabs<R>(P).spec();
+  const long cpi = ncomp / P->nitems;
   {
     ProfScope ps(P, FG_PASS_R2C);
-    launch_r2c<R>(P->M, in, data, (long)ncomp * P->n0 * P->n1, tb, skip, P->stream);
+    launch_r2c<R>(P->M, in, data, (long)ncomp * P->n0 * P->n1, tb, skip.unit(cpi * P->n0 * P->n1), P->stream);
   }
   ProfScope ps(P, FG_PASS_AXIS);
-  launch_axis<R>(P->n1, false, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1, skip,
-                 P->stream);
+  launch_axis<R>(P->n1, false, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1,
+                 skip.unit(cpi * P->n0), P->stream);
 }
 
 // Inverse passes 2 and 1, data -> out with the C2R epilogue; returns #partials.
 template <typename R>
 int inv_yx(fg_plan* P, R* data, R* out, int ncomp, const C2REpi& epi) {
   const SpecTables<R> tb = tabs<R>(P).spec();
+  const long cpi = ncomp / P->nitems;
   {
     ProfScope ps(P, FG_PASS_AXIS);
-    launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1, epi.skip,
-                   P->stream);
+    launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1,
+                   epi.skip.unit(cpi * P->n0), P->stream);
   }
   ProfScope ps(P, FG_PASS_C2R);
-  return launch_c2r<R>(P->M, data, out, (long)ncomp * P->n0 * P->n1, tb, epi, P->stream);
+  C2REpi e = epi;
+  e.skip = epi.skip.unit(cpi * P->n0 * P->n1);
+  return launch_c2r<R>(P->M, data, out, (long)ncomp * P->n0 * P->n1, tb, e, P->stream);
 }
 
-// y = G * x for 9-component fields (projection), returns #partials.
+// y = G * x for the 9-component fields of all items (projection); returns
+// the number of partials (all items; nitems divides it).
 template <typename R>
 int project9(fg_plan* P, const R* in, R* work, R* out, const C2REpi& epi) {
-  fwd_xy<R>(P, in, work, 9, epi.skip);
+  fwd_xy<R>(P, in, work, 9 * P->nitems, epi.skip);
   {
     ProfScope ps(P, FG_PASS_ZPROJ);
-    launch_zproj<R>(P->n0, work, P->n1, P->M, tabs<R>(P).spec(), (R)(1.0 / (double)P->N), epi.skip, P->stream);
+    launch_zproj<R>(P->n0, work, P->n1, P->M, tabs<R>(P).spec(), (R)(1.0 / (double)P->N), epi.skip.unit(3),
+                    P->stream, P->nitems);
   }
-  return inv_yx<R>(P, work, out, 9, epi);
+  return inv_yx<R>(P, work, out, 9 * P->nitems, epi);
 }
 
 // y = F^-1[ F[x] / (a0 + a1 lambda) ] for one scalar field, returns #partials.
@@ -354,23 +381,24 @@ int precond1(fg_plan* P, const R* in, R* work, R* out, double a0, double a1, con
 
 // ----------------------------------------------------------------------------
 // Mechanics.
-void constitutive(fg_plan* P, const double* Fu, double* Pout, void* state, double* pparts) {
+void constitutive(fg_plan* P, const double* Fu, double* Pout, void* state, double* pparts,
+                  const int* idle = nullptr) {
   ProfScope ps(P, FG_PASS_CONSTITUTIVE);
-  const unsigned nb = blocks_for(P->N);
+  const dim3 grid(blocks_for(P->N), (unsigned)P->nitems);
   const double* c = P->c ? P->c : P->zeroN;
   const double* d = P->d ? P->d : P->zeroN;
   if (P->prec == FG_FP64)
-    hipLaunchKernelGGL((k_constitutive<double>), dim3(nb), dim3(256), 0, P->stream, P->F, Fu, c, d, P->E, P->nu,
-                       P->Om, Pout, (double*)state, pparts, P->flags, P->N);
+    hipLaunchKernelGGL((k_constitutive<double>), grid, dim3(256), 0, P->stream, P->F, Fu, c, d, P->E, P->nu,
+                       P->Om, Pout, (double*)state, pparts, P->flags, P->N, idle);
   else
-    hipLaunchKernelGGL((k_constitutive<float>), dim3(nb), dim3(256), 0, P->stream, P->F, Fu, c, d, P->E, P->nu,
-                       P->Om, Pout, (float*)state, pparts, P->flags, P->N);
+    hipLaunchKernelGGL((k_constitutive<float>), grid, dim3(256), 0, P->stream, P->F, Fu, c, d, P->E, P->nu,
+                       P->Om, Pout, (float*)state, pparts, P->flags, P->N, idle);
   check_launch();
 }
 
 // ||G*P|| of the stress in S64 (in place), into dscal[slot]; G*P stays in S64.
 void residual_norm(fg_plan* P, int slot) {
-  C2REpi epi{1.0, nullptr, true, P->part, nullptr};
+  C2REpi epi{1.0, nullptr, true, P->part, Skip{}};
   const int nb = project9<double>(P, P->S64, P->S64, P->S64, epi);
   reduce_to(P, P->part, nb, slot);
 }
@@ -410,13 +438,62 @@ void note_noop_iterations(fg_plan* P, long noop) {
   P->prof_noop[FG_PASS_FINALIZE] += 2 * noop;
 }
 
+// One CG iteration for every item of the plan (items whose solve is done
+// skip every kernel):
+//   x += alpha_{k-1} p_{k-1}; p = r + beta p; Y = K:p; p.Y; N2 pass of Y
+//   alpha = r.r / p.Kp; N1, N0 (+ projection), N1 passes;
+//   r -= alpha G(K p) fused with the inverse N2 pass, r.r; beta, convergence.
+template <typename T>
+void cg_iteration(fg_plan* P) {
+  T* S = (T*)P->S;
+  const int nit = P->nitems;
+  KrylovScalars* ks = P->ks;
+  const SpecTables<T> tb = tabs<T>(P).spec();
+  const Skip skip = Skip::done(ks);
+  const long lines = (long)P->n0 * P->n1;
+  int nbf;
+  {
+    ProfScope ps(P, FG_PASS_FRONT);
+    nbf = launch_cg_front<T>(P->M, S, (T*)P->p, (T*)P->x, (const T*)P->r, (const T*)P->st, ks, P->part, P->N, lines,
+                             tb, P->stream, nit);
+  }
+  {
+    ProfScope ps(P, FG_PASS_FINALIZE);
+    hipLaunchKernelGGL(k_finalize, dim3(nit), dim3(1024), 0, P->stream, P->part, nbf / nit, ks, (double*)nullptr, 0,
+                       0);
+  }
+  {
+    ProfScope ps(P, FG_PASS_AXIS);
+    launch_axis<T>(P->n1, false, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * nit, 1, tb.tw1,
+                   skip.unit(9L * P->n0), P->stream);
+  }
+  {
+    ProfScope ps(P, FG_PASS_ZPROJ);
+    launch_zproj<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip.unit(3), P->stream, nit);
+  }
+  {
+    ProfScope ps(P, FG_PASS_AXIS);
+    launch_axis<T>(P->n1, true, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * nit, 1, tb.tw1,
+                   skip.unit(9L * P->n0), P->stream);
+  }
+  int nbc;
+  {
+    ProfScope ps(P, FG_PASS_C2R);
+    C2REpi epi{1.0, nullptr, true, P->part2, skip.unit(9 * lines), P->r, ks};
+    nbc = launch_c2r<T>(P->M, S, S, 9 * lines * nit, tb, epi, P->stream);
+  }
+  {
+    ProfScope ps(P, FG_PASS_FINALIZE);
+    hipLaunchKernelGGL(k_finalize, dim3(nit), dim3(1024), 0, P->stream, P->part2, nbc / nit, ks, (double*)nullptr,
+                       1, 0);
+  }
+  check_launch();
+}
+
 template <typename T>
 void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
-  T* S = (T*)P->S;
   T* x = (T*)P->x;
-  T* r = (T*)P->r;
   T* p = (T*)P->p;
-  const T* st = (const T*)P->st;
   KrylovScalars* ks = P->ks;
   const long n9 = 9 * P->N;
   // ks was initialised (rr0, rr, iter = 0, done) by the residual pass
@@ -429,48 +506,11 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
     FG_HIP(hipMemcpyAsync(&ks->tol2, P->hd + 62, sizeof(double), hipMemcpyHostToDevice, P->stream));
     FG_HIP(hipMemcpyAsync(&ks->maxit, P->hd + 63, sizeof(int), hipMemcpyHostToDevice, P->stream));
   }
-  const SpecTables<T> tb = tabs<T>(P).spec();
-  const int* skip = &ks->done;
   int chunk = 8;
   long launched = 0;
   for (int guard = 0; guard < 1000000; ++guard) {
     launched += chunk;
-    for (int k = 0; k < chunk; ++k) {
-      // x += alpha_{k-1} p_{k-1}; p = r + beta p; Y = K:p; p.Y; N2 pass of Y
-      int nbf;
-      {
-        ProfScope ps(P, FG_PASS_FRONT);
-        nbf = launch_cg_front<T>(P->M, S, p, x, r, st, ks, P->part, P->N, (long)P->n0 * P->n1, tb, P->stream);
-      }
-      {
-        ProfScope ps(P, FG_PASS_FINALIZE);  // alpha = r.r / p.Kp
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nbf, ks, (double*)nullptr, 0, 0);
-      }
-      {
-        ProfScope ps(P, FG_PASS_AXIS);
-        launch_axis<T>(P->n1, false, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0, 1, tb.tw1, skip, P->stream);
-      }
-      {
-        ProfScope ps(P, FG_PASS_ZPROJ);
-        launch_zproj<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip, P->stream);
-      }
-      {
-        ProfScope ps(P, FG_PASS_AXIS);
-        launch_axis<T>(P->n1, true, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0, 1, tb.tw1, skip, P->stream);
-      }
-      int nbc;
-      {
-        // r -= alpha G(K p), r.r
-        ProfScope ps(P, FG_PASS_C2R);
-        C2REpi epi{1.0, nullptr, true, P->part2, skip, r, ks};
-        nbc = launch_c2r<T>(P->M, S, S, 9L * P->n0 * P->n1, tb, epi, P->stream);
-      }
-      {
-        ProfScope ps(P, FG_PASS_FINALIZE);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, nbc, ks, (double*)nullptr, 1, 0);
-      }
-      check_launch();
-    }
+    for (int k = 0; k < chunk; ++k) cg_iteration<T>(P);
     sync_read(P);
     if (P->hks[0].done) break;
     chunk = next_chunk(P->hks[0], launched);
@@ -530,7 +570,7 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
     if (it >= o->max_newton) throw Status(FG_E_NOCONV, "Newton reached max_newton iterations");
     // b = -G*(G*P): second projection of the residual (compatible rhs)
     {
-      C2REpi epi{-1.0, nullptr, true, P->part, nullptr};
+      C2REpi epi{-1.0, nullptr, true, P->part, Skip{}};
       const int nb = project9<double>(P, P->S64, P->S64, P->S64, epi);
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
       check_launch();
@@ -560,7 +600,7 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
       hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->S64,
                          (const float*)P->x, n9);
       {
-        C2REpi epi{1.0, nullptr, true, nullptr, nullptr};
+        C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
         project9<double>(P, P->S64, P->S64, P->S64, epi);
       }
       hipLaunchKernelGGL((k_axpy_into_f64<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->F,
@@ -594,9 +634,9 @@ void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_sol
   {
     // b = -G*(G*(K:W)): the second projection keeps the right-hand side
     // compatible to rounding (as for the Newton right-hand side)
-    C2REpi e1{1.0, nullptr, true, nullptr, nullptr};
+    C2REpi e1{1.0, nullptr, true, nullptr, Skip{}};
     project9<T>(P, S, S, S, e1);
-    C2REpi e2{-1.0, nullptr, true, P->part, nullptr};
+    C2REpi e2{-1.0, nullptr, true, P->part, Skip{}};
     const int nb = project9<T>(P, S, S, S, e2);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
     FG_HIP(hipMemcpyAsync(P->r, S, n9 * sizeof(T), hipMemcpyDeviceToDevice, P->stream));
@@ -650,12 +690,12 @@ ScalarVecs scalar_vecs(fg_plan* P) {
 void scalar_pcg(fg_plan* P, ScalarOp op, double a0, double a1, double dt, const fg_solver_opts* o,
                 fg_stats* stats) {
   ScalarVecs v = scalar_vecs(P);
-  KrylovScalars* ks = P->ks + 1;
+  KrylovScalars* ks = P->ksc;
   P->hd[60] = (o->fixed_lin > 0) ? 0.0 : o->tol_lin * o->tol_lin;
   ((int*)(P->hd + 61))[0] = (o->fixed_lin > 0) ? o->fixed_lin : o->max_lin;
   FG_HIP(hipMemcpyAsync(&ks->tol2, P->hd + 60, sizeof(double), hipMemcpyHostToDevice, P->stream));
   FG_HIP(hipMemcpyAsync(&ks->maxit, P->hd + 61, sizeof(int), hipMemcpyHostToDevice, P->stream));
-  const int* skip = &ks->done;
+  const Skip skip = Skip::done(ks);
   const unsigned nbN = blocks_for(P->N);
   const unsigned nbu = grid_stride_blocks(P->N);
   const Grid3 g{P->n0, P->n1, P->n2, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]};
@@ -687,10 +727,10 @@ void scalar_pcg(fg_plan* P, ScalarOp op, double a0, double a1, double dt, const 
       check_launch();
     }
     sync_read(P);
-    if (P->hks[1].done) break;
-    chunk = next_chunk(P->hks[1], 0);
+    if (P->hksc[0].done) break;
+    chunk = next_chunk(P->hksc[0], 0);
   }
-  const KrylovScalars& h = P->hks[1];
+  const KrylovScalars& h = P->hksc[0];
   if (stats) {
     stats->lin_iters_last = h.iter;
     stats->lin_relres = h.rr0 > 0 ? std::sqrt(h.rr / h.rr0) : 0.0;
@@ -709,14 +749,14 @@ void pff(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
                      v.a, v.r, v.x, P->gc, P->lc, P->part, P->part2, P->flags, P->N);
   check_launch();
   reduce_to(P, P->part, (int)nbN, 0);  // sum H
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbN, P->ks + 1, (double*)nullptr,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbN, P->ksc, (double*)nullptr,
                      5, 1);
   check_launch();
   sync_read(P);
   check_domain(P);
   if (stats) stats->lin_iters_total = 0;
   const double Hbar = P->hd[0] / (double)P->N;
-  if (!P->hks[1].done) {
+  if (!P->hksc[0].done) {
     scalar_pcg(P, ScalarOp::PFF, P->gc / P->lc + 2.0 * Hbar, P->gc * P->lc, 0.0, o, stats);
   } else if (stats) {
     stats->lin_iters_last = 0;
@@ -760,7 +800,7 @@ void fick(fg_plan* P, double dt, const double* cdot, const fg_solver_opts* o, fg
     sync_read(P);
     check_domain(P);
     const double winv = P->hd[2] / (double)N;
-    if (!P->hks[1].done) scalar_pcg(P, ScalarOp::FICK, winv, dt * abar, dt, o, stats);
+    if (!P->hksc[0].done) scalar_pcg(P, ScalarOp::FICK, winv, dt * abar, dt, o, stats);
     hipLaunchKernelGGL(k_fick_update, dim3(nbN), dim3(256), 0, P->stream, P->c, v.x, v.w, P->part, N);
     check_launch();
     reduce_to(P, P->part, (int)nbN, 3);
@@ -790,7 +830,7 @@ void apply_macro(fg_plan* P, const double F_macro[9]) {
   for (int k = 0; k < 9; ++k) P->hd[32 + k] = F_macro[k] - P->hd[8 + k] / (double)P->N;
   FG_HIP(hipMemcpyAsync(P->Fu, P->hd + 32, 9 * sizeof(double), hipMemcpyHostToDevice, P->stream));
   hipLaunchKernelGGL(k_add_uniform9, dim3(blocks_for(P->N)), dim3(256), 0, P->stream, P->F, (const double*)P->Fu,
-                     P->N);
+                     P->N, P->N);
   check_launch();
 }
 
@@ -818,20 +858,12 @@ fg_status run(fg_plan* P, const std::function<void()>& fn) {
   }
 }
 
-void need_ready(fg_plan* P, bool need_state) {
-  if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
-  if (!P->have_material) throw Status(FG_E_STATE, "material not set");
-  if (need_state && !P->F) throw Status(FG_E_STATE, "state not set");
-}
-}  // namespace
-
-extern "C" {
-
-fg_status fg_plan_create(const int grid[3], const double spacing[3], fg_precision prec, void* stream,
-                         fg_plan** out) {
+fg_status plan_new(const int grid[3], const double spacing[3], fg_precision prec, void* stream, int nitems,
+                   fg_plan** out) {
   if (!grid || !spacing || !out) return FG_E_ARG;
   *out = nullptr;
   if (prec != FG_FP64 && prec != FG_MIXED) return FG_E_ARG;
+  if (nitems < 1) return FG_E_ARG;
   for (int k = 0; k < 3; ++k)
     if (!(spacing[k] > 0.0) || !std::isfinite(spacing[k])) return FG_E_ARG;
   if (!fg::fft_axis_length_supported(grid[0]) || !fg::fft_axis_length_supported(grid[1])) return FG_E_SIZE;
@@ -844,17 +876,33 @@ fg_status fg_plan_create(const int grid[3], const double spacing[3], fg_precisio
   P->M = grid[2] / 2;
   P->N = (long)grid[0] * grid[1] * grid[2];
   for (int k = 0; k < 3; ++k) P->h[k] = spacing[k];
+  P->nitems = nitems;
   P->prec = prec;
   P->stream = (hipStream_t)stream;
   P->need = layout(P, nullptr) + kAlign;
-  if (hipHostMalloc((void**)&P->hks, 2 * sizeof(KrylovScalars), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&P->hd, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc((void**)&P->hks, (nitems + 1) * sizeof(KrylovScalars), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&P->hd, (64 + 16 * nitems) * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&P->hflags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     fg_plan_destroy(P);
     return FG_E_HIP;
   }
+  P->hksc = P->hks + nitems;
   *out = P;
   return FG_OK;
+}
+
+void need_ready(fg_plan* P, bool need_state) {
+  if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
+  if (!P->have_material) throw Status(FG_E_STATE, "material not set");
+  if (need_state && !P->F) throw Status(FG_E_STATE, "state not set");
+}
+}  // namespace
+
+extern "C" {
+
+fg_status fg_plan_create(const int grid[3], const double spacing[3], fg_precision prec, void* stream,
+                         fg_plan** out) {
+  return plan_new(grid, spacing, prec, stream, 1, out);
 }
 
 size_t fg_plan_workspace_bytes(const fg_plan* P) { return P ? P->need : 0; }
@@ -879,10 +927,10 @@ fg_status fg_plan_set_workspace(fg_plan* P, void* dev, size_t bytes) {
     host_tables<double>(P, blob, P->t64, P->ws);
     host_tables<float>(P, blob, P->t32, P->ws);
     FG_HIP(hipMemcpyAsync(P->ws, blob.data(), tab_end, hipMemcpyHostToDevice, P->stream));
-    FG_HIP(hipMemsetAsync(P->ks, 0, 2 * sizeof(KrylovScalars), P->stream));
+    FG_HIP(hipMemsetAsync(P->ks, 0, (P->nitems + 1) * sizeof(KrylovScalars), P->stream));
     FG_HIP(hipMemsetAsync(P->flags, 0, 4 * sizeof(int), P->stream));
-    P->zeroN = P->sc + 15 * P->N;
-    FG_HIP(hipMemsetAsync(P->zeroN, 0, P->N * sizeof(double), P->stream));
+    P->zeroN = (P->nitems == 1) ? P->sc + 15 * P->N : P->sc;
+    FG_HIP(hipMemsetAsync(P->zeroN, 0, P->N * P->nitems * sizeof(double), P->stream));
     FG_HIP(hipStreamSynchronize(P->stream));  // the host blob goes out of scope
   });
 }
@@ -1002,7 +1050,7 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
                          (const double*)nullptr,
                          (const double*)P->st, (const KrylovScalars*)nullptr, P->N, 0);
       check_launch();
-      C2REpi epi{1.0, nullptr, true, nullptr, nullptr};
+      C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
       project9<double>(P, y, y, y, epi);
     } else {
       constitutive(P, nullptr, nullptr, P->st, nullptr);
@@ -1014,7 +1062,7 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
                          (const float*)nullptr,
                          (const float*)P->st, (const KrylovScalars*)nullptr, P->N, 0);
       check_launch();
-      C2REpi epi{1.0, nullptr, true, nullptr, nullptr};
+      C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
       project9<float>(P, yf, yf, yf, epi);
       hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, y,
                          (const float*)yf, n9);
@@ -1027,7 +1075,7 @@ fg_status fg_project(fg_plan* P, const double* x, double* y) {
   if (!P || !x || !y) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
-    C2REpi epi{1.0, nullptr, true, nullptr, nullptr};
+    C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
     project9<double>(P, x, P->S64, y, epi);
     check_launch();
   });
@@ -1038,9 +1086,9 @@ fg_status fg_fft_r2c(fg_plan* P, double* data, int ncomp) {
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
     const SpecTables<double> tb = P->t64.spec();
-    fwd_xy<double>(P, data, data, ncomp, nullptr);
+    fwd_xy<double>(P, data, data, ncomp, Skip{});
     launch_axis<double>(P->n0, false, data, (long)P->n1 * P->M, P->M, (long)P->n0 * P->n1 * P->M, P->M, P->n1,
-                        ncomp, tb.tw0, nullptr, P->stream);
+                        ncomp, tb.tw0, Skip{}, P->stream);
     check_launch();
   });
 }
@@ -1051,8 +1099,8 @@ fg_status fg_fft_c2r(fg_plan* P, double* data, int ncomp) {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
     const SpecTables<double> tb = P->t64.spec();
     launch_axis<double>(P->n0, true, data, (long)P->n1 * P->M, P->M, (long)P->n0 * P->n1 * P->M, P->M, P->n1,
-                        ncomp, tb.tw0, nullptr, P->stream);
-    C2REpi epi{1.0 / (double)P->N, nullptr, true, nullptr, nullptr};
+                        ncomp, tb.tw0, Skip{}, P->stream);
+    C2REpi epi{1.0 / (double)P->N, nullptr, true, nullptr, Skip{}};
     inv_yx<double>(P, data, data, ncomp, epi);
     check_launch();
   });
@@ -1137,6 +1185,503 @@ void fg_plan_destroy(fg_plan* P) {
   if (P->hd) (void)hipHostFree(P->hd);
   if (P->hflags) (void)hipHostFree(P->hflags);
   delete P;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ batched form --
+// Many independent (RVE, load case) items, possibly on different grids.
+// Items of one grid form a group: one plan whose fields hold all its items
+// item-major, so every kernel of the CG and Newton passes covers the whole
+// group in one launch, with finished items masked.  Each group runs on a
+// stream of its own; one tick advances every item of every group by one step
+// (a CG iteration or a Newton step), and a captured graph holds several ticks
+// of all groups (forked from and joined into the batch stream).
+struct fg_batch {
+  int n_rve = 0, n_cases = 0;
+  fg_precision prec = FG_FP64;
+  hipStream_t user = nullptr;  // caller's stream: inputs are ordered on it
+  hipStream_t s0 = nullptr;    // batch stream (fork / join, graph launch)
+  hipEvent_t ev_in = nullptr, ev_fork = nullptr;
+  struct Group {
+    int grid[3];
+    double h[3];
+    std::vector<std::pair<int, int>> items;  // (rve, case) of each item
+    fg_plan* P = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t ev_join = nullptr;
+    size_t off = 0, plan_bytes = 0, bytes = 0;
+    double *E = nullptr, *nu = nullptr, *Om = nullptr, *c = nullptr, *F = nullptr;
+    NewtonCtl* nc = nullptr;
+    int* idle = nullptr;
+    int* active = nullptr;
+  };
+  std::vector<Group> groups;
+  std::vector<std::pair<int, int>> where;  // (rve, case) -> (group, item)
+  std::vector<char> have_mat;              // per RVE
+  size_t need = 0;
+  char* ws = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_ticks = 0;
+  NewtonCtl* hnc = nullptr;  // pinned, max items of a group
+  int* hactive = nullptr;    // pinned, one per group
+  std::string err;
+};
+
+namespace {
+
+// Items per group: bounded by the grid limits of the N1 pass (9 N0 planes
+// per item on grid.y) and the N0 pass (3 rows per item on grid.z).
+int max_items_per_group(const int grid[3]) { return std::max(1, 65535 / (9 * grid[0])); }
+
+fg_status batch_run(fg_batch* B, const std::function<void()>& fn) {
+  try {
+    fn();
+    B->err.clear();
+    return FG_OK;
+  } catch (const Status& s) {
+    B->err = s.what();
+    return s.code;
+  } catch (const HipError& e) {
+    B->err = e.what();
+    return FG_E_HIP;
+  } catch (const std::invalid_argument& e) {
+    B->err = e.what();
+    return FG_E_SIZE;
+  } catch (const std::exception& e) {
+    B->err = e.what();
+    return FG_E_HIP;
+  }
+}
+
+inline dim3 item_grid(long n, int nitems) {
+  return dim3((unsigned)std::min<long>(256, (n + 255) / 256), (unsigned)nitems);
+}
+
+// One tick of a group: a CG iteration for the items whose solve runs, then
+// the Newton step for the items whose solve has ended.
+template <typename T>
+void batch_tick(fg_plan* P, fg_batch::Group& g) {
+  cg_iteration<T>(P);
+  const int nit = P->nitems;
+  const long n9 = 9 * P->N;
+  const dim3 gi = item_grid(n9, nit);
+  hipLaunchKernelGGL(k_newton_gate, dim3(1), dim3(1024), 0, P->stream, (const KrylovScalars*)P->ks, g.nc, g.idle,
+                     g.active, nit, (int)FG_E_BREAKDOWN, (int)FG_E_NOCONV);
+  hipLaunchKernelGGL((k_items_final_x<T>), gi, dim3(256), 0, P->stream, (T*)P->x, (const T*)P->p,
+                     (const KrylovScalars*)P->ks, (const int*)g.idle, n9);
+  const Skip idle = Skip::flags(g.idle);
+  if (P->prec == FG_FP64) {
+    hipLaunchKernelGGL((k_items_axpy<double>), gi, dim3(256), 0, P->stream, P->F, (const double*)P->x,
+                       (const int*)g.idle, n9);
+  } else {
+    // dF = G * x in double precision (as in the single-item mixed form)
+    hipLaunchKernelGGL((k_items_convert<float, double>), gi, dim3(256), 0, P->stream, P->S64, (const float*)P->x,
+                       (const int*)g.idle, n9);
+    C2REpi e{1.0, nullptr, true, nullptr, idle};
+    project9<double>(P, P->S64, P->S64, P->S64, e);
+    hipLaunchKernelGGL((k_items_axpy<double>), gi, dim3(256), 0, P->stream, P->F, (const double*)P->S64,
+                       (const int*)g.idle, n9);
+  }
+  constitutive(P, nullptr, P->S64, P->st, nullptr, g.idle);
+  {
+    // err_res of eq. (31) and the Newton test
+    C2REpi e{1.0, nullptr, true, P->part, idle};
+    const int nb = project9<double>(P, P->S64, P->S64, P->S64, e);
+    hipLaunchKernelGGL(k_newton_check, dim3(nit), dim3(1024), 0, P->stream, (const double*)P->part, nb / nit, g.nc,
+                       g.idle, (int)FG_E_NOCONV);
+  }
+  {
+    // b = -G*(G*P) and a fresh CG
+    C2REpi e{-1.0, nullptr, true, P->part, idle};
+    const int nb = project9<double>(P, P->S64, P->S64, P->S64, e);
+    hipLaunchKernelGGL(k_newton_cg_start, dim3(nit), dim3(1024), 0, P->stream, (const double*)P->part, nb / nit,
+                       P->ks, g.nc, (const int*)g.idle);
+  }
+  hipLaunchKernelGGL((k_items_rhs<T>), gi, dim3(256), 0, P->stream, (T*)P->r, (T*)P->x, (const double*)P->S64,
+                     (const int*)g.idle, n9);
+  check_launch();
+}
+
+// ticks of every group, forked from s0 and joined back into it
+void batch_enqueue(fg_batch* B, int ticks) {
+  FG_HIP(hipEventRecord(B->ev_fork, B->s0));
+  for (auto& g : B->groups) {
+    FG_HIP(hipStreamWaitEvent(g.s, B->ev_fork, 0));
+    for (int t = 0; t < ticks; ++t) {
+      if (B->prec == FG_FP64)
+        batch_tick<double>(g.P, g);
+      else
+        batch_tick<float>(g.P, g);
+    }
+    FG_HIP(hipEventRecord(g.ev_join, g.s));
+    FG_HIP(hipStreamWaitEvent(B->s0, g.ev_join, 0));
+  }
+}
+
+void batch_capture(fg_batch* B, int ticks) {
+  if (B->exec && B->graph_ticks == ticks) return;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->exec = nullptr;
+  B->graph = nullptr;
+  FG_HIP(hipStreamBeginCapture(B->s0, hipStreamCaptureModeThreadLocal));
+  try {
+    batch_enqueue(B, ticks);
+  } catch (...) {
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(B->s0, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    throw;
+  }
+  FG_HIP(hipStreamEndCapture(B->s0, &B->graph));
+  FG_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+  B->graph_ticks = ticks;
+}
+
+// Start of the solve for a group: F = F_macro of the item's load case
+// (uniform), the normaliser of eq. (31) per item, Newton and CG control.
+void batch_prologue(fg_batch* B, fg_batch::Group& g, const double* F_macro, const fg_solver_opts* o) {
+  fg_plan* P = g.P;
+  const int nit = P->nitems;
+  const long N = P->N;
+  for (int b = 0; b < nit; ++b)
+    for (int k = 0; k < 9; ++k) P->hd[64 + 9 * b + k] = F_macro[9 * g.items[b].second + k];
+  FG_HIP(hipMemcpyAsync(P->Fu, P->hd + 64, 9 * nit * sizeof(double), hipMemcpyHostToDevice, P->stream));
+  hipLaunchKernelGGL((k_fill<double>), dim3(grid_stride_blocks(9 * N * nit)), dim3(256), 0, P->stream, P->F, 0.0,
+                     9 * N * nit);
+  hipLaunchKernelGGL(k_add_uniform9, dim3(blocks_for(N * nit)), dim3(256), 0, P->stream, P->F,
+                     (const double*)P->Fu, N, N * nit);
+  hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, P->stream, P->flags, 0, 4L);
+  check_launch();
+  // ||P(Fbar)||^2 and ||G*P(Fbar)||^2 per item
+  constitutive(P, P->Fu, P->S64, nullptr, P->part2);
+  reduce_items(P, P->part2, (int)blocks_for(N), 0);
+  {
+    C2REpi e{1.0, nullptr, true, P->part, Skip{}};
+    const int nb = project9<double>(P, P->S64, P->S64, P->S64, e);
+    reduce_items(P, P->part, nb / nit, 1);
+  }
+  sync_read(P);
+  check_domain(P);
+  const bool mixed = (P->prec == FG_MIXED);
+  fg_solver_opts om = *o;
+  if (mixed && om.fixed_lin <= 0) om.tol_lin = std::max(o->tol_lin, 1e-5);
+  for (int b = 0; b < nit; ++b) {
+    NewtonCtl& c = B->hnc[b];
+    std::memset(&c, 0, sizeof(NewtonCtl));
+    const double p2 = item_value(P, 0, b), gp2 = item_value(P, 1, b);
+    c.den = std::max(std::max(std::sqrt(gp2), 1e-14 * std::sqrt(p2)), 1e-300);
+    c.tol = mixed ? 0.01 * o->tol_newton : o->tol_newton;
+    c.max_newton = o->max_newton;
+    c.mixed = mixed ? 1 : 0;
+    KrylovScalars& k = P->hks[b];
+    std::memset(&k, 0, sizeof(KrylovScalars));
+    k.done = 1;  // the first tick starts with the Newton step
+    k.tol2 = (om.fixed_lin > 0) ? 0.0 : om.tol_lin * om.tol_lin;
+    k.maxit = (om.fixed_lin > 0) ? om.fixed_lin : om.max_lin;
+  }
+  FG_HIP(hipMemcpyAsync(g.nc, B->hnc, nit * sizeof(NewtonCtl), hipMemcpyHostToDevice, P->stream));
+  FG_HIP(hipMemcpyAsync(P->ks, P->hks, nit * sizeof(KrylovScalars), hipMemcpyHostToDevice, P->stream));
+  const long n9 = 9 * N * nit;
+  if (P->prec == FG_FP64)
+    hipLaunchKernelGGL((k_fill<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, (double*)P->x, 0.0,
+                       n9);
+  else
+    hipLaunchKernelGGL((k_fill<float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, (float*)P->x, 0.0f,
+                       n9);
+  check_launch();
+  FG_HIP(hipStreamSynchronize(P->stream));  // pinned control blocks are reused
+}
+
+// <P> and statistics of a group after the solve; returns the first failure.
+void batch_epilogue(fg_batch* B, fg_batch::Group& g, double* P_avg, fg_stats* stats, fg_status& first,
+                    std::string& first_msg) {
+  fg_plan* P = g.P;
+  const int nit = P->nitems;
+  const long N = P->N;
+  constitutive(P, nullptr, P->S64, nullptr, nullptr);
+  const unsigned nb = blocks_for(N);
+  hipLaunchKernelGGL(k_mean9_partials, dim3(nb, (unsigned)nit), dim3(256), 0, P->stream, (const double*)P->S64,
+                     P->part2, N);
+  check_launch();
+  for (int k = 0; k < 9; ++k) reduce_items(P, P->part2 + (size_t)k * nit * nb, (int)nb, k);
+  FG_HIP(hipMemcpyAsync(B->hnc, g.nc, nit * sizeof(NewtonCtl), hipMemcpyDeviceToHost, P->stream));
+  sync_read(P);
+  const bool domain = P->hflags[0] & FG_FLAG_DOMAIN;
+  for (int b = 0; b < nit; ++b) {
+    const int rve = g.items[b].first, lc = g.items[b].second;
+    const long idx = (long)rve * B->n_cases + lc;
+    if (P_avg)
+      for (int k = 0; k < 9; ++k) P_avg[9 * idx + k] = item_value(P, k, b) / (double)N;
+    const NewtonCtl& c = B->hnc[b];
+    const KrylovScalars& h = P->hks[b];
+    if (stats) {
+      fg_stats& s = stats[idx];
+      std::memset(&s, 0, sizeof(fg_stats));
+      s.newton_iters = c.it;
+      s.lin_iters_total = c.lin_total;
+      s.lin_iters_last = c.lin_last;
+      s.n_history = c.n_hist;
+      s.err_res = c.err;
+      s.lin_relres = h.rr0 > 0 ? std::sqrt(h.rr / h.rr0) : 0.0;
+      for (int k = 0; k < std::min(c.n_hist, FG_NHIST); ++k) s.err_history[k] = c.err_hist[k];
+      for (int k = 0; k < std::min(c.it, FG_NHIST); ++k) s.lin_history[k] = c.lin_hist[k];
+    }
+    fg_status st = (fg_status)c.status;
+    if (st == FG_OK && !c.finished) st = FG_E_NOCONV;
+    if (st != FG_OK && first == FG_OK) {
+      first = st;
+      first_msg = "item (rve " + std::to_string(rve) + ", case " + std::to_string(lc) + "): " +
+                  (st == FG_E_BREAKDOWN ? "CG breakdown" : "Newton did not converge");
+    }
+  }
+  if (domain && first == FG_OK) {
+    first = FG_E_DOMAIN;
+    first_msg = "det F <= 0 or 1 + Omega c <= 0 in a batch item";
+  }
+}
+
+void batch_destroy_parts(fg_batch* B) {
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  for (auto& g : B->groups) {
+    if (g.P) fg_plan_destroy(g.P);
+    if (g.ev_join) (void)hipEventDestroy(g.ev_join);
+    if (g.s) (void)hipStreamDestroy(g.s);
+  }
+  if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+  if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+  if (B->s0) (void)hipStreamDestroy(B->s0);
+  if (B->hnc) (void)hipHostFree(B->hnc);
+  if (B->hactive) (void)hipHostFree(B->hactive);
+}
+
+}  // namespace
+
+extern "C" {
+
+fg_status fg_batch_create(int n_rve, const int* grids, const double* spacings, int n_cases, fg_precision prec,
+                          void* stream, fg_batch** out) {
+  if (!out) return FG_E_ARG;
+  *out = nullptr;
+  if (n_rve < 1 || n_cases < 1 || !grids || !spacings) return FG_E_ARG;
+  if (prec != FG_FP64 && prec != FG_MIXED) return FG_E_ARG;
+  fg_batch* B = new (std::nothrow) fg_batch();
+  if (!B) return FG_E_HIP;
+  B->n_rve = n_rve;
+  B->n_cases = n_cases;
+  B->prec = prec;
+  B->user = (hipStream_t)stream;
+  B->where.assign((size_t)n_rve * n_cases, {-1, -1});
+  B->have_mat.assign(n_rve, 0);
+  // group the items by grid and spacing, in RVE order
+  for (int r = 0; r < n_rve; ++r) {
+    const int* gr = grids + 3 * r;
+    const double* sp = spacings + 3 * r;
+    for (int lc = 0; lc < n_cases; ++lc) {
+      int gidx = -1;
+      for (size_t k = 0; k < B->groups.size(); ++k) {
+        const auto& g = B->groups[k];
+        if (g.grid[0] == gr[0] && g.grid[1] == gr[1] && g.grid[2] == gr[2] && g.h[0] == sp[0] && g.h[1] == sp[1] &&
+            g.h[2] == sp[2] && (int)g.items.size() < max_items_per_group(gr))
+          gidx = (int)k;
+      }
+      if (gidx < 0) {
+        fg_batch::Group g;
+        for (int k = 0; k < 3; ++k) {
+          g.grid[k] = gr[k];
+          g.h[k] = sp[k];
+        }
+        B->groups.push_back(g);
+        gidx = (int)B->groups.size() - 1;
+      }
+      auto& g = B->groups[gidx];
+      B->where[(size_t)r * n_cases + lc] = {gidx, (int)g.items.size()};
+      g.items.push_back({r, lc});
+    }
+  }
+  fg_status st = FG_OK;
+  int max_items = 1;
+  for (auto& g : B->groups) {
+    st = plan_new(g.grid, g.h, prec, nullptr, (int)g.items.size(), &g.P);
+    if (st != FG_OK) break;
+    if (hipStreamCreateWithFlags(&g.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming) != hipSuccess) {
+      st = FG_E_HIP;
+      break;
+    }
+    g.P->stream = g.s;
+    max_items = std::max(max_items, (int)g.items.size());
+  }
+  if (st == FG_OK && (hipStreamCreateWithFlags(&B->s0, hipStreamNonBlocking) != hipSuccess ||
+                      hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
+                      hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                      hipHostMalloc((void**)&B->hnc, max_items * sizeof(NewtonCtl), hipHostMallocDefault) !=
+                          hipSuccess ||
+                      hipHostMalloc((void**)&B->hactive, B->groups.size() * sizeof(int), hipHostMallocDefault) !=
+                          hipSuccess))
+    st = FG_E_HIP;
+  if (st != FG_OK) {
+    batch_destroy_parts(B);
+    delete B;
+    return st;
+  }
+  // workspace: per group the plan workspace, then E, nu, Omega, c (N each
+  // per item), F (9 N per item), the Newton control blocks and flags
+  size_t off = 0;
+  for (auto& g : B->groups) {
+    const long NT = g.P->N * g.P->nitems;
+    g.off = off;
+    g.plan_bytes = align_up(g.P->need);
+    size_t b = g.plan_bytes;
+    b += align_up(4 * NT * sizeof(double));
+    b += align_up(9 * NT * sizeof(double));
+    b += align_up(g.items.size() * sizeof(NewtonCtl));
+    b += align_up((g.items.size() + 64) * sizeof(int));
+    g.bytes = b;
+    off += b;
+  }
+  B->need = off + kAlign;
+  *out = B;
+  return FG_OK;
+}
+
+size_t fg_batch_workspace_bytes(const fg_batch* B) { return B ? B->need : 0; }
+
+int fg_batch_groups(const fg_batch* B) { return B ? (int)B->groups.size() : 0; }
+
+fg_status fg_batch_set_workspace(fg_batch* B, void* dev, size_t bytes) {
+  if (!B || !dev) return FG_E_ARG;
+  if (((uintptr_t)dev) % kAlign != 0) {
+    B->err = "workspace must be 256-byte aligned";
+    return FG_E_ARG;
+  }
+  if (bytes < B->need) {
+    B->err = "workspace too small";
+    return FG_E_SIZE;
+  }
+  return batch_run(B, [&]() {
+    B->ws = (char*)dev;
+    for (auto& g : B->groups) {
+      char* base = B->ws + g.off;
+      const fg_status st = fg_plan_set_workspace(g.P, base, g.plan_bytes);
+      if (st != FG_OK) throw Status(st, std::string("group workspace: ") + fg_last_error(g.P));
+      const long NT = g.P->N * g.P->nitems;
+      size_t o = g.plan_bytes;
+      g.E = reinterpret_cast<double*>(base + o);
+      g.nu = g.E + NT;
+      g.Om = g.nu + NT;
+      g.c = g.Om + NT;
+      o += align_up(4 * NT * sizeof(double));
+      g.F = reinterpret_cast<double*>(base + o);
+      o += align_up(9 * NT * sizeof(double));
+      g.nc = reinterpret_cast<NewtonCtl*>(base + o);
+      o += align_up(g.items.size() * sizeof(NewtonCtl));
+      g.idle = reinterpret_cast<int*>(base + o);
+      g.active = g.idle + g.items.size();
+      FG_HIP(hipMemsetAsync(g.c, 0, NT * sizeof(double), g.s));
+      FG_HIP(hipMemsetAsync(g.idle, 0, (g.items.size() + 64) * sizeof(int), g.s));
+      g.P->E = g.E;
+      g.P->nu = g.nu;
+      g.P->Om = g.Om;
+      g.P->c = g.c;
+      g.P->F = g.F;
+      g.P->gc = g.P->lc = g.P->RT = g.P->cmax = 1.0;
+      g.P->have_material = true;
+      FG_HIP(hipStreamSynchronize(g.s));
+    }
+    // a new workspace invalidates a captured graph
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->graph_ticks = 0;
+  });
+}
+
+fg_status fg_batch_set_material(fg_batch* B, int rve, const double* E, const double* nu, const double* Omega,
+                                const double* c) {
+  if (!B || !E || !nu || !Omega || rve < 0 || rve >= B->n_rve) return FG_E_ARG;
+  return batch_run(B, [&]() {
+    if (!B->ws) throw Status(FG_E_STATE, "workspace not set");
+    FG_HIP(hipEventRecord(B->ev_in, B->user));
+    for (int lc = 0; lc < B->n_cases; ++lc) {
+      const auto w = B->where[(size_t)rve * B->n_cases + lc];
+      auto& g = B->groups[w.first];
+      const long N = g.P->N;
+      const size_t nb = N * sizeof(double);
+      FG_HIP(hipStreamWaitEvent(g.s, B->ev_in, 0));
+      FG_HIP(hipMemcpyAsync(g.E + w.second * N, E, nb, hipMemcpyDeviceToDevice, g.s));
+      FG_HIP(hipMemcpyAsync(g.nu + w.second * N, nu, nb, hipMemcpyDeviceToDevice, g.s));
+      FG_HIP(hipMemcpyAsync(g.Om + w.second * N, Omega, nb, hipMemcpyDeviceToDevice, g.s));
+      if (c)
+        FG_HIP(hipMemcpyAsync(g.c + w.second * N, c, nb, hipMemcpyDeviceToDevice, g.s));
+      else
+        FG_HIP(hipMemsetAsync(g.c + w.second * N, 0, nb, g.s));
+      FG_HIP(hipStreamSynchronize(g.s));  // the caller may free or reuse its buffers
+    }
+    B->have_mat[rve] = 1;
+  });
+}
+
+fg_status fg_batch_newton_solve(fg_batch* B, const double* F_macro, const fg_solver_opts* opts, int graph_ticks,
+                                double* P_avg, fg_stats* stats) {
+  if (!B || !F_macro || !opts) return FG_E_ARG;
+  if (opts->max_lin <= 0 && opts->fixed_lin <= 0) return FG_E_ARG;
+  if (graph_ticks < 0) return FG_E_ARG;
+  return batch_run(B, [&]() {
+    if (!B->ws) throw Status(FG_E_STATE, "workspace not set");
+    for (int r = 0; r < B->n_rve; ++r)
+      if (!B->have_mat[r]) throw Status(FG_E_STATE, "material not set for every RVE");
+    FG_HIP(hipEventRecord(B->ev_in, B->user));
+    for (auto& g : B->groups) {
+      FG_HIP(hipStreamWaitEvent(g.s, B->ev_in, 0));
+      batch_prologue(B, g, F_macro, opts);
+    }
+    const int maxit = (opts->fixed_lin > 0) ? opts->fixed_lin : opts->max_lin;
+    // every Newton step takes at most maxit CG ticks and one tick of its own
+    const long cap = (long)(opts->max_newton + 1) * (maxit + 1) + 2;
+    const int per = graph_ticks > 0 ? graph_ticks : 8;
+    if (graph_ticks > 0) batch_capture(B, graph_ticks);
+    for (long ticks = 0; ticks < cap; ticks += per) {
+      if (graph_ticks > 0)
+        FG_HIP(hipGraphLaunch(B->exec, B->s0));
+      else
+        batch_enqueue(B, per);
+      for (size_t k = 0; k < B->groups.size(); ++k)
+        FG_HIP(hipMemcpyAsync(B->hactive + k, B->groups[k].active, sizeof(int), hipMemcpyDeviceToHost, B->s0));
+      FG_HIP(hipStreamSynchronize(B->s0));
+      int act = 0;
+      for (size_t k = 0; k < B->groups.size(); ++k) act += B->hactive[k];
+      if (act == 0) break;
+    }
+    fg_status first = FG_OK;
+    std::string msg;
+    for (auto& g : B->groups) batch_epilogue(B, g, P_avg, stats, first, msg);
+    if (first != FG_OK) throw Status(first, msg);
+  });
+}
+
+fg_status fg_batch_state(fg_batch* B, int rve, int lcase, double* F) {
+  if (!B || !F || rve < 0 || rve >= B->n_rve || lcase < 0 || lcase >= B->n_cases) return FG_E_ARG;
+  return batch_run(B, [&]() {
+    if (!B->ws) throw Status(FG_E_STATE, "workspace not set");
+    const auto w = B->where[(size_t)rve * B->n_cases + lcase];
+    auto& g = B->groups[w.first];
+    const long n9 = 9 * g.P->N;
+    FG_HIP(hipMemcpyAsync(F, g.F + w.second * n9, n9 * sizeof(double), hipMemcpyDeviceToDevice, g.s));
+    FG_HIP(hipStreamSynchronize(g.s));
+  });
+}
+
+const char* fg_batch_last_error(const fg_batch* B) { return B ? B->err.c_str() : "null batch"; }
+
+void fg_batch_destroy(fg_batch* B) {
+  if (!B) return;
+  batch_destroy_parts(B);
+  delete B;
 }
 
 }  // extern "C"

@@ -25,11 +25,27 @@ __global__ void __launch_bounds__(256)
 k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, const double* __restrict__ c,
                const double* __restrict__ d, const double* __restrict__ E, const double* __restrict__ nu,
                const double* __restrict__ Om, double* __restrict__ P, S* __restrict__ state,
-               double* __restrict__ pnorm_partials, int* __restrict__ flags, long N) {
+               double* __restrict__ pnorm_partials, int* __restrict__ flags, long N,
+               const int* __restrict__ idle) {
+  // voxel i of batch item b = blockIdx.y (item-major fields: material, c and
+  // d at b N + i, tensor fields at (9 b + k) N + i, Fu per item); items with
+  // idle[b] != 0 are left alone (idle may be nullptr); partial sums at
+  // b gridDim.x + blockIdx.x
   __shared__ double red[16];
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long b = blockIdx.y;
+  if (idle && idle[b]) return;
   double pp = 0.0;
   if (i < N) {
+    F += b * 9 * N;
+    if (Fu) Fu += 9 * b;
+    if (P) P += b * 9 * N;
+    if (state) state += b * 12 * N;
+    c += b * N;
+    d += b * N;
+    E += b * N;
+    nu += b * N;
+    Om += b * N;
     double f[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) f[k] = Fu ? Fu[k] : F[k * N + i];
@@ -81,7 +97,7 @@ k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, cons
   }
   if (pnorm_partials) {
     const double s = block_sum(pp, red);
-    if (threadIdx.x == 0) pnorm_partials[blockIdx.x] = s;
+    if (threadIdx.x == 0) pnorm_partials[b * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -236,7 +252,11 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ partia
 // mode 5: initialise a Krylov solve from rr0 = sum (b.b): rr = rr0, iter = 0.
 __global__ void __launch_bounds__(1024)
 k_finalize(const double* __restrict__ partials, int nparts, KrylovScalars* ks, double* out, int mode, int pcg) {
+  // one workgroup per batch item: nparts partials, scalars and output each
   __shared__ double red[16];
+  partials += (long)blockIdx.x * nparts;
+  if (ks) ks += blockIdx.x;
+  if (out) out += blockIdx.x;
   if (ks && ks->done && mode != 5 && mode != 2) return;
   const double s = sum_partials(partials, nparts, red);
   if (threadIdx.x != 0) return;
@@ -295,12 +315,14 @@ __global__ void __launch_bounds__(256) k_axpy_into_f64(double* __restrict__ F, c
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) F[i] += (double)x[i];
 }
 
-// F_k += dF_k for a uniform 3x3 increment.
-__global__ void __launch_bounds__(256) k_add_uniform9(double* __restrict__ F, const double* __restrict__ dF, long N) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// F_k += dF_k for a uniform 3x3 increment per batch item (dF: 9 per item).
+__global__ void __launch_bounds__(256) k_add_uniform9(double* __restrict__ F, const double* __restrict__ dF, long N,
+                                                      long Ntot) {
+  const long gi = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= Ntot) return;
+  const long b = gi / N, i = gi - b * N;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) F[k * N + i] += dF[k];
+  for (int k = 0; k < 9; ++k) F[(9 * b + k) * N + i] += dF[9 * b + k];
 }
 
 template <typename A, typename B>
@@ -380,15 +402,17 @@ k_adjoint_grad(const double* __restrict__ F, const double* __restrict__ c, const
   if (gO) gO[i] = sO * invN;
 }
 
-// Per-block partial sums of the 9 components of a tensor field (for <P>).
+// Per-block partial sums of the 9 components of a tensor field (for <P>),
+// batch item b = blockIdx.y: partials[(k gridDim.y + b) gridDim.x + block].
 __global__ void __launch_bounds__(256) k_mean9_partials(const double* __restrict__ P, double* __restrict__ partials,
                                                         long N) {
   __shared__ double red[16];
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long b = blockIdx.y;
   for (int k = 0; k < 9; ++k) {
-    const double v = (i < N) ? P[k * N + i] : 0.0;
+    const double v = (i < N) ? P[(9 * b + k) * N + i] : 0.0;
     const double s = block_sum(v, red);
-    if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) partials[((long)k * gridDim.y + b) * gridDim.x + blockIdx.x] = s;
   }
 }
 

@@ -25,6 +25,8 @@ EXPORTED = [
     "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
     "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_adjoint_gradient", "fg_residual", "fg_homogenized_stress", "fg_stress",
     "fg_apply_operator", "fg_project", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
+    "fg_batch_create", "fg_batch_workspace_bytes", "fg_batch_groups", "fg_batch_set_workspace",
+    "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
     "fg_profile_begin", "fg_profile_end", "fg_status_string", "fg_last_error", "fg_plan_destroy",
 ]
 PASS_NAMES = ["front", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive", "zscalar"]
@@ -109,6 +111,17 @@ def load_library(path=LIB_PATH):
         "fg_status_string": ([c_int], ctypes.c_char_p),
         "fg_last_error": ([vp], ctypes.c_char_p),
         "fg_plan_destroy": ([vp], None),
+        "fg_batch_create": ([c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_int, c_int, vp,
+                             ctypes.POINTER(vp)], c_int),
+        "fg_batch_workspace_bytes": ([vp], c_size),
+        "fg_batch_groups": ([vp], c_int),
+        "fg_batch_set_workspace": ([vp, vp, c_size], c_int),
+        "fg_batch_set_material": ([vp, c_int, dptr, dptr, dptr, dptr], c_int),
+        "fg_batch_newton_solve": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(SolverOpts), c_int,
+                                   ctypes.POINTER(c_double), ctypes.POINTER(Stats)], c_int),
+        "fg_batch_state": ([vp, c_int, c_int, dptr], c_int),
+        "fg_batch_last_error": ([vp], ctypes.c_char_p),
+        "fg_batch_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -280,3 +293,79 @@ class Plan:
         d = stats.to_dict()
         d["status"] = st
         return d
+
+
+class Batch:
+    """Batched Newton solves (fg_batch_*): RVEs of any supported grids times
+    macroscopic load cases.  Owns its workspace tensor; material arrays are
+    copied into the batch by set_material."""
+
+    def __init__(self, grids, spacings, n_cases, precision="fp64", stream=None, device="cuda"):
+        import torch
+
+        self.lib = load_library()
+        self.grids = [tuple(int(n) for n in g) for g in grids]
+        self.spacings = [tuple(float(h) for h in s) for s in spacings]
+        if len(self.grids) != len(self.spacings) or not self.grids:
+            raise ValueError("one grid and one spacing per RVE")
+        self.n_rve = len(self.grids)
+        self.n_cases = int(n_cases)
+        self.precision = precision
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        g = (ctypes.c_int * (3 * self.n_rve))(*[n for gr in self.grids for n in gr])
+        h = (ctypes.c_double * (3 * self.n_rve))(*[x for sp in self.spacings for x in sp])
+        out = ctypes.c_void_p()
+        st = self.lib.fg_batch_create(self.n_rve, g, h, self.n_cases, PRECISIONS[precision],
+                                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
+        if st != FG_OK:
+            raise FgError(st, f"fg_batch_create: {self.lib.fg_status_string(st).decode()}")
+        self.handle = out
+        nbytes = int(self.lib.fg_batch_workspace_bytes(self.handle))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._check(self.lib.fg_batch_set_workspace(self.handle, ctypes.c_void_p(self.workspace.data_ptr()),
+                                                     nbytes), "fg_batch_set_workspace")
+
+    @property
+    def n_groups(self):
+        return int(self.lib.fg_batch_groups(self.handle))
+
+    def _check(self, st, what):
+        if st != FG_OK:
+            msg = self.lib.fg_batch_last_error(self.handle).decode() if self.handle else ""
+            raise FgError(st, f"{what}: {self.lib.fg_status_string(st).decode()}: {msg}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_material(self, rve, E, nu, Omega, c=None):
+        self._check(self.lib.fg_batch_set_material(self.handle, int(rve), _ptr(E), _ptr(nu), _ptr(Omega), _ptr(c)),
+                    "fg_batch_set_material")
+
+    def newton_solve(self, F_macro, opts=None, graph_ticks=16, raise_on_error=True):
+        """Solve every (RVE, case) item.  F_macro: n_cases 3x3 tensors.
+        Returns (P_avg [n_rve, n_cases, 3, 3], list of per-item stats dicts
+        (rve-major), status)."""
+        opts = opts or make_opts()
+        Fm = np.ascontiguousarray(np.asarray(F_macro, dtype=np.float64).reshape(self.n_cases * 9))
+        P = np.zeros(self.n_rve * self.n_cases * 9)
+        stats = (Stats * (self.n_rve * self.n_cases))()
+        dp = ctypes.POINTER(ctypes.c_double)
+        st = self.lib.fg_batch_newton_solve(self.handle, Fm.ctypes.data_as(dp), ctypes.byref(opts), int(graph_ticks),
+                                            P.ctypes.data_as(dp), stats)
+        if raise_on_error:
+            self._check(st, "fg_batch_newton_solve")
+        return P.reshape(self.n_rve, self.n_cases, 3, 3), [s.to_dict() for s in stats], st
+
+    def state(self, rve, lcase, out):
+        self._check(self.lib.fg_batch_state(self.handle, int(rve), int(lcase), _ptr(out)), "fg_batch_state")
+        return out

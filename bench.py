@@ -16,6 +16,7 @@ refers to the kernel class with the largest time in the FP64 timed region;
 its average launch duration comes from HIP events on the plan stream.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--n 256] [--no-cpu]
+    python bench.py --batch [--batch-items 48] [--graph-ticks 16]   (batched form)
 """
 from __future__ import annotations
 
@@ -52,6 +53,12 @@ def parse():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--batch", action="store_true",
+                    help="the batched form instead: 48 ragged RVEs x 6 load cases (effective stiffness), batched "
+                         "FP64 and mixed against the 288 single-item FP64 solves")
+    ap.add_argument("--batch-items", type=int, default=48)
+    ap.add_argument("--graph-ticks", type=int, default=16)
+    ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 9 N doubles device-to-device 3 times (a plain copy kernel of known size, "
                          "for scaling HBM counters)")
@@ -177,14 +184,128 @@ def cpu_baseline(work, iters):
                        f"{el:.1f} s")
 
 
+def run_batch(args):
+    """Batched form: every (RVE, load case) item to tol_newton 1e-8 / CG 1e-10
+    from the reference state; batched FP64 and mixed (one captured graph per
+    form, warm solve first), then the same 288 solves one at a time with
+    single-item FP64 plans.  value = item solves per second of the batched
+    FP64 form."""
+    import torch
+
+    import synth
+    from paper_2411_16583_amd import Batch, Plan, make_opts
+    from paper_2411_16583_amd.homogenize import voigt_stiffness
+
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    items = synth.batch_workloads(args.batch_items)
+    eps = 1e-3
+    loads = items[0]["loads"]
+    ncase = len(loads)
+    Ns = [int(np.prod(w["shape"])) for w in items]
+    sizes = sorted(set(w["shape"][0] for w in items))
+    print(f"batch workload: {len(items)} RVEs, sizes {[(n, sum(w['shape'][0] == n for w in items)) for n in sizes]}, "
+          f"{sum(Ns)} voxels, built in {time.perf_counter() - t0:.1f} s", flush=True)
+    opts = make_opts(tol_newton=1e-8, tol_lin=1e-10, max_newton=50, max_lin=20000)
+    out = {}
+    for form in ("fp64", "mixed"):
+        b = Batch([w["shape"] for w in items], [w["spacing"] for w in items], ncase, form)
+        for k, w in enumerate(items):
+            b.set_material(k, t(w["E"]), t(w["nu"]), t(w["Omega"]))
+        b.newton_solve(loads, opts, graph_ticks=args.graph_ticks)  # warm: graph capture, first touch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P, stats, _ = b.newton_solve(loads, opts, graph_ticks=args.graph_ticks)
+        el = time.perf_counter() - t0
+        vi = sum(Ns[i // ncase] * s["lin_iters_total"] for i, s in enumerate(stats))
+        out[form] = dict(elapsed=el, P=P, voxel_iters=vi, groups=b.n_groups,
+                         newton=[s["newton_iters"] for s in stats], cg=sum(s["lin_iters_total"] for s in stats),
+                         err_max=max(s["err_res"] for s in stats))
+        print(f"[batch {form}] {el:.3f} s, {b.n_groups} groups, CG iterations {out[form]['cg']}, "
+              f"Newton {min(out[form]['newton'])}..{max(out[form]['newton'])}, max err_res {out[form]['err_max']:.1e}",
+              flush=True)
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    seq = None
+    if not args.no_sequential:
+        plans = []
+        for w in items:
+            pl = Plan(w["shape"], w["spacing"], "fp64")
+            mats = [t(w[k]) for k in ("E", "nu", "Omega")]
+            pl.set_material(*mats, None, None, gc=1.0, lc=1.0, RT=1.0, c_max=1.0)
+            F = torch.zeros((9,) + w["shape"], dtype=torch.float64, device=dev)
+            pl.set_state(F)
+            plans.append((pl, mats, F))
+        Pseq = np.zeros((len(items), ncase, 3, 3))
+        cg = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, (pl, mats, F) in enumerate(plans):
+            for lc, Fm in enumerate(loads):
+                F.zero_()
+                F[0] = 1.0
+                F[4] = 1.0
+                F[8] = 1.0
+                s = pl.newton_solve(Fm, opts)
+                cg += s["lin_iters_total"]
+                Pseq[k, lc] = pl.homogenized_stress()
+        el = time.perf_counter() - t0
+        seq = dict(elapsed=el, P=Pseq, cg=cg)
+        print(f"[sequential fp64] {el:.3f} s for {len(items) * ncase} solves, CG iterations {cg}", flush=True)
+        for pl, _, _ in plans:
+            pl.close()
+    ref = seq["P"] if seq else out["fp64"]["P"]
+    Cref = np.stack([voigt_stiffness(ref[k], eps) for k in range(len(items))])
+
+    def cdiff(P):
+        C = np.stack([voigt_stiffness(P[k], eps) for k in range(len(items))])
+        return float(np.max(np.abs(C - Cref)) / np.max(np.abs(Cref)))
+
+    nsolve = len(items) * ncase
+    f64, mx = out["fp64"], out["mixed"]
+    line = {
+        "metric": "batched effective-stiffness solves/s (48 ragged RVEs x 6 load cases, Newton 1e-8)",
+        "value": nsolve / f64["elapsed"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": 1e3 * f64["elapsed"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(items)} Boolean-sphere RVEs, N ~ U{{32,48,64,96}}, phi ~ U(0.1,0.4), "
+                               f"contrast 10, 6 load cases eps = 1e-3, from the reference state",
+                   "voxels": sum(Ns), "graph_ticks": args.graph_ticks, "groups": f64["groups"]},
+        "batched_fp64": dict(seconds=round(f64["elapsed"], 4), cg_iters=f64["cg"],
+                             voxel_cg_iters_per_s=f64["voxel_iters"] / f64["elapsed"],
+                             C_eff_rel_diff=cdiff(f64["P"]) if seq else 0.0),
+        "batched_mixed": dict(seconds=round(mx["elapsed"], 4), cg_iters=mx["cg"],
+                              voxel_cg_iters_per_s=mx["voxel_iters"] / mx["elapsed"],
+                              C_eff_rel_diff=cdiff(mx["P"]), speedup_vs_batched_fp64=f64["elapsed"] / mx["elapsed"]),
+    }
+    if seq:
+        line["sequential_fp64"] = dict(seconds=round(seq["elapsed"], 4), cg_iters=seq["cg"],
+                                       speedup_batched_fp64=seq["elapsed"] / f64["elapsed"],
+                                       speedup_batched_mixed=seq["elapsed"] / mx["elapsed"])
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hot path here is single-GPU "
-              "(sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(a sharded multi-GPU form is not implemented)", file=sys.stderr)
         sys.exit(2)
     import synth
 
+    if args.batch:
+        run_batch(args)
+        return
     t0 = time.perf_counter()
     work = synth.polydisperse_workload(n=args.n)
     N = int(np.prod(work["shape"]))

@@ -132,14 +132,20 @@ fg_status fg_newton_solve(fg_plan* plan, const double F_macro[9], const fg_solve
 fg_status fg_apply_macro(fg_plan* plan, const double F_macro[9]);
 
 /* Adjoint sensitivity of L = sum_ij w_ij <P_ij> at the current, converged
- * state (eq. (30) differentiated; see the derivation in the design doc): solves
- * G*(K : lam) = -G*(K : W) (W the uniform field w = dL_dPavg, host, 9
- * doubles) by CG with opts->tol_lin, then writes
+ * state (eq. (30) differentiated: the equilibrium operator is self-adjoint
+ * on compatible fields): solves G*(K : lam) = -G*(K : W) (W the uniform
+ * field w = dL_dPavg, host, 9 doubles) to ||r|| <= opts->tol_lin ||b||, then
+ * writes
  *   dL_dlogE[x]  = (W + lam(x)) : P(x) / N,
  *   dL_dOmega[x] = (W + lam(x)) : dP/dOmega(x) / N
- * (device, N doubles each, either may be NULL).  FG_FP64 plans only
- * (FG_E_ARG otherwise).  stats: lin_iters_last, lin_relres.  Errors:
- * FG_E_STATE, FG_E_NOCONV, FG_E_BREAKDOWN, FG_E_DOMAIN, FG_E_HIP. */
+ * (device, N doubles each, either may be NULL).  FG_FP64 plans solve by CG
+ * in double precision.  FG_MIXED plans refine lam in double precision:
+ * each step solves for a correction by CG with the single-precision
+ * operator (relative tolerance max(1e-5, what is left)) and recomputes the
+ * residual with the double-precision tangent.  stats: lin_iters_last,
+ * lin_relres (final ||r|| / ||b||); mixed plans also lin_iters_total and
+ * newton_iters = number of refinements.  Errors: FG_E_STATE, FG_E_NOCONV,
+ * FG_E_BREAKDOWN, FG_E_DOMAIN, FG_E_HIP. */
 fg_status fg_adjoint_gradient(fg_plan* plan, const double dL_dPavg[9], double* dL_dlogE, double* dL_dOmega,
                               const fg_solver_opts* opts, fg_stats* stats);
 
@@ -238,6 +244,44 @@ fg_status fg_batch_newton_solve(fg_batch* batch, const double* F_macro, const fg
 fg_status fg_batch_state(fg_batch* batch, int rve, int lcase, double* F);
 const char* fg_batch_last_error(const fg_batch* batch);
 void fg_batch_destroy(fg_batch* batch);
+
+/* Group g of a batch (items of one grid) as a plan handle owned by the
+ * batch: only the tile calls below accept it (others return FG_E_ARG) and
+ * fg_plan_destroy ignores it.  NULL for a bad index. */
+fg_plan* fg_batch_plan(fg_batch* batch, int group);
+/* Grid (3 ints) and item count of group g; 0, or -1 for a bad index. */
+int fg_batch_group_info(const fg_batch* batch, int group, int grid[3], int* nitems);
+
+/* ---------------------------------------------------------------------
+ * Tile widths of the two column passes, for the autotuner: the complex
+ * pass along N1 and the N0 pass fused with the projection of eq. (28) work
+ * on `tile` adjacent kx columns per workgroup.  Pass index `which`:
+ * 0 = N1 pass FP64, 1 = N0 projection pass FP64, 2 = N1 pass FP32,
+ * 3 = N0 projection pass FP32 (the single-precision passes run in FG_MIXED
+ * plans).  Valid tiles are powers of two dividing N2/2 with (threads per
+ * line) x tile <= 256 and the LDS of the workgroup within 64 KiB; 0 selects
+ * the built-in choice (the largest valid tile, ky-major for the projection
+ * passes).  Results do not depend on
+ * the tile: every column is transformed by the same arithmetic.  A tile of
+ * the projection passes (1, 3) may carry FG_TILE_KY_MAJOR: its workgroups are
+ * then ordered ky fastest instead of kx tile fastest. */
+enum { FG_TILE_KY_MAJOR = 0x10000 };
+/* Valid tiles of pass `which` into out[cap] (ascending, then for the
+ * projection passes the same widths with FG_TILE_KY_MAJOR); returns how many
+ * there are (may exceed cap), -1 on bad arguments. */
+int fg_plan_tile_candidates(const fg_plan* plan, int which, int* out, int cap);
+/* Set the four tiles (0 = built-in).  Errors: FG_E_ARG (invalid tile; the
+ * plan keeps its previous tiles). */
+fg_status fg_plan_set_tiles(fg_plan* plan, const int tiles[4]);
+/* The four tiles in use (built-in choice resolved). */
+fg_status fg_plan_get_tiles(const fg_plan* plan, int tiles[4]);
+/* Mean time in milliseconds of one launch of pass `which` with `tile`
+ * (0 = built-in) over all items of the plan, from reps launches after one
+ * warm-up, HIP events on the plan stream.  Overwrites the plan's spectral
+ * work buffer (state and material are untouched).  Synchronises.
+ * Errors: FG_E_ARG (bad pass or tile, FP32 pass on an FG_FP64 plan),
+ * FG_E_STATE (no workspace), FG_E_HIP. */
+fg_status fg_plan_time_pass(fg_plan* plan, int which, int tile, int reps, double* ms);
 
 /* Kernel classes timed by fg_profile_*: */
 enum {

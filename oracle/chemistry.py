@@ -14,7 +14,7 @@ forward-difference frequencies xi_j = (e^{i q_j} - 1)/h_j, div by the
 backward-difference frequencies -conj(xi_j) (their adjoint, so that
 div grad is the 7-point Laplacian).
 
-Readings (A9-A13):
+Readings of the paper taken here:
 * M(d) literal: the effective diffusivity at d = 0 is 0.9 D.
 * mu_e is re-derived from the chosen energy (the printed eq. (18) is
   garbled):  mu_e = dpsi_e/dc = -g Omega / (3 (1 + Omega c))

@@ -4,7 +4,7 @@ Kinematics: F = F_e F_c (eq. (1)), F_c = (1 + Omega c)^{1/3} I (eq. (2)).
 Damage degrades the elastic energy by g(d) = (1 - d)^2 (eq. (9)) and
 P = dpsi_e/dF (eq. (11)), P(F, c, d) = (1 - d)^2 P_0(F_e) (eq. (27)).
 
-Readings (listed in DESIGN.md as A1/A2):
+Readings of the paper taken here:
 * The hyperelastic law is the compressible Neo-Hookean energy
       psi_0(F_e) = G/2 (tr C_e - 3) - G ln J_e + lambda/2 (ln J_e)^2,
   C_e = F_e^T F_e, J_e = det F_e, with Lame constants (lambda, G) from

@@ -1,7 +1,7 @@
 """Dense real-space operators on tiny grids (brute force, no FFT).
 
 The rotated scheme is read as the 8-corner finite-difference gradient
-(Sec. 3.2; A3): nodal displacements u live at voxel corners, node
+(Sec. 3.2; the reading of the discretisation taken here): nodal displacements u live at voxel corners, node
 (i0, i1, i2) at the lower corner of voxel (i0, i1, i2); the gradient at a
 voxel centre along axis a is the mean over the four corner edges parallel
 to a of the edge difference divided by h_a.  The compatible fields are the

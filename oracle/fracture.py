@@ -11,7 +11,7 @@ constant-coefficient preconditioner (eq. (36))
     P(.) = F^{-1}{ F(.) / (g_c/l_c + 2 Hbar + xi.xi g_c l_c) },
 Hbar = mean(H).
 
-Readings (A4-A6, A20):
+Readings of the paper taken here:
 * xi.xi is the forward/backward finite-difference symbol
   lambda(q) = sum_j (2/h_j)^2 sin^2(q_j/2) (7-point Laplacian).
 * H carries the factor g_c/(2 l_c):  H = max(H_old, g_c/(2 l_c) D_f), which

@@ -7,7 +7,7 @@ Per time step:
      (Alg. 2) with the new stress -> d^{k+1}; stop when the equilibrium
      residual (eq. (31)) recomputed with d^{k+1} is <= tol_nw.
 
-Readings (A16, A21, A30): Alg. 4 tests "tol_mech" but declares
+Readings of the paper taken here: Alg. 4 tests "tol_mech" but declares
 tol_nw; we use tol_nw with at most 20 staggered iterations.  The history
 is updated as H <- max(H, D_f) at every PFF call, so staggered iterates
 count as intermediate states.

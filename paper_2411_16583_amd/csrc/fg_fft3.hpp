@@ -161,7 +161,7 @@ template <int L> using ZLine = typename ZLineSel<L>::type;
 
 template <typename R, int L>
 __global__ void __launch_bounds__(256)
-k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip) {
+k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor) {
   using C = cplx<R>;
   using LS = ZLine<L>;
   extern __shared__ char smem_raw[];
@@ -178,8 +178,11 @@ k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip
   __syncthreads();
   const int col = threadIdx.x % B;
   const int t = threadIdx.x / B;
-  const int kx = blockIdx.x * B + col;
-  const int ky = blockIdx.y;
+  // workgroup order: kx tiles fastest (grid M/B x N1), or ky fastest
+  // (grid N1 x M/B: consecutive workgroups then sit 16 M bytes apart
+  // instead of 16 B bytes, spreading concurrent accesses over the plane)
+  const int kx = (kymajor ? blockIdx.y : blockIdx.x) * B + col;
+  const int ky = kymajor ? blockIdx.x : blockIdx.y;
   const int i = blockIdx.z;
   const long plane = (long)N1 * M;
   const long comp = (long)L * plane;

@@ -50,8 +50,8 @@ int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb,
 
 template <typename R>
 void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
-                 const cplx<R>* tw, const Skip& skip, hipStream_t s) {
-  const int B = column_tile(L, M, (int)sizeof(cplx<R>));
+                 const cplx<R>* tw, const Skip& skip, hipStream_t s, int tile) {
+  const int B = tile > 0 ? tile : column_tile(L, M, (int)sizeof(cplx<R>));
   const int T = line_threads(L);
   const size_t shm = (size_t)L * B * sizeof(cplx<R>);
   dim3 grid((unsigned)(M / B), (unsigned)gy, (unsigned)gz);
@@ -73,16 +73,21 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 
 template <typename R>
 void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
-                  hipStream_t s, int nitems) {
+                  hipStream_t s, int nitems, int tile) {
   const int T = zline_threads(N0);
-  const int B = column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
+  // built-in choice (tile 0): the largest tile, workgroups ky fastest
+  const int kymajor = (tile == 0 || (tile & kTileKyMajor)) ? 1 : 0;
+  tile &= ~kTileKyMajor;
+  const int B = tile > 0 ? tile : column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
   const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zpass_extra_lds<R>(N0);
-  dim3 grid((unsigned)(M / B), (unsigned)N1, (unsigned)(3 * nitems));
+  dim3 grid = kymajor ? dim3((unsigned)N1, (unsigned)(M / B), (unsigned)(3 * nitems))
+                      : dim3((unsigned)(M / B), (unsigned)N1, (unsigned)(3 * nitems));
   dim3 gdc((unsigned)(N1 / 2 + 1), (unsigned)(3 * nitems), 1);
   switch (N0) {
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \
-    hipLaunchKernelGGL((k_fft_z_proj<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, skip); \
+    hipLaunchKernelGGL((k_fft_z_proj<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, skip, \
+                       kymajor);                                                                       \
     hipLaunchKernelGGL((k_fft_z_dc<R, L_, 0>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, skip); \
     return;
     FG_FOR_AXIS(FG_CASE)
@@ -136,8 +141,8 @@ int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const K
   template void launch_r2c<R>(int, const R*, R*, long, const SpecTables<R>&, const Skip&, hipStream_t); \
   template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t); \
   template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const Skip&, \
-                               hipStream_t);                                                            \
-  template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int); \
+                               hipStream_t, int);                                                       \
+  template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
   template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const Skip&, \
                                   hipStream_t);
 

@@ -30,14 +30,21 @@ void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb
 template <typename R>
 int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const C2REpi& epi,
                hipStream_t s);
+// tile: columns per workgroup (0: column_tile).
 template <typename R>
 void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
-                 const cplx<R>* tw, const Skip& skip, hipStream_t s);
+                 const cplx<R>* tw, const Skip& skip, hipStream_t s, int tile = 0);
 // N0 pass fused with the projection, for nitems 9-component fields (3 rows
 // each).
 template <typename R>
 void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
-                  hipStream_t s, int nitems = 1);
+                  hipStream_t s, int nitems = 1, int tile = 0);
+// Flag on a projection-pass tile: workgroups ordered ky fastest.
+constexpr int kTileKyMajor = 1 << 16;
+// Tile widths a pass accepts: powers of two dividing M with T tile <= 256
+// threads and an L x tile exchange buffer (plus the pass's tables) within
+// 64 KiB.  zproj: the fused N0 projection pass (L = N0), else the N1 pass.
+bool tile_valid(bool zproj, int L, int M, int elem_bytes, int tile);
 // N0 pass fused with a scalar symbol scale / (a0 + a1 lambda(q)), 1 component.
 template <typename R>
 void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0, double a1,

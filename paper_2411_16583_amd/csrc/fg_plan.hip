@@ -62,6 +62,18 @@ int zline_threads(int L) {
   return line_threads(L);
 }
 
+static_assert(kTileKyMajor == FG_TILE_KY_MAJOR, "public tile flag");
+
+bool tile_valid(bool zproj, int L, int M, int elem_bytes, int tile) {
+  if (zproj && (tile & kTileKyMajor)) tile &= ~kTileKyMajor;
+  if (tile < 1 || (tile & (tile - 1)) != 0 || M % tile != 0) return false;
+  const int T = zproj ? zline_threads(L) : line_threads(L);
+  if (T * tile > 256) return false;
+  // exchange buffer, plus the twiddles and kz tables of the projection pass
+  const long lds = (long)L * tile * elem_bytes + (zproj ? 2L * L * elem_bytes : 0L);
+  return lds <= 65536;
+}
+
 }  // namespace fg
 
 namespace {
@@ -99,6 +111,11 @@ struct fg_plan {
   int n0, n1, n2, M;
   long N;          // voxels per item
   int nitems = 1;  // batch items (independent solves on the same grid)
+  bool batch_group = false;  // owned by a batch: only the tile calls are public
+  // tile widths (columns per workgroup), 0 = heuristic:
+  // [0] N1 pass FP64, [1] N0 projection pass FP64, [2] N1 pass FP32, [3] N0 projection pass FP32
+  int tiles[4] = {0, 0, 0, 0};
+  int tiles_gen = 0;  // bumped by fg_plan_set_tiles (a captured batch graph is then stale)
   double h[3];
   fg_precision prec;
   hipStream_t stream;
@@ -321,6 +338,8 @@ inline double item_value(const fg_plan* P, int slot, int b) { return P->hd[64 + 
 template <typename R> const TablesDev<R>& tabs(const fg_plan* P);
 template <> const TablesDev<double>& tabs<double>(const fg_plan* P) { return P->t64; }
 template <> const TablesDev<float>& tabs<float>(const fg_plan* P) { return P->t32; }
+template <typename R> int tile_axis(const fg_plan* P) { return P->tiles[sizeof(R) == 8 ? 0 : 2]; }
+template <typename R> int tile_zproj(const fg_plan* P) { return P->tiles[sizeof(R) == 8 ? 1 : 3]; }
 
 // Forward passes 1 and 2 (N2 real-to-complex, N1 complex) of ncomp fields,
 // in -> data (in may equal data).  In a batch the ncomp fields are
@@ -335,7 +354,7 @@ void fwd_xy(fg_plan* P, const R* in, R* data, int ncomp, const Skip& skip) {
   }
   ProfScope ps(P, FG_PASS_AXIS);
   launch_axis<R>(P->n1, false, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1,
-                 skip.unit(cpi * P->n0), P->stream);
+                 skip.unit(cpi * P->n0), P->stream, tile_axis<R>(P));
 }
 
 // Inverse passes 2 and 1, data -> out with the C2R epilogue; returns #partials.
@@ -346,7 +365,7 @@ int inv_yx(fg_plan* P, R* data, R* out, int ncomp, const C2REpi& epi) {
   {
     ProfScope ps(P, FG_PASS_AXIS);
     launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 0, P->M, ncomp * P->n0, 1, tb.tw1,
-                   epi.skip.unit(cpi * P->n0), P->stream);
+                   epi.skip.unit(cpi * P->n0), P->stream, tile_axis<R>(P));
   }
   ProfScope ps(P, FG_PASS_C2R);
   C2REpi e = epi;
@@ -362,7 +381,7 @@ int project9(fg_plan* P, const R* in, R* work, R* out, const C2REpi& epi) {
   {
     ProfScope ps(P, FG_PASS_ZPROJ);
     launch_zproj<R>(P->n0, work, P->n1, P->M, tabs<R>(P).spec(), (R)(1.0 / (double)P->N), epi.skip.unit(3),
-                    P->stream, P->nitems);
+                    P->stream, P->nitems, tile_zproj<R>(P));
   }
   return inv_yx<R>(P, work, out, 9 * P->nitems, epi);
 }
@@ -465,16 +484,17 @@ void cg_iteration(fg_plan* P) {
   {
     ProfScope ps(P, FG_PASS_AXIS);
     launch_axis<T>(P->n1, false, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * nit, 1, tb.tw1,
-                   skip.unit(9L * P->n0), P->stream);
+                   skip.unit(9L * P->n0), P->stream, tile_axis<T>(P));
   }
   {
     ProfScope ps(P, FG_PASS_ZPROJ);
-    launch_zproj<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip.unit(3), P->stream, nit);
+    launch_zproj<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip.unit(3), P->stream, nit,
+                    tile_zproj<T>(P));
   }
   {
     ProfScope ps(P, FG_PASS_AXIS);
     launch_axis<T>(P->n1, true, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * nit, 1, tb.tw1,
-                   skip.unit(9L * P->n0), P->stream);
+                   skip.unit(9L * P->n0), P->stream, tile_axis<T>(P));
   }
   int nbc;
   {
@@ -653,6 +673,74 @@ void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_sol
   const double* d = P->d ? P->d : P->zeroN;
   hipLaunchKernelGGL((k_adjoint_grad<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu,
                      P->Om, (const T*)P->x, (const double*)P->Fu, gE, gO, P->flags, N);
+  check_launch();
+  sync_read(P);
+  check_domain(P);
+}
+
+// Mixed form of the adjoint: the system G*(K:lam) = -G*(K:W) is refined in
+// double precision, lam_{k+1} = lam_k + G*(d_k), where d_k solves
+// G*(K:d) = R_k by CG with the single-precision operator and
+//   R_k = -G*(G*(K:(W + lam_k)))
+// is the double-precision residual (K evaluated from F on the fly).  Stops
+// when ||R_k|| <= tol_lin ||R_0||, the criterion of the double-precision CG.
+// lam lives in the (otherwise unused) scalar-solver area.
+void adjoint_mixed(fg_plan* P, const double W[9], double* gE, double* gO, const fg_solver_opts* o,
+                   fg_stats* stats) {
+  const long N = P->N, n9 = 9 * N;
+  double* lam = P->sc;
+  const double* c = P->c ? P->c : P->zeroN;
+  const double* d = P->d ? P->d : P->zeroN;
+  constitutive(P, nullptr, nullptr, P->st, nullptr);  // single-precision state for the inner CG
+  FG_HIP(hipMemcpyAsync(P->Fu, W, 9 * sizeof(double), hipMemcpyHostToDevice, P->stream));
+  hipLaunchKernelGGL((k_fill<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, lam, 0.0, n9);
+  check_launch();
+  const unsigned nbN = blocks_for(N);
+  double rr0 = 0.0, rr = 0.0;
+  int refine = 0;
+  for (;; ++refine) {
+    hipLaunchKernelGGL(k_tangent_apply_f64, dim3(nbN), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu, P->Om,
+                       (const double*)P->Fu, (const double*)lam, P->S64, P->flags, N);
+    check_launch();
+    C2REpi e1{1.0, nullptr, true, nullptr, Skip{}};
+    project9<double>(P, P->S64, P->S64, P->S64, e1);
+    C2REpi e2{-1.0, nullptr, true, P->part, Skip{}};
+    const int nb = project9<double>(P, P->S64, P->S64, P->S64, e2);
+    // rr = R.R, and the inner CG starts from it (rr0 of the correction)
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
+    check_launch();
+    sync_read(P);
+    check_domain(P);
+    rr = P->hks[0].rr0;
+    if (refine == 0) rr0 = rr;
+    if (rr0 == 0.0 || std::sqrt(rr / rr0) <= o->tol_lin) break;
+    if (refine >= 30) throw Status(FG_E_NOCONV, "mixed adjoint: refinement did not converge");
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream,
+                       (float*)P->r, (const double*)P->S64, n9);
+    check_launch();
+    fg_solver_opts om = *o;
+    // the correction reduces R_k by 1e-5 at most (single-precision operator),
+    // and by no more than what is left to reach tol_lin ||R_0||
+    om.fixed_lin = 0;
+    om.tol_lin = std::max(1e-5, o->tol_lin * std::sqrt(rr0 / rr));
+    fg_stats inner{};
+    cg_solve<float>(P, &om, &inner);
+    if (stats) stats->lin_iters_total += inner.lin_iters_last;
+    // lam += G*(d) in double precision
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->S64,
+                       (const float*)P->x, n9);
+    project9<double>(P, P->S64, P->S64, P->S64, e1);
+    hipLaunchKernelGGL((k_axpy_into_f64<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, lam,
+                       (const double*)P->S64, n9);
+    check_launch();
+  }
+  if (stats) {
+    stats->newton_iters = refine;  // double-precision refinements
+    stats->lin_iters_last = stats->lin_iters_total;
+    stats->lin_relres = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
+  }
+  hipLaunchKernelGGL((k_adjoint_grad<double>), dim3(nbN), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu, P->Om,
+                     (const double*)lam, (const double*)P->Fu, gE, gO, P->flags, N);
   check_launch();
   sync_read(P);
   check_domain(P);
@@ -837,6 +925,9 @@ void apply_macro(fg_plan* P, const double F_macro[9]) {
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI --
+fg_status plan_set_workspace(fg_plan* P, void* dev, size_t bytes);
+void plan_delete(fg_plan* P);
+
 namespace {
 fg_status run(fg_plan* P, const std::function<void()>& fn) {
   try {
@@ -883,7 +974,7 @@ fg_status plan_new(const int grid[3], const double spacing[3], fg_precision prec
   if (hipHostMalloc((void**)&P->hks, (nitems + 1) * sizeof(KrylovScalars), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&P->hd, (64 + 16 * nitems) * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&P->hflags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
-    fg_plan_destroy(P);
+    plan_delete(P);
     return FG_E_HIP;
   }
   P->hksc = P->hks + nitems;
@@ -892,6 +983,7 @@ fg_status plan_new(const int grid[3], const double spacing[3], fg_precision prec
 }
 
 void need_ready(fg_plan* P, bool need_state) {
+  if (P->batch_group) throw Status(FG_E_ARG, "a batch group plan takes only the tile calls");
   if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
   if (!P->have_material) throw Status(FG_E_STATE, "material not set");
   if (need_state && !P->F) throw Status(FG_E_STATE, "state not set");
@@ -908,7 +1000,13 @@ fg_status fg_plan_create(const int grid[3], const double spacing[3], fg_precisio
 size_t fg_plan_workspace_bytes(const fg_plan* P) { return P ? P->need : 0; }
 
 fg_status fg_plan_set_workspace(fg_plan* P, void* dev, size_t bytes) {
-  if (!P || !dev) return FG_E_ARG;
+  if (!P || !dev || P->batch_group) return FG_E_ARG;
+  return plan_set_workspace(P, dev, bytes);
+}
+
+}  // extern "C"
+
+fg_status plan_set_workspace(fg_plan* P, void* dev, size_t bytes) {
   if (((uintptr_t)dev) % kAlign != 0) {
     P->err = "workspace must be 256-byte aligned";
     return FG_E_ARG;
@@ -935,9 +1033,11 @@ fg_status fg_plan_set_workspace(fg_plan* P, void* dev, size_t bytes) {
   });
 }
 
+extern "C" {
+
 fg_status fg_set_material(fg_plan* P, const double* E, const double* nu, const double* Omega, const double* D,
                           const double* sigma_max, double gc, double lc, double RT, double c_max) {
-  if (!P || !E || !nu || !Omega) return FG_E_ARG;
+  if (!P || !E || !nu || !Omega || P->batch_group) return FG_E_ARG;
   if (!(gc > 0) || !(lc > 0) || !(RT > 0) || !(c_max > 0)) {
     P->err = "gc, lc, RT and c_max must be positive";
     return FG_E_ARG;
@@ -956,7 +1056,7 @@ fg_status fg_set_material(fg_plan* P, const double* E, const double* nu, const d
 }
 
 fg_status fg_set_state(fg_plan* P, double* F, double* c, double* d, double* H) {
-  if (!P || !F) return FG_E_ARG;
+  if (!P || !F || P->batch_group) return FG_E_ARG;
   P->F = F;
   P->c = c;
   P->d = d;
@@ -991,9 +1091,11 @@ fg_status fg_adjoint_gradient(fg_plan* P, const double dL_dPavg[9], double* dL_d
   if (!dL_dlogE && !dL_dOmega) return FG_E_ARG;
   return run(P, [&]() {
     need_ready(P, true);
-    if (P->prec != FG_FP64) throw Status(FG_E_ARG, "the adjoint is built for FG_FP64 plans");
     if (stats) std::memset(stats, 0, sizeof(fg_stats));
-    adjoint<double>(P, dL_dPavg, dL_dlogE, dL_dOmega, opts, stats);
+    if (P->prec == FG_FP64)
+      adjoint<double>(P, dL_dPavg, dL_dlogE, dL_dOmega, opts, stats);
+    else
+      adjoint_mixed(P, dL_dPavg, dL_dlogE, dL_dOmega, opts, stats);
     FG_HIP(hipStreamSynchronize(P->stream));
   });
 }
@@ -1072,7 +1174,7 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
 }
 
 fg_status fg_project(fg_plan* P, const double* x, double* y) {
-  if (!P || !x || !y) return FG_E_ARG;
+  if (!P || !x || !y || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
     C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
@@ -1082,7 +1184,7 @@ fg_status fg_project(fg_plan* P, const double* x, double* y) {
 }
 
 fg_status fg_fft_r2c(fg_plan* P, double* data, int ncomp) {
-  if (!P || !data || ncomp <= 0) return FG_E_ARG;
+  if (!P || !data || ncomp <= 0 || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
     const SpecTables<double> tb = P->t64.spec();
@@ -1094,7 +1196,7 @@ fg_status fg_fft_r2c(fg_plan* P, double* data, int ncomp) {
 }
 
 fg_status fg_fft_c2r(fg_plan* P, double* data, int ncomp) {
-  if (!P || !data || ncomp <= 0) return FG_E_ARG;
+  if (!P || !data || ncomp <= 0 || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
     const SpecTables<double> tb = P->t64.spec();
@@ -1127,7 +1229,7 @@ fg_status fick_step(fg_plan* P, double dt, const double* cdot_B, const fg_solver
 }
 
 fg_status fg_profile_begin(fg_plan* P) {
-  if (!P) return FG_E_ARG;
+  if (!P || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     FG_HIP(hipStreamSynchronize(P->stream));
     P->prof_on = true;
@@ -1175,7 +1277,13 @@ const char* fg_status_string(fg_status s) {
 const char* fg_last_error(const fg_plan* P) { return P ? P->err.c_str() : "null plan"; }
 
 void fg_plan_destroy(fg_plan* P) {
-  if (!P) return;
+  if (!P || P->batch_group) return;  // a batch owns its group plans
+  plan_delete(P);
+}
+
+}  // extern "C"
+
+void plan_delete(fg_plan* P) {
   for (int k = 0; k < FG_NPASS; ++k)
     for (auto& e : P->prof_ev[k]) {
       (void)hipEventDestroy(e.first);
@@ -1186,8 +1294,6 @@ void fg_plan_destroy(fg_plan* P) {
   if (P->hflags) (void)hipHostFree(P->hflags);
   delete P;
 }
-
-}  // extern "C"
 
 // ------------------------------------------------------------ batched form --
 // Many independent (RVE, load case) items, possibly on different grids.
@@ -1224,6 +1330,7 @@ struct fg_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_ticks = 0;
+  std::vector<int> graph_gen;  // tiles_gen of each group at capture
   NewtonCtl* hnc = nullptr;  // pinned, max items of a group
   int* hactive = nullptr;    // pinned, one per group
   std::string err;
@@ -1321,7 +1428,9 @@ void batch_enqueue(fg_batch* B, int ticks) {
 }
 
 void batch_capture(fg_batch* B, int ticks) {
-  if (B->exec && B->graph_ticks == ticks) return;
+  std::vector<int> gen;
+  for (auto& g : B->groups) gen.push_back(g.P->tiles_gen);
+  if (B->exec && B->graph_ticks == ticks && gen == B->graph_gen) return;
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   B->exec = nullptr;
@@ -1338,6 +1447,7 @@ void batch_capture(fg_batch* B, int ticks) {
   FG_HIP(hipStreamEndCapture(B->s0, &B->graph));
   FG_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
   B->graph_ticks = ticks;
+  B->graph_gen = gen;
 }
 
 // Start of the solve for a group: F = F_macro of the item's load case
@@ -1447,7 +1557,7 @@ void batch_destroy_parts(fg_batch* B) {
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   for (auto& g : B->groups) {
-    if (g.P) fg_plan_destroy(g.P);
+    if (g.P) plan_delete(g.P);
     if (g.ev_join) (void)hipEventDestroy(g.ev_join);
     if (g.s) (void)hipStreamDestroy(g.s);
   }
@@ -1513,6 +1623,7 @@ fg_status fg_batch_create(int n_rve, const int* grids, const double* spacings, i
       break;
     }
     g.P->stream = g.s;
+    g.P->batch_group = true;
     max_items = std::max(max_items, (int)g.items.size());
   }
   if (st == FG_OK && (hipStreamCreateWithFlags(&B->s0, hipStreamNonBlocking) != hipSuccess ||
@@ -1566,7 +1677,7 @@ fg_status fg_batch_set_workspace(fg_batch* B, void* dev, size_t bytes) {
     B->ws = (char*)dev;
     for (auto& g : B->groups) {
       char* base = B->ws + g.off;
-      const fg_status st = fg_plan_set_workspace(g.P, base, g.plan_bytes);
+      const fg_status st = plan_set_workspace(g.P, base, g.plan_bytes);
       if (st != FG_OK) throw Status(st, std::string("group workspace: ") + fg_last_error(g.P));
       const long NT = g.P->N * g.P->nitems;
       size_t o = g.plan_bytes;
@@ -1676,12 +1787,129 @@ fg_status fg_batch_state(fg_batch* B, int rve, int lcase, double* F) {
   });
 }
 
+fg_plan* fg_batch_plan(fg_batch* B, int group) {
+  if (!B || group < 0 || group >= (int)B->groups.size()) return nullptr;
+  return B->groups[group].P;
+}
+
+int fg_batch_group_info(const fg_batch* B, int group, int grid[3], int* nitems) {
+  if (!B || group < 0 || group >= (int)B->groups.size()) return -1;
+  const auto& g = B->groups[group];
+  if (grid)
+    for (int k = 0; k < 3; ++k) grid[k] = g.grid[k];
+  if (nitems) *nitems = (int)g.items.size();
+  return 0;
+}
+
 const char* fg_batch_last_error(const fg_batch* B) { return B ? B->err.c_str() : "null batch"; }
 
 void fg_batch_destroy(fg_batch* B) {
   if (!B) return;
   batch_destroy_parts(B);
   delete B;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ tile tuning --
+namespace {
+struct TilePass {
+  bool zproj;
+  int elem;  // bytes of one complex value
+};
+TilePass tile_pass(int which) { return TilePass{(which & 1) != 0, (which < 2) ? 16 : 8}; }
+int tile_len(const fg_plan* P, int which) { return (which & 1) ? P->n0 : P->n1; }
+
+template <typename R>
+void time_pass_impl(fg_plan* P, bool zproj, int tile, int reps, double* ms) {
+  R* S = (sizeof(R) == 8) ? (R*)P->S64 : (R*)P->S;
+  const long n = 9 * P->N * P->nitems;
+  hipLaunchKernelGGL((k_fill<R>), dim3(grid_stride_blocks(n)), dim3(256), 0, P->stream, S, (R)1e-3, n);
+  check_launch();
+  const SpecTables<R> tb = tabs<R>(P).spec();
+  auto launch = [&]() {
+    if (zproj)
+      launch_zproj<R>(P->n0, S, P->n1, P->M, tb, (R)(1.0 / (double)P->N), Skip{}, P->stream, P->nitems, tile);
+    else
+      launch_axis<R>(P->n1, false, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * P->nitems, 1, tb.tw1, Skip{},
+                     P->stream, tile);
+  };
+  hipEvent_t e0, e1;
+  FG_HIP(hipEventCreate(&e0));
+  FG_HIP(hipEventCreate(&e1));
+  try {
+    launch();  // warm-up
+    FG_HIP(hipEventRecord(e0, P->stream));
+    for (int k = 0; k < reps; ++k) launch();
+    FG_HIP(hipEventRecord(e1, P->stream));
+    check_launch();
+    FG_HIP(hipEventSynchronize(e1));
+    float el = 0.f;
+    FG_HIP(hipEventElapsedTime(&el, e0, e1));
+    *ms = (double)el / reps;
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+}  // namespace
+
+extern "C" {
+
+int fg_plan_tile_candidates(const fg_plan* P, int which, int* out, int cap) {
+  if (!P || which < 0 || which > 3 || (cap > 0 && !out)) return -1;
+  const TilePass tp = tile_pass(which);
+  int n = 0;
+  for (int order = 0; order < (tp.zproj ? 2 : 1); ++order)
+    for (int b = 1; b <= 256; b *= 2)
+      if (fg::tile_valid(tp.zproj, tile_len(P, which), P->M, tp.elem, b)) {
+        if (n < cap) out[n] = b | (order ? fg::kTileKyMajor : 0);
+        ++n;
+      }
+  return n;
+}
+
+fg_status fg_plan_set_tiles(fg_plan* P, const int tiles[4]) {
+  if (!P || !tiles) return FG_E_ARG;
+  for (int w = 0; w < 4; ++w) {
+    const TilePass tp = tile_pass(w);
+    if (tiles[w] != 0 && !fg::tile_valid(tp.zproj, tile_len(P, w), P->M, tp.elem, tiles[w])) {
+      P->err = "tile width " + std::to_string(tiles[w]) + " not valid for pass " + std::to_string(w);
+      return FG_E_ARG;
+    }
+  }
+  for (int w = 0; w < 4; ++w) P->tiles[w] = tiles[w];
+  P->tiles_gen += 1;
+  return FG_OK;
+}
+
+fg_status fg_plan_get_tiles(const fg_plan* P, int tiles[4]) {
+  if (!P || !tiles) return FG_E_ARG;
+  for (int w = 0; w < 4; ++w) {
+    const TilePass tp = tile_pass(w);
+    const int L = tile_len(P, w);
+    const int T = tp.zproj ? fg::zline_threads(L) : fg::line_threads(L);
+    tiles[w] = P->tiles[w] > 0 ? P->tiles[w]
+                               : (fg::column_tile_t(T, L, P->M, tp.elem) | (tp.zproj ? fg::kTileKyMajor : 0));
+  }
+  return FG_OK;
+}
+
+fg_status fg_plan_time_pass(fg_plan* P, int which, int tile, int reps, double* ms) {
+  if (!P || which < 0 || which > 3 || reps < 1 || !ms) return FG_E_ARG;
+  const TilePass tp = tile_pass(which);
+  if (tile != 0 && !fg::tile_valid(tp.zproj, tile_len(P, which), P->M, tp.elem, tile)) return FG_E_ARG;
+  if (which >= 2 && P->prec != FG_MIXED) return FG_E_ARG;  // single-precision passes exist in mixed plans only
+  return run(P, [&]() {
+    if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
+    if (which < 2)
+      time_pass_impl<double>(P, tp.zproj, tile, reps, ms);
+    else
+      time_pass_impl<float>(P, tp.zproj, tile, reps, ms);
+  });
 }
 
 }  // extern "C"

@@ -10,16 +10,60 @@ namespace fg {
 
 constexpr int FG_FLAG_DOMAIN = 1;  // det F <= 0 or 1 + Omega c <= 0
 
-// Constitutive update (Sec. 2, eqs. (1), (2), (9), (11), (27); compressible
-// Neo-Hookean energy, energy per reference volume):
+// Compressible Neo-Hookean point (Sec. 2, eqs. (1), (2), (9), (11), (27);
+// energy per reference volume):
 //   s^-2 = (1 + Omega c)^{-2/3}, ln J_e = ln det F - ln(1 + Omega c),
 //   P = g [ G s^-2 F + (lambda ln J_e - G) F^-T ],  g = (1 - d)^2,
 // and the 12-word tangent state {A = F^-T, alpha = g G s^-2, beta = g lambda,
 // gamma = g (G - lambda ln J_e)} with which
 //   K : X = alpha X + beta (A : X) A + gamma A X^T A.
-// F is either the field F (9 planes) or, when Fu != nullptr, the uniform
-// tensor Fu.  P (FP64) may be nullptr; state (type S) may be nullptr.
-// pnorm_partials (optional) receives per-block sums of P : P.
+// ok = false when det F <= 0 or 1 + Omega c <= 0 (then J = 1 is used).
+struct NHPoint {
+  double A[9];
+  double c1, c2;             // P = c1 F + c2 A
+  double alpha, beta, gamma;  // tangent scalars
+  bool ok;
+};
+
+__device__ __forceinline__ NHPoint neo_hooke_point(const double (&f)[9], double cc, double dd, double EE, double nn,
+                                                   double oo) {
+  NHPoint q;
+  // cofactor matrix: F^-T = cof(F) / det F
+  double cof[9];
+  cof[0] = f[4] * f[8] - f[5] * f[7];
+  cof[1] = f[5] * f[6] - f[3] * f[8];
+  cof[2] = f[3] * f[7] - f[4] * f[6];
+  cof[3] = f[2] * f[7] - f[1] * f[8];
+  cof[4] = f[0] * f[8] - f[2] * f[6];
+  cof[5] = f[1] * f[6] - f[0] * f[7];
+  cof[6] = f[1] * f[5] - f[2] * f[4];
+  cof[7] = f[2] * f[3] - f[0] * f[5];
+  cof[8] = f[0] * f[4] - f[1] * f[3];
+  double J = f[0] * cof[0] + f[1] * cof[1] + f[2] * cof[2];
+  const double a = 1.0 + oo * cc;
+  q.ok = (J > 0.0) && (a > 0.0);
+  if (!q.ok) J = 1.0;
+  const double G = EE / (2.0 * (1.0 + nn));
+  const double lam = EE * nn / ((1.0 + nn) * (1.0 - 2.0 * nn));
+  const double g = (1.0 - dd) * (1.0 - dd);
+  const double la = log(a > 0.0 ? a : 1.0);
+  const double s2inv = exp(-2.0 / 3.0 * la);
+  const double lnJe = log(J) - la;
+  const double iJ = 1.0 / J;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) q.A[k] = cof[k] * iJ;
+  q.c1 = g * G * s2inv;
+  q.c2 = g * (lam * lnJe - G);
+  q.alpha = q.c1;
+  q.beta = g * lam;
+  q.gamma = g * (G - lam * lnJe);
+  return q;
+}
+
+// Constitutive update over the field: P (FP64) and the tangent state (type
+// S).  F is either the field F (9 planes) or, when Fu != nullptr, the uniform
+// tensor Fu.  P may be nullptr; state may be nullptr.  pnorm_partials
+// (optional) receives per-block sums of P : P.
 template <typename S>
 __global__ void __launch_bounds__(256)
 k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, const double* __restrict__ c,
@@ -49,56 +93,50 @@ k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, cons
     double f[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) f[k] = Fu ? Fu[k] : F[k * N + i];
-    // cofactor matrix: F^-T = cof(F) / det F
-    double cof[9];
-    cof[0] = f[4] * f[8] - f[5] * f[7];
-    cof[1] = f[5] * f[6] - f[3] * f[8];
-    cof[2] = f[3] * f[7] - f[4] * f[6];
-    cof[3] = f[2] * f[7] - f[1] * f[8];
-    cof[4] = f[0] * f[8] - f[2] * f[6];
-    cof[5] = f[1] * f[6] - f[0] * f[7];
-    cof[6] = f[1] * f[5] - f[2] * f[4];
-    cof[7] = f[2] * f[3] - f[0] * f[5];
-    cof[8] = f[0] * f[4] - f[1] * f[3];
-    double J = f[0] * cof[0] + f[1] * cof[1] + f[2] * cof[2];
-    const double cc = c[i], dd = d[i], EE = E[i], nn = nu[i], oo = Om[i];
-    const double a = 1.0 + oo * cc;
-    if (!(J > 0.0) || !(a > 0.0)) {
-      flags[0] = FG_FLAG_DOMAIN;
-      J = 1.0;
-    }
-    const double G = EE / (2.0 * (1.0 + nn));
-    const double lam = EE * nn / ((1.0 + nn) * (1.0 - 2.0 * nn));
-    const double g = (1.0 - dd) * (1.0 - dd);
-    const double la = log(a > 0.0 ? a : 1.0);
-    const double s2inv = exp(-2.0 / 3.0 * la);
-    const double lnJe = log(J) - la;
-    const double iJ = 1.0 / J;
-    double A[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) A[k] = cof[k] * iJ;
-    const double c1 = g * G * s2inv;
-    const double c2 = g * (lam * lnJe - G);
+    const NHPoint q = neo_hooke_point(f, c[i], d[i], E[i], nu[i], Om[i]);
+    if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
     if (P) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        const double pk = c1 * f[k] + c2 * A[k];
+        const double pk = q.c1 * f[k] + q.c2 * q.A[k];
         P[k * N + i] = pk;
         pp += pk * pk;
       }
     }
     if (state) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) state[k * N + i] = (S)A[k];
-      state[9 * N + i] = (S)c1;
-      state[10 * N + i] = (S)(g * lam);
-      state[11 * N + i] = (S)(g * (G - lam * lnJe));
+      for (int k = 0; k < 9; ++k) state[k * N + i] = (S)q.A[k];
+      state[9 * N + i] = (S)q.alpha;
+      state[10 * N + i] = (S)q.beta;
+      state[11 * N + i] = (S)q.gamma;
     }
   }
   if (pnorm_partials) {
     const double s = block_sum(pp, red);
     if (threadIdx.x == 0) pnorm_partials[b * gridDim.x + blockIdx.x] = s;
   }
+}
+
+// Y = K(F) : (W + X) in double precision with the tangent evaluated from F
+// on the fly (no stored state): W uniform (9, device), X a 9-plane field.
+__global__ void __launch_bounds__(256)
+k_tangent_apply_f64(const double* __restrict__ F, const double* __restrict__ c, const double* __restrict__ d,
+                    const double* __restrict__ E, const double* __restrict__ nu, const double* __restrict__ Om,
+                    const double* __restrict__ W, const double* __restrict__ X, double* __restrict__ Y,
+                    int* __restrict__ flags, long N) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double f[9], x[9], y[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    f[k] = F[k * N + i];
+    x[k] = W[k] + X[k * N + i];
+  }
+  const NHPoint q = neo_hooke_point(f, c[i], d[i], E[i], nu[i], Om[i]);
+  if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
+  tangent_apply<double>(q.A, q.alpha, q.beta, q.gamma, x, y);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Y[k * N + i] = y[k];
 }
 
 // CG direction update fused with the tangent contraction:

@@ -27,6 +27,8 @@ EXPORTED = [
     "fg_apply_operator", "fg_project", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
     "fg_batch_create", "fg_batch_workspace_bytes", "fg_batch_groups", "fg_batch_set_workspace",
     "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
+    "fg_batch_plan", "fg_batch_group_info", "fg_plan_tile_candidates", "fg_plan_set_tiles", "fg_plan_get_tiles",
+    "fg_plan_time_pass",
     "fg_profile_begin", "fg_profile_end", "fg_status_string", "fg_last_error", "fg_plan_destroy",
 ]
 PASS_NAMES = ["front", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive", "zscalar"]
@@ -122,6 +124,12 @@ def load_library(path=LIB_PATH):
         "fg_batch_state": ([vp, c_int, c_int, dptr], c_int),
         "fg_batch_last_error": ([vp], ctypes.c_char_p),
         "fg_batch_destroy": ([vp], None),
+        "fg_batch_plan": ([vp, c_int], vp),
+        "fg_batch_group_info": ([vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)], c_int),
+        "fg_plan_tile_candidates": ([vp, c_int, ctypes.POINTER(c_int), c_int], c_int),
+        "fg_plan_set_tiles": ([vp, ctypes.POINTER(c_int)], c_int),
+        "fg_plan_get_tiles": ([vp, ctypes.POINTER(c_int)], c_int),
+        "fg_plan_time_pass": ([vp, c_int, c_int, c_int, ctypes.POINTER(c_double)], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -273,6 +281,22 @@ class Plan:
         d["status"] = st
         return d
 
+    def autotune(self, cache_path=None, reps=10, force=False):
+        """Pick the tile widths of the column passes by timing them on this
+        plan (cached per architecture, grid and pass)."""
+        from .autotune import tune_plan
+
+        return tune_plan(self, cache_path, reps, force)
+
+    def tiles(self):
+        from .autotune import get_tiles
+
+        return get_tiles(self.handle, self.lib)
+
+    def set_tiles(self, tiles):
+        self._check(self.lib.fg_plan_set_tiles(self.handle, (ctypes.c_int * 4)(*[int(t) for t in tiles])),
+                    "fg_plan_set_tiles")
+
     def profile_begin(self):
         self._check(self.lib.fg_profile_begin(self.handle), "fg_profile_begin")
 
@@ -365,6 +389,11 @@ class Batch:
         if raise_on_error:
             self._check(st, "fg_batch_newton_solve")
         return P.reshape(self.n_rve, self.n_cases, 3, 3), [s.to_dict() for s in stats], st
+
+    def autotune(self, cache_path=None, reps=10, force=False):
+        from .autotune import tune_batch
+
+        return tune_batch(self, cache_path, reps, force)
 
     def state(self, rve, lcase, out):
         self._check(self.lib.fg_batch_state(self.handle, int(rve), int(lcase), _ptr(out)), "fg_batch_state")

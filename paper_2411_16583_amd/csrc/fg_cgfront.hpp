@@ -83,11 +83,11 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
         V xo = xv[k * Nv + g];
         xo.x += alpha * po[k].x;
         xo.y += alpha * po[k].y;
-        xv[k * Nv + g] = xo;
+        st_stream(xv + k * Nv + g, xo);
         pk.x = rk[k].x + beta * po[k].x;
         pk.y = rk[k].y + beta * po[k].y;
       }
-      pv[k * Nv + g] = pk;
+      st_stream(pv + k * Nv + g, pk);
       X0[k] = pk.x;
       X1[k] = pk.y;
     }
@@ -135,7 +135,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
       const C od = cscale(mul_mi(csub(zk, cconj(zm))), R(0.5));
       X = cadd(ev, cmul(od, tb.post[k]));
     }
-    if (active) dst[k] = X;
+    if (active) st_stream(dst + k, X);
   }
   const double s = block_sum(acc, red);
   if (tid == 0) partials[blockIdx.x] = s;

@@ -30,6 +30,15 @@ template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
 }
 template <typename C> __device__ __forceinline__ C cconj(C a) { return mk<C>(a.x, -a.y); }
 template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
+// Streaming store of one complex value (nontemporal: the line is not kept
+// in the caches for reuse; for write streams that are read back only by a
+// later kernel).
+template <typename C> __device__ __forceinline__ void st_stream(C* p, C v) {
+  using T = decltype(C::x);
+  typedef T nv2 __attribute__((ext_vector_type(2)));
+  nv2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<nv2*>(p));
+}
 // multiply by -i (forward quarter turn) / +i
 template <typename C> __device__ __forceinline__ C mul_mi(C a) { return mk<C>(a.y, -a.x); }
 template <typename C> __device__ __forceinline__ C mul_pi(C a) { return mk<C>(-a.y, a.x); }

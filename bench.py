@@ -38,9 +38,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # fields; the spectrum occupies the same bytes as the real field).
 WORDS_PER_VOXEL = {
     "front": 66,      # read r, p, x (27) + state (12); write x, p, spectrum (27)
-    "axis": 18,       # read 9, write 9 (per launch; 2 launches / iteration)
-    "zproj": 18,      # read 9, write 9
-    "c2r": 27,        # read spectrum 9 + r 9, write r 9
+    "axis": 18,       # N1 pass of the 9-component spectrum: read 9, write 9
+    "zproj": 12,      # N0 pass + projection to the potential: read 9, write 3
+    "axis3": 6,       # inverse N1 pass of the potential: read 3, write 3
+    "c2r3": 6,        # inverse N2 pass of the potential: read 3, write 3
+    "grad": 21,       # corner-stencil gradient + r -= alpha Ap: read U 3 + r 9, write r 9
 }
 
 
@@ -141,7 +143,22 @@ def roofline(res, N, word_bytes):
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 avg_launch_us=round(avg_s * 1e6, 2), launches=launches,
                 bytes_per_launch=bytes_per_launch,
-                breakdown_ms={k: round(v[0], 2) for k, v in prof.items()})
+                per_class=per_class(prof, N, word_bytes))
+
+
+def per_class(prof, N, word_bytes):
+    """Per kernel class: total ms, counted launches, mean us per launch and,
+    for the CG-iteration classes, algorithmic GB/s."""
+    out = {}
+    for k, (ms, n) in prof.items():
+        if n <= 0:
+            continue
+        avg = ms / n
+        d = {"ms": round(ms, 2), "launches": int(n), "avg_us": round(1e3 * avg, 1)}
+        if k in WORDS_PER_VOXEL:
+            d["GB/s"] = round(WORDS_PER_VOXEL[k] * word_bytes * N / (avg * 1e-3) / 1e9, 1)
+        out[k] = d
+    return out
 
 
 def cpu_baseline(work, iters):

@@ -171,6 +171,14 @@ fg_status fg_apply_operator(fg_plan* plan, const double* x, double* y);
  * precision (x, y: device, 9 N doubles; y may equal x).  Does not sync. */
 fg_status fg_project(fg_plan* plan, const double* x, double* y);
 
+/* The same projection computed as the CG iteration computes it: the N0
+ * pass reduces the 9-component spectrum to the 3-component potential
+ * U = -i e^{i Phi} (A r) / |r|^2 (Phi = (q0 + q1 + q2) / 2), only U is
+ * transformed back, and y = D U with D the corner-difference stencil of the
+ * rotated scheme (its symbol is i e^{-i Phi} r).  Double precision; x, y:
+ * device, 9 N doubles (y may equal x).  Does not synchronise. */
+fg_status fg_project_grad(fg_plan* plan, const double* x, double* y);
+
 /* 3-D real transform of ncomp scalar fields, double precision, in place:
  * fg_fft_r2c turns ncomp real fields (ncomp N doubles) into the packed half
  * spectrum (the same bytes: ncomp x N0 x N1 x N2/2 complex, where the kx = 0
@@ -288,13 +296,16 @@ enum {
   FG_PASS_FRONT = 0,        /* CG front: x, p updates, K:p, p.Kp, N2 pass  */
   FG_PASS_R2C = 1,          /* real-to-complex pass along N2 (residuals)   */
   FG_PASS_AXIS = 2,         /* complex pass along N1 (forward and inverse) */
-  FG_PASS_ZPROJ = 3,        /* N0 pass fused with the projection (main)    */
-  FG_PASS_C2R = 4,          /* N2 complex-to-real pass; in CG: r -= a Ap   */
+  FG_PASS_ZPROJ = 3,        /* N0 pass fused with the projection           */
+  FG_PASS_C2R = 4,          /* N2 complex-to-real pass (9 components)      */
   FG_PASS_CG_UPDATE = 5,    /* vector updates of the scalar PCGs           */
   FG_PASS_FINALIZE = 6,     /* one-block reductions of the Krylov scalars  */
   FG_PASS_CONSTITUTIVE = 7, /* stress and tangent state                    */
   FG_PASS_ZSCALAR = 8,      /* N0 pass fused with a scalar symbol          */
-  FG_NPASS = 9
+  FG_PASS_AXIS3 = 9,        /* inverse N1 pass of the 3-component potential */
+  FG_PASS_C2R3 = 10,        /* inverse N2 pass of the potential            */
+  FG_PASS_GRAD = 11,        /* corner-stencil gradient + r -= a Ap, r.r    */
+  FG_NPASS = 12
 };
 
 /* Time every launch of each kernel class with a HIP event pair on the plan

@@ -46,6 +46,7 @@ struct Skip {
   const int* gate = nullptr;  // nullptr: never skip
   int stride = 0;             // ints between the words of consecutive items
   long per_item = 1L << 62;   // grid units (lines, planes or rows) per item
+  long item_stride = 0;       // real passes: lines between the first lines of consecutive items (0: per_item)
   __host__ __device__ int item(long unit) const { return (int)(unit / per_item); }
   __device__ __forceinline__ bool operator()(long unit) const {
     return gate && gate[(long)item(unit) * stride] != 0;
@@ -92,7 +93,7 @@ __device__ __forceinline__ LineMap map_line(const Skip& sk, long nlines, int lpb
   const long bpi = (lpi + lpb - 1) / lpb;
   const long it = (long)blockIdx.x / bpi;
   const long lin = ((long)blockIdx.x - it * bpi) * lpb + ll;
-  return LineMap{it * lpi + lin, lin < lpi, (int)it};
+  return LineMap{it * (sk.item_stride > 0 ? sk.item_stride : lpi) + lin, lin < lpi, (int)it};
 }
 static_assert(sizeof(KrylovScalars) % sizeof(int) == 0, "gate stride");
 
@@ -230,6 +231,9 @@ template <typename R> struct SpecTables {
   const R* sy;          // (2/h1) sin(pi ky / N1)
   const R* cx;          // cos(pi kx / N2), kx = 0..M, exact 0 at kx = M
   const R* sx;          // (2/h2) sin(pi kx / N2)
+  const R* snz;         // sin(pi kz / N0)  (half-voxel phase factors e^{i q / 2})
+  const R* sny;         // sin(pi ky / N1)
+  const R* snx;         // sin(pi kx / N2), kx = 0..M
 };
 
 // ----------------------------------------------------------------------------
@@ -393,7 +397,7 @@ k_fft_axis(R* data, long estride, long ystride, long zstride, int B, const cplx<
   using LS = Line<L>;
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
-  if (skip(blockIdx.y)) return;
+  if (skip((long)blockIdx.y + (long)gridDim.y * blockIdx.z)) return;  // unit: plane (y) of line set (z)
   const int col = threadIdx.x % B;
   const int t = threadIdx.x / B;
   C* base = reinterpret_cast<C*>(data) + (long)blockIdx.y * ystride + (long)blockIdx.z * zstride +
@@ -487,149 +491,164 @@ k_fft_z_scalar(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, double 
 // (ky, -ky), transforms along N0, separates
 //   A(k) = (P(k) + conj P(-k)) / 2,   B(k) = (P(k) - conj P(-k)) / (2i),
 // applies the operator at qx = 0 to A and at qx = pi to B, and recombines.
-// OP = 0: projection (3 rows, grid.y = 3); OP = 1: scalar symbol.
+// OP = 0: projection, one row per workgroup (grid.y = 3 rows per item);
+// OP = 1: scalar symbol (grid.y = 1);
+// OP = 2: projection to the 3-component potential (see k_fft_z_grad3), the
+//         three rows of one item per workgroup (grid.y = items).
 template <typename R, int L, int OP>
 __global__ void __launch_bounds__(64)
 k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, Skip skip) {
   using C = cplx<R>;
   using LS = Line<L>;
-  constexpr int NC = (OP == 0) ? 3 : 1;
+  constexpr int NC = (OP == 1) ? 1 : 3;    // components read per row
+  constexpr int NROW = (OP == 2) ? 3 : 1;  // rows per workgroup
+  constexpr int NOUT = (OP == 0) ? 3 : 1;  // components written per row
   __shared__ C xbuf[2 * L];
   __shared__ C spec[NC * 2 * L];
   if (skip(blockIdx.y)) return;
   const int col = threadIdx.x % 2;
   const int t = threadIdx.x / 2;
-  if (t >= LS::T) {
-    // idle lanes still take part in every barrier below
-  }
+  // idle lanes (t >= T) still take part in every barrier below
   const bool lane_ok = t < LS::T;
   const int ky0 = blockIdx.x;
   const int ky1 = (N1 - ky0) % N1;
   const int myky = col ? ky1 : ky0;
-  const int i = blockIdx.y;
   const long plane = (long)N1 * M;
   const long comp = (long)L * plane;
   C* base = reinterpret_cast<C*>(data) + (long)myky * M;  // kx = 0
-  const int c0 = (OP == 0) ? 3 * i : 0;
-  for (int l = 0; l < NC; ++l) {
-    C v[LS::E];
+  const bool store = lane_ok && (col == 0 || ky1 != ky0);
+#pragma unroll 1
+  for (int row = 0; row < NROW; ++row) {
+    // first component read and written by this row
+    const int cin = (OP == 0) ? 3 * (int)blockIdx.y : (OP == 2) ? 9 * (int)blockIdx.y + 3 * row : 0;
+    const int cout = (OP == 2) ? 9 * (int)blockIdx.y + row : cin;
+    for (int l = 0; l < NC; ++l) {
+      C v[LS::E];
 #pragma unroll
-    for (int e = 0; e < LS::E; ++e)
-      v[e] = lane_ok ? base[(c0 + l) * comp + LS::idxA(t, e) * plane] : mk<C>(R(0), R(0));
-    if constexpr (LS::R2 == 1) {
-      Dft<LS::R1, 1, false, C>::run(v);
-    } else {
-      // same two-stage transform, guarded for the idle lanes
+      for (int e = 0; e < LS::E; ++e)
+        v[e] = lane_ok ? base[(cin + l) * comp + LS::idxA(t, e) * plane] : mk<C>(R(0), R(0));
+      if constexpr (LS::R2 == 1) {
+        Dft<LS::R1, 1, false, C>::run(v);
+      } else {
+        // same two-stage transform, guarded for the idle lanes
 #pragma unroll
-      for (int u = 0; u < LS::U; ++u) {
-        const int b = t + LS::T * u;
-        Dft<LS::R1, 1, false, C>::run(v + u * LS::R1);
+        for (int u = 0; u < LS::U; ++u) {
+          const int b = t + LS::T * u;
+          Dft<LS::R1, 1, false, C>::run(v + u * LS::R1);
 #pragma unroll
-        for (int k1 = 1; k1 < LS::R1; ++k1)
-          if (lane_ok) v[u * LS::R1 + k1] = twiddle_tab<false>(v[u * LS::R1 + k1], tb.tw0, (b * k1) % L);
-        if (lane_ok)
+          for (int k1 = 1; k1 < LS::R1; ++k1)
+            if (lane_ok) v[u * LS::R1 + k1] = twiddle_tab<false>(v[u * LS::R1 + k1], tb.tw0, (b * k1) % L);
+          if (lane_ok)
 #pragma unroll
-          for (int k1 = 0; k1 < LS::R1; ++k1) xbuf[(k1 * LS::R2 + b) * 2 + col] = v[u * LS::R1 + k1];
+            for (int k1 = 0; k1 < LS::R1; ++k1) xbuf[(k1 * LS::R2 + b) * 2 + col] = v[u * LS::R1 + k1];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < LS::V; ++w) {
+          const int k1 = t + LS::T * w;
+          if (lane_ok)
+#pragma unroll
+            for (int n2 = 0; n2 < LS::R2; ++n2) v[w * LS::R2 + n2] = xbuf[(k1 * LS::R2 + n2) * 2 + col];
+          Dft<LS::R2, 1, false, C>::run(v + w * LS::R2);
+        }
+        __syncthreads();
       }
-      __syncthreads();
+      if (lane_ok)
 #pragma unroll
-      for (int w = 0; w < LS::V; ++w) {
-        const int k1 = t + LS::T * w;
-        if (lane_ok)
-#pragma unroll
-          for (int n2 = 0; n2 < LS::R2; ++n2) v[w * LS::R2 + n2] = xbuf[(k1 * LS::R2 + n2) * 2 + col];
-        Dft<LS::R2, 1, false, C>::run(v + w * LS::R2);
-      }
-      __syncthreads();
+        for (int e = 0; e < LS::E; ++e) spec[(l * 2 + col) * L + LS::idxB(t, e)] = v[e];
     }
-    if (lane_ok)
-#pragma unroll
-      for (int e = 0; e < LS::E; ++e) spec[(l * 2 + col) * L + LS::idxB(t, e)] = v[e];
-  }
-  __syncthreads();
-  // separate, apply, recombine: thread (t, col) owns kz = idxB(t, e) of its column
-  C tA[LS::E], tB[LS::E];
-#pragma unroll
-  for (int e = 0; e < LS::E; ++e) {
-    tA[e] = mk<C>(R(0), R(0));
-    tB[e] = mk<C>(R(0), R(0));
-  }
-  if (lane_ok) {
+    __syncthreads();
+    // separate, apply, recombine: thread (t, col) owns kz = idxB(t, e) of its column
+    C tA[LS::E], tB[LS::E];
 #pragma unroll
     for (int e = 0; e < LS::E; ++e) {
-      const int kz = LS::idxB(t, e);
-      const int kzm = (L - kz) % L;
-      if constexpr (OP == 0) {
-        const RVec<R> rA = rot_vec(tb, kz, myky, 0);
-        const RVec<R> rB = rot_vec(tb, kz, myky, M);
-        for (int l = 0; l < 3; ++l) {
-          const C P = spec[(l * 2 + col) * L + kz];
-          const C Pm = spec[(l * 2 + (1 - col)) * L + kzm];
+      tA[e] = mk<C>(R(0), R(0));
+      tB[e] = mk<C>(R(0), R(0));
+    }
+    if (lane_ok) {
+#pragma unroll
+      for (int e = 0; e < LS::E; ++e) {
+        const int kz = LS::idxB(t, e);
+        const int kzm = (L - kz) % L;
+        if constexpr (OP != 1) {
+          const RVec<R> rA = rot_vec(tb, kz, myky, 0);
+          const RVec<R> rB = rot_vec(tb, kz, myky, M);
+          for (int l = 0; l < 3; ++l) {
+            const C P = spec[(l * 2 + col) * L + kz];
+            const C Pm = spec[(l * 2 + (1 - col)) * L + kzm];
+            const C A = cscale(cadd(P, cconj(Pm)), R(0.5));
+            const C Bv = cscale(mul_mi(csub(P, cconj(Pm))), R(0.5));
+            const R ra = rget(rA, l), rb = rget(rB, l);
+            tA[e] = mk<C>(tA[e].x + A.x * ra, tA[e].y + A.y * ra);
+            tB[e] = mk<C>(tB[e].x + Bv.x * rb, tB[e].y + Bv.y * rb);
+          }
+          const R a2 = rA.x * rA.x + rA.y * rA.y + rA.z * rA.z;
+          const R b2 = rB.x * rB.x + rB.y * rB.y + rB.z * rB.z;
+          tA[e] = cscale(tA[e], a2 > R(0) ? scale / a2 : R(0));
+          tB[e] = cscale(tB[e], b2 > R(0) ? scale / b2 : R(0));
+        } else {
+          const C P = spec[col * L + kz];
+          const C Pm = spec[(1 - col) * L + kzm];
           const C A = cscale(cadd(P, cconj(Pm)), R(0.5));
           const C Bv = cscale(mul_mi(csub(P, cconj(Pm))), R(0.5));
-          const R ra = rget(rA, l), rb = rget(rB, l);
-          tA[e] = mk<C>(tA[e].x + A.x * ra, tA[e].y + A.y * ra);
-          tB[e] = mk<C>(tB[e].x + Bv.x * rb, tB[e].y + Bv.y * rb);
+          const double dA = a0 + a1 * (double)lap_sym(tb, kz, myky, 0);
+          const double dB = a0 + a1 * (double)lap_sym(tb, kz, myky, M);
+          tA[e] = cscale(A, (R)((double)scale / dA));
+          tB[e] = cscale(Bv, (R)((double)scale / dB));
         }
-        const R a2 = rA.x * rA.x + rA.y * rA.y + rA.z * rA.z;
-        const R b2 = rB.x * rB.x + rB.y * rB.y + rB.z * rB.z;
-        tA[e] = cscale(tA[e], a2 > R(0) ? scale / a2 : R(0));
-        tB[e] = cscale(tB[e], b2 > R(0) ? scale / b2 : R(0));
-      } else {
-        const C P = spec[col * L + kz];
-        const C Pm = spec[(1 - col) * L + kzm];
-        const C A = cscale(cadd(P, cconj(Pm)), R(0.5));
-        const C Bv = cscale(mul_mi(csub(P, cconj(Pm))), R(0.5));
-        const double dA = a0 + a1 * (double)lap_sym(tb, kz, myky, 0);
-        const double dB = a0 + a1 * (double)lap_sym(tb, kz, myky, M);
-        tA[e] = cscale(A, (R)((double)scale / dA));
-        tB[e] = cscale(Bv, (R)((double)scale / dB));
       }
     }
-  }
-  const bool store = lane_ok && (col == 0 || ky1 != ky0);
-  for (int j = 0; j < NC; ++j) {
-    C v[LS::E];
+    for (int j = 0; j < NOUT; ++j) {
+      C v[LS::E];
 #pragma unroll
-    for (int e = 0; e < LS::E; ++e) {
-      R fa = R(1), fb = R(1);
-      if constexpr (OP == 0) {
+      for (int e = 0; e < LS::E; ++e) {
         const int kz = LS::idxB(t, e);
-        fa = rget(rot_vec(tb, kz, myky, 0), j);
-        fb = rget(rot_vec(tb, kz, myky, M), j);
+        if constexpr (OP == 0) {
+          const C a = cscale(tA[e], rget(rot_vec(tb, kz, myky, 0), j));
+          const C b = cscale(tB[e], rget(rot_vec(tb, kz, myky, M), j));
+          v[e] = cadd(a, mul_pi(b));  // A' + i B'
+        } else if constexpr (OP == 2) {
+          // potential U = -i e^{i Phi} w: at qx = 0, U_A = -i e^{i Phi_A} tA;
+          // at qx = pi, e^{i Phi_B} = i e^{i Phi_A}, so U_B = e^{i Phi_A} tB;
+          // packed as U_A + i U_B
+          const C ph = cmul(mk<C>(tb.cz[kz], tb.snz[kz]), mk<C>(tb.cy[myky], tb.sny[myky]));  // e^{i Phi_A}
+          const C a = mul_mi(cmul(tA[e], ph));
+          const C b = cmul(tB[e], ph);
+          v[e] = cadd(a, mul_pi(b));
+        } else {
+          v[e] = cadd(tA[e], mul_pi(tB[e]));
+        }
       }
-      const C a = cscale(tA[e], fa);
-      const C b = cscale(tB[e], fb);
-      v[e] = cadd(a, mul_pi(b));  // A' + i B'
+      if constexpr (LS::R2 == 1) {
+        Dft<LS::R1, 1, true, C>::run(v);
+      } else {
+#pragma unroll
+        for (int w = 0; w < LS::V; ++w) {
+          const int k1 = t + LS::T * w;
+          Dft<LS::R2, 1, true, C>::run(v + w * LS::R2);
+#pragma unroll
+          for (int n2 = 1; n2 < LS::R2; ++n2)
+            if (lane_ok) v[w * LS::R2 + n2] = twiddle_tab<true>(v[w * LS::R2 + n2], tb.tw0, (n2 * k1) % L);
+          if (lane_ok)
+#pragma unroll
+            for (int n2 = 0; n2 < LS::R2; ++n2) xbuf[(n2 * LS::R1 + k1) * 2 + col] = v[w * LS::R2 + n2];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < LS::U; ++u) {
+          const int n2 = t + LS::T * u;
+          if (lane_ok)
+#pragma unroll
+            for (int k1 = 0; k1 < LS::R1; ++k1) v[u * LS::R1 + k1] = xbuf[(n2 * LS::R1 + k1) * 2 + col];
+          Dft<LS::R1, 1, true, C>::run(v + u * LS::R1);
+        }
+        __syncthreads();
+      }
+      if (store)
+#pragma unroll
+        for (int e = 0; e < LS::E; ++e) base[(cout + j) * comp + LS::idxA(t, e) * plane] = v[e];
     }
-    if constexpr (LS::R2 == 1) {
-      Dft<LS::R1, 1, true, C>::run(v);
-    } else {
-#pragma unroll
-      for (int w = 0; w < LS::V; ++w) {
-        const int k1 = t + LS::T * w;
-        Dft<LS::R2, 1, true, C>::run(v + w * LS::R2);
-#pragma unroll
-        for (int n2 = 1; n2 < LS::R2; ++n2)
-          if (lane_ok) v[w * LS::R2 + n2] = twiddle_tab<true>(v[w * LS::R2 + n2], tb.tw0, (n2 * k1) % L);
-        if (lane_ok)
-#pragma unroll
-          for (int n2 = 0; n2 < LS::R2; ++n2) xbuf[(n2 * LS::R1 + k1) * 2 + col] = v[w * LS::R2 + n2];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < LS::U; ++u) {
-        const int n2 = t + LS::T * u;
-        if (lane_ok)
-#pragma unroll
-          for (int k1 = 0; k1 < LS::R1; ++k1) v[u * LS::R1 + k1] = xbuf[(n2 * LS::R1 + k1) * 2 + col];
-        Dft<LS::R1, 1, true, C>::run(v + u * LS::R1);
-      }
-      __syncthreads();
-    }
-    if (store)
-#pragma unroll
-      for (int e = 0; e < LS::E; ++e) base[(c0 + j) * comp + LS::idxA(t, e) * plane] = v[e];
+    __syncthreads();  // spec and xbuf are reused by the next row
   }
 }
 

@@ -97,6 +97,31 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
 }
 
 template <typename R>
+void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
+                  hipStream_t s, int nitems, int tile) {
+  const int T = zline_threads(N0);
+  const int kymajor = (tile == 0 || (tile & kTileKyMajor)) ? 1 : 0;
+  tile &= ~kTileKyMajor;
+  const int B = tile > 0 ? tile : column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
+  const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zgrad_extra_lds<R>(N0);
+  dim3 grid = kymajor ? dim3((unsigned)N1, (unsigned)(M / B), (unsigned)nitems)
+                      : dim3((unsigned)(M / B), (unsigned)N1, (unsigned)nitems);
+  dim3 gdc((unsigned)(N1 / 2 + 1), (unsigned)nitems, 1);
+  const Skip sk = skip.unit(1);  // grid.z (grad) and grid.y (kx = 0) index the item
+  switch (N0) {
+#define FG_CASE(L_)                                                                                    \
+  case L_:                                                                                             \
+    hipLaunchKernelGGL((k_fft_z_grad3<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, sk, \
+                       kymajor);                                                                       \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 2>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, sk); \
+    return;
+    FG_FOR_AXIS(FG_CASE)
+#undef FG_CASE
+  }
+  throw std::invalid_argument("unsupported N0");
+}
+
+template <typename R>
 void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0, double a1,
                     const Skip& skip, hipStream_t s) {
   const int B = column_tile(N0, M, (int)sizeof(cplx<R>));
@@ -143,6 +168,7 @@ int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const K
   template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const Skip&, \
                                hipStream_t, int);                                                       \
   template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
+  template void launch_zgrad<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
   template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const Skip&, \
                                   hipStream_t);
 

@@ -39,6 +39,11 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 template <typename R>
 void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
                   hipStream_t s, int nitems = 1, int tile = 0);
+// N0 pass fused with the projection in the potential form (3 components
+// written per item, slots 0..2), and its kx = 0 companion.
+template <typename R>
+void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
+                  hipStream_t s, int nitems = 1, int tile = 0);
 // Flag on a projection-pass tile: workgroups ordered ky fastest.
 constexpr int kTileKyMajor = 1 << 16;
 // Tile widths a pass accepts: powers of two dividing M with T tile <= 256

@@ -19,6 +19,7 @@
 #include "fg_cgfront.hpp"
 #include "fg_fft3.hpp"
 #include "fg_batch.hpp"
+#include "fg_cggrad.hpp"
 
 using namespace fg;
 
@@ -70,7 +71,8 @@ bool tile_valid(bool zproj, int L, int M, int elem_bytes, int tile) {
   const int T = zproj ? zline_threads(L) : line_threads(L);
   if (T * tile > 256) return false;
   // exchange buffer, plus the twiddles and kz tables of the projection pass
-  const long lds = (long)L * tile * elem_bytes + (zproj ? 2L * L * elem_bytes : 0L);
+  // (the potential form of the projection stages one more kz table)
+  const long lds = (long)L * tile * elem_bytes + (zproj ? 5L * L * elem_bytes / 2 : 0L);
   return lds <= 65536;
 }
 
@@ -102,7 +104,10 @@ template <typename R> struct TablesDev {
   cplx<R>* twM;
   cplx<R>* post;
   R *cz, *sz, *cy, *sy, *cx, *sx;
-  SpecTables<R> spec() const { return SpecTables<R>{tw0, tw1, twM, post, cz, sz, cy, sy, cx, sx}; }
+  R *snz, *sny, *snx;
+  SpecTables<R> spec() const {
+    return SpecTables<R>{tw0, tw1, twM, post, cz, sz, cy, sy, cx, sx, snz, sny, snx};
+  }
 };
 
 }  // namespace
@@ -190,6 +195,9 @@ size_t layout(fg_plan* P, char* base) {
     t.sy = carve<R>(base, off, n1);
     t.cx = carve<R>(base, off, M + 1);
     t.sx = carve<R>(base, off, M + 1);
+    t.snz = carve<R>(base, off, n0);
+    t.sny = carve<R>(base, off, n1);
+    t.snx = carve<R>(base, off, M + 1);
   };
   tabs(P->t64, double());
   tabs(P->t32, float());
@@ -255,22 +263,29 @@ template <typename R> void host_tables(const fg_plan* P, std::vector<char>& blob
     }
     put(dev.post, w.data(), P->M * sizeof(cplx<R>));
   }
-  auto half = [&](int n, int count, double h, void* cptr, void* sptr) {
-    std::vector<R> cc(count), ss(count);
+  // cos(q/2), (2/h) sin(q/2) and sin(q/2) at q = 2 pi m / n (the rotated
+  // vector and the half-voxel phase e^{i q/2} of the potential form)
+  auto half = [&](int n, int count, double h, void* cptr, void* sptr, void* nptr) {
+    std::vector<R> cc(count), ss(count), sn(count);
     for (int m = 0; m < count; ++m) {
       const long double a = PI * (long double)m / (long double)n;
       long double cv = std::cos(a), sv = std::sin(a);
       if (m == 0) sv = 0.0L;
-      if (2 * m == n) cv = 0.0L;  // exact zero at q = pi
+      if (2 * m == n) {
+        cv = 0.0L;  // exact values at q = pi
+        sv = 1.0L;
+      }
       cc[m] = (R)cv;
       ss[m] = (R)((2.0L / (long double)h) * sv);
+      sn[m] = (R)sv;
     }
     put(cptr, cc.data(), count * sizeof(R));
     put(sptr, ss.data(), count * sizeof(R));
+    put(nptr, sn.data(), count * sizeof(R));
   };
-  half(P->n0, P->n0, P->h[0], dev.cz, dev.sz);
-  half(P->n1, P->n1, P->h[1], dev.cy, dev.sy);
-  half(P->n2, P->M + 1, P->h[2], dev.cx, dev.sx);
+  half(P->n0, P->n0, P->h[0], dev.cz, dev.sz, dev.snz);
+  half(P->n1, P->n1, P->h[1], dev.cy, dev.sy, dev.sny);
+  half(P->n2, P->M + 1, P->h[2], dev.cx, dev.sx, dev.snx);
 }
 
 // Event pair around one launch of kernel class `pass` (no-op unless on).
@@ -451,17 +466,41 @@ int next_chunk(const KrylovScalars& h, long launched) {
 void note_noop_iterations(fg_plan* P, long noop) {
   if (!P->prof_on || noop <= 0) return;
   P->prof_noop[FG_PASS_FRONT] += noop;
-  P->prof_noop[FG_PASS_AXIS] += 2 * noop;
+  P->prof_noop[FG_PASS_AXIS] += noop;
   P->prof_noop[FG_PASS_ZPROJ] += noop;
-  P->prof_noop[FG_PASS_C2R] += noop;
+  P->prof_noop[FG_PASS_AXIS3] += noop;
+  P->prof_noop[FG_PASS_C2R3] += noop;
+  P->prof_noop[FG_PASS_GRAD] += noop;
   P->prof_noop[FG_PASS_FINALIZE] += 2 * noop;
+}
+
+// Inverse half of the projection in the potential form for all items: the
+// 3-component potential U (slots 0..2 of each item, spectral, written by
+// launch_zgrad) back to real space: N1 pass, then N2 complex-to-real.
+template <typename R>
+void inv_potential(fg_plan* P, R* data, const Skip& skip) {
+  const SpecTables<R> tb = tabs<R>(P).spec();
+  const long lines = (long)P->n0 * P->n1;
+  {
+    ProfScope ps(P, FG_PASS_AXIS3);
+    // planes y = component * N0 + i0 of one item, z = item (9 components apart)
+    launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 9L * P->n0 * P->n1 * P->M, P->M, 3 * P->n0,
+                   P->nitems, tb.tw1, skip.unit(3L * P->n0), P->stream, tile_axis<R>(P));
+  }
+  ProfScope ps(P, FG_PASS_C2R3);
+  Skip sk = skip.unit(3 * lines);
+  sk.item_stride = 9 * lines;
+  C2REpi epi{1.0, nullptr, true, nullptr, sk};
+  launch_c2r<R>(P->M, data, data, 3 * lines * P->nitems, tb, epi, P->stream);
 }
 
 // One CG iteration for every item of the plan (items whose solve is done
 // skip every kernel):
 //   x += alpha_{k-1} p_{k-1}; p = r + beta p; Y = K:p; p.Y; N2 pass of Y
-//   alpha = r.r / p.Kp; N1, N0 (+ projection), N1 passes;
-//   r -= alpha G(K p) fused with the inverse N2 pass, r.r; beta, convergence.
+//   alpha = r.r / p.Kp; N1 pass (9 components); N0 pass reducing the
+//   projection to the 3-component potential; N1 and N2 inverse passes of
+//   the potential; r -= alpha G(K p) with G(K p) = D U from the corner
+//   stencil, r.r; beta, convergence.
 template <typename T>
 void cg_iteration(fg_plan* P) {
   T* S = (T*)P->S;
@@ -488,23 +527,19 @@ void cg_iteration(fg_plan* P) {
   }
   {
     ProfScope ps(P, FG_PASS_ZPROJ);
-    launch_zproj<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip.unit(3), P->stream, nit,
-                    tile_zproj<T>(P));
+    launch_zgrad<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip, P->stream, nit, tile_zproj<T>(P));
   }
+  inv_potential<T>(P, S, skip);
+  const dim3 gg((unsigned)((P->N / 2 + 255) / 256), (unsigned)nit);
   {
-    ProfScope ps(P, FG_PASS_AXIS);
-    launch_axis<T>(P->n1, true, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * nit, 1, tb.tw1,
-                   skip.unit(9L * P->n0), P->stream, tile_axis<T>(P));
-  }
-  int nbc;
-  {
-    ProfScope ps(P, FG_PASS_C2R);
-    C2REpi epi{1.0, nullptr, true, P->part2, skip.unit(9 * lines), P->r, ks};
-    nbc = launch_c2r<T>(P->M, S, S, 9 * lines * nit, tb, epi, P->stream);
+    ProfScope ps(P, FG_PASS_GRAD);
+    hipLaunchKernelGGL((k_cg_grad<T>), gg, dim3(256), 0, P->stream, (const T*)S, (T*)P->r,
+                       (const KrylovScalars*)ks, P->part2, P->n0, P->n1, P->n2, (T)(1.0 / P->h[0]),
+                       (T)(1.0 / P->h[1]), (T)(1.0 / P->h[2]), 0);
   }
   {
     ProfScope ps(P, FG_PASS_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3(nit), dim3(1024), 0, P->stream, P->part2, nbc / nit, ks, (double*)nullptr,
+    hipLaunchKernelGGL(k_finalize, dim3(nit), dim3(1024), 0, P->stream, P->part2, (int)gg.x, ks, (double*)nullptr,
                        1, 0);
   }
   check_launch();
@@ -1183,6 +1218,21 @@ fg_status fg_project(fg_plan* P, const double* x, double* y) {
   });
 }
 
+fg_status fg_project_grad(fg_plan* P, const double* x, double* y) {
+  if (!P || !x || !y || P->batch_group) return FG_E_ARG;
+  return run(P, [&]() {
+    if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
+    fwd_xy<double>(P, x, P->S64, 9, Skip{});
+    launch_zgrad<double>(P->n0, P->S64, P->n1, P->M, P->t64.spec(), 1.0 / (double)P->N, Skip{}, P->stream, 1,
+                         tile_zproj<double>(P));
+    inv_potential<double>(P, P->S64, Skip{});
+    hipLaunchKernelGGL((k_cg_grad<double>), dim3((unsigned)((P->N / 2 + 255) / 256), 1), dim3(256), 0, P->stream,
+                       (const double*)P->S64, y, (const KrylovScalars*)nullptr, (double*)nullptr, P->n0, P->n1,
+                       P->n2, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2], 1);
+    check_launch();
+  });
+}
+
 fg_status fg_fft_r2c(fg_plan* P, double* data, int ncomp) {
   if (!P || !data || ncomp <= 0 || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
@@ -1829,7 +1879,7 @@ void time_pass_impl(fg_plan* P, bool zproj, int tile, int reps, double* ms) {
   const SpecTables<R> tb = tabs<R>(P).spec();
   auto launch = [&]() {
     if (zproj)
-      launch_zproj<R>(P->n0, S, P->n1, P->M, tb, (R)(1.0 / (double)P->N), Skip{}, P->stream, P->nitems, tile);
+      launch_zgrad<R>(P->n0, S, P->n1, P->M, tb, (R)(1.0 / (double)P->N), Skip{}, P->stream, P->nitems, tile);
     else
       launch_axis<R>(P->n1, false, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * P->nitems, 1, tb.tw1, Skip{},
                      P->stream, tile);

@@ -24,14 +24,15 @@ PRECISIONS = {"fp64": FG_FP64, "mixed": FG_MIXED}
 EXPORTED = [
     "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
     "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_adjoint_gradient", "fg_residual", "fg_homogenized_stress", "fg_stress",
-    "fg_apply_operator", "fg_project", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
+    "fg_apply_operator", "fg_project", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
     "fg_batch_create", "fg_batch_workspace_bytes", "fg_batch_groups", "fg_batch_set_workspace",
     "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
     "fg_batch_plan", "fg_batch_group_info", "fg_plan_tile_candidates", "fg_plan_set_tiles", "fg_plan_get_tiles",
     "fg_plan_time_pass",
     "fg_profile_begin", "fg_profile_end", "fg_status_string", "fg_last_error", "fg_plan_destroy",
 ]
-PASS_NAMES = ["front", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive", "zscalar"]
+PASS_NAMES = ["front", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive", "zscalar", "axis3",
+              "c2r3", "grad"]
 
 
 class SolverOpts(ctypes.Structure):
@@ -104,6 +105,7 @@ def load_library(path=LIB_PATH):
         "fg_stress": ([vp, dptr], c_int),
         "fg_apply_operator": ([vp, dptr, dptr], c_int),
         "fg_project": ([vp, dptr, dptr], c_int),
+        "fg_project_grad": ([vp, dptr, dptr], c_int),
         "fg_fft_r2c": ([vp, dptr, c_int], c_int),
         "fg_fft_c2r": ([vp, dptr, c_int], c_int),
         "pff_solve": ([vp, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
@@ -261,6 +263,10 @@ class Plan:
 
     def project(self, x, y):
         self._check(self.lib.fg_project(self.handle, _ptr(x), _ptr(y)), "fg_project")
+        return y
+
+    def project_grad(self, x, y):
+        self._check(self.lib.fg_project_grad(self.handle, _ptr(x), _ptr(y)), "fg_project_grad")
         return y
 
     def fft_r2c(self, data, ncomp):

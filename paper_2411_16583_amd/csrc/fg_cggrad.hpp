@@ -8,8 +8,8 @@
 //   mode 0 (CG):  r <- r - alpha D U (alpha of the item), per-block partial
 //                 sums of the new r . r;
 //   mode 1:       r <- D U (the projection itself; r is the output).
-// U: component slots 0..2 of the item's 9-component buffer (real after the
-// inverse passes).  Grid (ceil(N / 512), items), one thread per voxel pair
+// U: component slots 0, 3, 6 of the item's 9-component buffer (real after
+// the inverse passes).  Grid (ceil(N / 512), items), one thread per voxel pair
 // (x, x + 1) along N2 (N2 even).
 #pragma once
 #include "fg_fft.hpp"
@@ -46,7 +46,7 @@ k_cg_grad(const T* __restrict__ U, T* __restrict__ r, const KrylovScalars* __res
     const long gv = line * M + x / 2;  // voxel pair index of (line, x)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T* Uc = U + c * N;
+      const T* Uc = U + 3 * c * N;
       // u[a][b][p]: corner values at x - 1, x, x + 1 (p = 0, 1, 2)
       T u[2][2][3];
 #pragma unroll

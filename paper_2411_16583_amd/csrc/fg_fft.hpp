@@ -47,6 +47,7 @@ struct Skip {
   int stride = 0;             // ints between the words of consecutive items
   long per_item = 1L << 62;   // grid units (lines, planes or rows) per item
   long item_stride = 0;       // real passes: lines between the first lines of consecutive items (0: per_item)
+  int sub = 1;                // real passes: per_item counts sub-items, sub of them per gated item
   __host__ __device__ int item(long unit) const { return (int)(unit / per_item); }
   __device__ __forceinline__ bool operator()(long unit) const {
     return gate && gate[(long)item(unit) * stride] != 0;
@@ -72,7 +73,7 @@ struct Skip {
     s.per_item = per;
     return s;
   }
-  __device__ __forceinline__ bool masked(int item) const { return gate && gate[(long)item * stride] != 0; }
+  __device__ __forceinline__ bool masked(int item) const { return gate && gate[(long)(item / sub) * stride] != 0; }
   // Workgroups of lpb lines over nlines lines (per_item lines per item) that
   // never straddle two items: ceil(lines per item / lpb) workgroups per item.
   __host__ __device__ long item_lines(long nlines) const { return per_item < nlines ? per_item : nlines; }
@@ -493,15 +494,14 @@ k_fft_z_scalar(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, double 
 // applies the operator at qx = 0 to A and at qx = pi to B, and recombines.
 // OP = 0: projection, one row per workgroup (grid.y = 3 rows per item);
 // OP = 1: scalar symbol (grid.y = 1);
-// OP = 2: projection to the 3-component potential (see k_fft_z_grad3), the
-//         three rows of one item per workgroup (grid.y = items).
+// OP = 2: projection to the 3-component potential (see k_fft_z_grad3), one
+//         row per workgroup (grid.y = 3 rows per item), U_i into slot 3 i.
 template <typename R, int L, int OP>
 __global__ void __launch_bounds__(64)
 k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, Skip skip) {
   using C = cplx<R>;
   using LS = Line<L>;
   constexpr int NC = (OP == 1) ? 1 : 3;    // components read per row
-  constexpr int NROW = (OP == 2) ? 3 : 1;  // rows per workgroup
   constexpr int NOUT = (OP == 0) ? 3 : 1;  // components written per row
   __shared__ C xbuf[2 * L];
   __shared__ C spec[NC * 2 * L];
@@ -517,11 +517,10 @@ k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double 
   const long comp = (long)L * plane;
   C* base = reinterpret_cast<C*>(data) + (long)myky * M;  // kx = 0
   const bool store = lane_ok && (col == 0 || ky1 != ky0);
-#pragma unroll 1
-  for (int row = 0; row < NROW; ++row) {
-    // first component read and written by this row
-    const int cin = (OP == 0) ? 3 * (int)blockIdx.y : (OP == 2) ? 9 * (int)blockIdx.y + 3 * row : 0;
-    const int cout = (OP == 2) ? 9 * (int)blockIdx.y + row : cin;
+  {
+    // first component read and written by this workgroup's row
+    const int cin = (OP == 1) ? 0 : 3 * (int)blockIdx.y;
+    const int cout = cin;
     for (int l = 0; l < NC; ++l) {
       C v[LS::E];
 #pragma unroll
@@ -648,7 +647,6 @@ k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double 
 #pragma unroll
         for (int e = 0; e < LS::E; ++e) base[(cout + j) * comp + LS::idxA(t, e) * plane] = v[e];
     }
-    __syncthreads();  // spec and xbuf are reused by the next row
   }
 }
 

@@ -234,4 +234,85 @@ k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip
 }
 
 
+// LDS bytes of k_fft_z_grad3 beyond the L x B exchange buffer: the stage
+// twiddles and three kz tables (cos, scaled sin, sin).
+template <typename R> constexpr size_t zgrad_extra_lds(int L) {
+  return (size_t)L * sizeof(cplx<R>) + 3 * (size_t)L * sizeof(R);
+}
+
+// N0 pass fused with the projection, potential form (eq. (28) with the
+// rotated scheme).  The projected field Z_ij = w_i r_j, w_i = (sum_l A_il r_l)
+// scale / |r|^2, is the corner-stencil gradient of the 3-component potential
+// U_i = -i e^{i Phi} w_i, Phi = (q0 + q1 + q2) / 2: the stencil
+//   (D_j U)[n] = 1/(4 h_j) sum over the 4 edges of the voxel parallel to j
+//                of the corner difference (corner n - 1/2 stored at n - 1)
+// has the symbol i e^{-i Phi} r_j.  Only U is transformed back (one inverse
+// per row instead of three); U_i is stored in component slot 3 i of the item
+// (the slot of A_i0, which only this workgroup reads for its columns), and
+// the gradient is formed in real space by k_cg_grad.  Grid (M/B, N1, 3 rows
+// per item), or (N1, M/B, rows) with kymajor.  The kx = 0 column is left to
+// k_fft_z_dc<OP = 2>.
+template <typename R, int L>
+__global__ void __launch_bounds__(256)
+k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor) {
+  using C = cplx<R>;
+  using LS = ZLine<L>;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C* stw = lds + L * B;
+  R* scz = reinterpret_cast<R*>(stw + L);
+  R* ssz = scz + L;
+  R* snz = ssz + L;
+  if (skip(blockIdx.z)) return;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    stw[k] = tb.tw0[k];
+    scz[k] = tb.cz[k];
+    ssz[k] = tb.sz[k];
+    snz[k] = tb.snz[k];
+  }
+  __syncthreads();
+  const int col = threadIdx.x % B;
+  const int t = threadIdx.x / B;
+  const int kx = (kymajor ? blockIdx.y : blockIdx.x) * B + col;
+  const int ky = kymajor ? blockIdx.x : blockIdx.y;
+  const int i = blockIdx.z;  // row of the 3x3 field, items consecutive
+  const long plane = (long)N1 * M;
+  const long comp = (long)L * plane;
+  const R cy = tb.cy[ky], sy = tb.sy[ky], cx = tb.cx[kx], sx = tb.sx[kx];
+  const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
+  // -i e^{i (qy + qx) / 2}; the kz factor is applied per element
+  const C eyx = mul_mi(cmul(mk<C>(cy, tb.sny[ky]), mk<C>(cx, tb.snx[kx])));
+  C* base = reinterpret_cast<C*>(data) + (long)(3 * i) * comp + (long)ky * M + kx;
+  C acc[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) acc[e] = mk<C>(R(0), R(0));
+#pragma unroll 1
+  for (int l = 0; l < 3; ++l) {
+    const C* src = base + l * comp;
+    C v[LS::E];
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) v[e] = src[LS::idxA(t, e) * plane];
+    LS::template fwd<false>(v, lds + col, B, t, stw);
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const int kz = LS::idxB(t, e);
+      const R rl = (l == 0) ? ssz[kz] * fx0 : scz[kz] * (l == 1 ? fx1 : fx2);
+      acc[e] = mk<C>(acc[e].x + v[e].x * rl, acc[e].y + v[e].y * rl);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const int kz = LS::idxB(t, e);
+    const R a = ssz[kz] * fx0, b = scz[kz] * fx1, c = scz[kz] * fx2;
+    const R r2 = a * a + b * b + c * c;
+    const R f = (r2 > R(0)) ? scale / r2 : R(0);
+    acc[e] = cmul(cscale(acc[e], f), cmul(mk<C>(scz[kz], snz[kz]), eyx));
+  }
+  LS::inv(acc, lds + col, B, t, stw);
+  if (kx != 0) {
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) base[LS::idxA(t, e) * plane] = acc[e];
+  }
+}
+
 }  // namespace fg

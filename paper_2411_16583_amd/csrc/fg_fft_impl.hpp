@@ -104,10 +104,10 @@ void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
   tile &= ~kTileKyMajor;
   const int B = tile > 0 ? tile : column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
   const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zgrad_extra_lds<R>(N0);
-  dim3 grid = kymajor ? dim3((unsigned)N1, (unsigned)(M / B), (unsigned)nitems)
-                      : dim3((unsigned)(M / B), (unsigned)N1, (unsigned)nitems);
-  dim3 gdc((unsigned)(N1 / 2 + 1), (unsigned)nitems, 1);
-  const Skip sk = skip.unit(1);  // grid.z (grad) and grid.y (kx = 0) index the item
+  dim3 grid = kymajor ? dim3((unsigned)N1, (unsigned)(M / B), (unsigned)(3 * nitems))
+                      : dim3((unsigned)(M / B), (unsigned)N1, (unsigned)(3 * nitems));
+  dim3 gdc((unsigned)(N1 / 2 + 1), (unsigned)(3 * nitems), 1);
+  const Skip sk = skip.unit(3);  // grid.z (grad) and grid.y (kx = 0): 3 rows per item
   switch (N0) {
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \

@@ -475,7 +475,7 @@ void note_noop_iterations(fg_plan* P, long noop) {
 }
 
 // Inverse half of the projection in the potential form for all items: the
-// 3-component potential U (slots 0..2 of each item, spectral, written by
+// 3-component potential U (slots 0, 3, 6 of each item, spectral, written by
 // launch_zgrad) back to real space: N1 pass, then N2 complex-to-real.
 template <typename R>
 void inv_potential(fg_plan* P, R* data, const Skip& skip) {
@@ -483,13 +483,15 @@ void inv_potential(fg_plan* P, R* data, const Skip& skip) {
   const long lines = (long)P->n0 * P->n1;
   {
     ProfScope ps(P, FG_PASS_AXIS3);
-    // planes y = component * N0 + i0 of one item, z = item (9 components apart)
-    launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 9L * P->n0 * P->n1 * P->M, P->M, 3 * P->n0,
-                   P->nitems, tb.tw1, skip.unit(3L * P->n0), P->stream, tile_axis<R>(P));
+    // planes y = i0, z = 3 item + c (components 3 apart)
+    launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 3L * P->n0 * P->n1 * P->M, P->M, P->n0,
+                   3 * P->nitems, tb.tw1, skip.unit(3L * P->n0), P->stream, tile_axis<R>(P));
   }
   ProfScope ps(P, FG_PASS_C2R3);
-  Skip sk = skip.unit(3 * lines);
-  sk.item_stride = 9 * lines;
+  // sub-items (item, c) of N0 N1 lines, 3 N0 N1 lines apart, 3 per item
+  Skip sk = skip.unit(lines);
+  sk.item_stride = 3 * lines;
+  sk.sub = 3;
   C2REpi epi{1.0, nullptr, true, nullptr, sk};
   launch_c2r<R>(P->M, data, data, 3 * lines * P->nitems, tb, epi, P->stream);
 }

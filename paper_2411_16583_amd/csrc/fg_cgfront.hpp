@@ -8,7 +8,7 @@
 // and transformed there.
 //
 // A workgroup owns LB grid lines (i0, i1) and all 9 components of them:
-// phase A is one thread per voxel (coalesced along N2), phase B is the
+// phase A is one thread per 2 or 4 voxels (coalesced along N2), phase B is the
 // two-stage line FFT of the 9 LB complex lines with T threads each
 // (9 LB T = 144 threads).
 #pragma once
@@ -16,6 +16,29 @@
 #include "fg_tangent.hpp"
 
 namespace fg {
+
+// W consecutive voxels of one plane in one 16-byte (or 8-byte) access.
+template <typename R, int W> struct FrontPack;
+template <> struct FrontPack<double, 2> { using type = double2; };
+template <> struct FrontPack<float, 2> { using type = float2; };
+template <> struct FrontPack<float, 4> { using type = float4; };
+// voxels per thread and step in phase A: 16-byte accesses where possible
+template <typename R, int M> constexpr int front_width() { return (sizeof(R) == 4 && M % 2 == 0) ? 4 : 2; }
+
+template <typename R, typename PV> __device__ __forceinline__ R pk_get(const PV& v, int w) {
+  return reinterpret_cast<const R*>(&v)[w];
+}
+template <typename R, typename PV> __device__ __forceinline__ void pk_set(PV& v, int w, R a) {
+  reinterpret_cast<R*>(&v)[w] = a;
+}
+// nontemporal store of a W-vector (write streams read back only by a later kernel)
+template <typename R, int W, typename PV> __device__ __forceinline__ void pk_stream(PV* p, const PV& v) {
+  typedef R nvw __attribute__((ext_vector_type(W)));
+  nvw a;
+#pragma unroll
+  for (int w = 0; w < W; ++w) a[w] = pk_get<R>(v, w);
+  __builtin_nontemporal_store(a, reinterpret_cast<nvw*>(p));
+}
 
 template <int M> struct FrontShape {
   static constexpr int T = Line<M>::T;
@@ -54,55 +77,62 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
   const R alpha = (R)ks->alpha;
   const R beta = (R)ks->beta;
   double acc = 0.0;
-  // ---- phase A: pointwise, two voxels per thread and step (2-vector loads)
-  using V = cplx<R>;
-  const long Nv = N / 2;
-  const V* rv = reinterpret_cast<const V*>(r);
-  const V* sv = reinterpret_cast<const V*>(st);
-  V* pv = reinterpret_cast<V*>(p);
-  V* xv = reinterpret_cast<V*>(x);
-  for (int v = tid; v < LB * M; v += FS::THREADS) {
-    const int l = v / M;
-    const int n = v % M;  // voxel pair (2n, 2n+1) of line l
+  // ---- phase A: pointwise, W voxels per thread and step (one W-vector
+  // access per plane; W = 4 in single precision, else 2)
+  constexpr int W = front_width<R, M>();
+  using PV = typename FrontPack<R, W>::type;
+  constexpr int GPL = 2 * M / W;  // voxel groups per line
+  const long Nw = N / W;
+  const PV* rv = reinterpret_cast<const PV*>(r);
+  const PV* sv = reinterpret_cast<const PV*>(st);
+  PV* pv = reinterpret_cast<PV*>(p);
+  PV* xv = reinterpret_cast<PV*>(x);
+  for (int v = tid; v < LB * GPL; v += FS::THREADS) {
+    const int l = v / GPL;
+    const int n = v % GPL;  // voxels W n .. W n + W - 1 of line l
     if (line0 + l >= nlines) continue;
-    const long g = (line0 + l) * M + n;
-    V rk[9], po[9], A[9];
+    const long g = (line0 + l) * GPL + n;
+    PV rk[9], po[9], A[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      rk[k] = rv[k * Nv + g];
-      if (!first) po[k] = pv[k * Nv + g];
+      rk[k] = rv[k * Nw + g];
+      if (!first) po[k] = pv[k * Nw + g];
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) A[k] = sv[k * Nv + g];
-    const V al = sv[9 * Nv + g], be = sv[10 * Nv + g], ga = sv[11 * Nv + g];
-    R X0[9], X1[9];
+    for (int k = 0; k < 9; ++k) A[k] = sv[k * Nw + g];
+    const PV al = sv[9 * Nw + g], be = sv[10 * Nw + g], ga = sv[11 * Nw + g];
+    R X[W][9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      V pk = rk[k];
+      PV pk = rk[k];
       if (!first) {
-        V xo = xv[k * Nv + g];
-        xo.x += alpha * po[k].x;
-        xo.y += alpha * po[k].y;
-        st_stream(xv + k * Nv + g, xo);
-        pk.x = rk[k].x + beta * po[k].x;
-        pk.y = rk[k].y + beta * po[k].y;
+        PV xo = xv[k * Nw + g];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          pk_set<R>(xo, w, pk_get<R>(xo, w) + alpha * pk_get<R>(po[k], w));
+          pk_set<R>(pk, w, pk_get<R>(rk[k], w) + beta * pk_get<R>(po[k], w));
+        }
+        pk_stream<R, W>(xv + k * Nw + g, xo);
       }
-      st_stream(pv + k * Nv + g, pk);
-      X0[k] = pk.x;
-      X1[k] = pk.y;
-    }
-    R A0[9], A1[9], Y0[9], Y1[9];
+      pk_stream<R, W>(pv + k * Nw + g, pk);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      A0[k] = A[k].x;
-      A1[k] = A[k].y;
+      for (int w = 0; w < W; ++w) X[w][k] = pk_get<R>(pk, w);
     }
-    tangent_apply<R>(A0, al.x, be.x, ga.x, X0, Y0);
-    tangent_apply<R>(A1, al.y, be.y, ga.y, X1, Y1);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      acc += (double)X0[k] * (double)Y0[k] + (double)X1[k] * (double)Y1[k];
-      buf[(k * LB + l) * FS::LSTRIDE + n] = mk<C>(Y0[k], Y1[k]);
+    for (int w = 0; w < W; w += 2) {
+      R A0[9], A1[9], Y0[9], Y1[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        A0[k] = pk_get<R>(A[k], w);
+        A1[k] = pk_get<R>(A[k], w + 1);
+      }
+      tangent_apply<R>(A0, pk_get<R>(al, w), pk_get<R>(be, w), pk_get<R>(ga, w), X[w], Y0);
+      tangent_apply<R>(A1, pk_get<R>(al, w + 1), pk_get<R>(be, w + 1), pk_get<R>(ga, w + 1), X[w + 1], Y1);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        acc += (double)X[w][k] * (double)Y0[k] + (double)X[w + 1][k] * (double)Y1[k];
+        buf[(k * LB + l) * FS::LSTRIDE + n * (W / 2) + w / 2] = mk<C>(Y0[k], Y1[k]);
+      }
     }
   }
   __syncthreads();

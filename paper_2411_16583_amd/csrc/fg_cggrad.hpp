@@ -9,30 +9,37 @@
 //                 sums of the new r . r;
 //   mode 1:       r <- D U (the projection itself; r is the output).
 // U: component slots 0, 3, 6 of the item's 9-component buffer (real after
-// the inverse passes).  Grid (ceil(N / 512), items), one thread per voxel pair
-// (x, x + 1) along N2 (N2 even).
+// the inverse passes).  Grid (ceil(N / (256 W)), items), one thread per W
+// consecutive voxels along N2.
 #pragma once
 #include "fg_fft.hpp"
 
 namespace fg {
 
-template <typename T>
+// W consecutive voxels of a line per thread (W = 4 in single precision when
+// N2 % 4 == 0, else 2): one W-vector access per plane and line.
+template <typename T, int W> struct GradPack;
+template <> struct GradPack<double, 2> { using type = double2; };
+template <> struct GradPack<float, 2> { using type = float2; };
+template <> struct GradPack<float, 4> { using type = float4; };
+
+template <typename T, int W>
 __global__ void __launch_bounds__(256)
 k_cg_grad(const T* __restrict__ U, T* __restrict__ r, const KrylovScalars* __restrict__ ks,
           double* __restrict__ partials, int n0, int n1, int n2, T ih0, T ih1, T ih2, int mode) {
-  using V = cplx<T>;
+  using V = typename GradPack<T, W>::type;
   __shared__ double red[16];
   const int item = blockIdx.y;
   if (mode == 0 && ks[item].done) return;
   const long N = (long)n0 * n1 * n2;
   U += (long)item * 9 * N;
   r += (long)item * 9 * N;
-  const int M = n2 / 2;
+  const int G = n2 / W;  // voxel groups per line
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double acc = 0.0;
-  if (g < N / 2) {
-    const long line = g / M;
-    const int x = 2 * (int)(g - line * M);
+  if (g < N / W) {
+    const long line = g / G;
+    const int x = W * (int)(g - line * G);
     const int i0 = (int)(line / n1), i1 = (int)(line - (long)i0 * n1);
     const int i0m = (i0 == 0) ? n0 - 1 : i0 - 1;
     const int i1m = (i1 == 0) ? n1 - 1 : i1 - 1;
@@ -43,24 +50,23 @@ k_cg_grad(const T* __restrict__ U, T* __restrict__ r, const KrylovScalars* __res
     const T alpha = (mode == 0) ? (T)ks[item].alpha : T(0);
     const T q0 = T(0.25) * ih0, q1 = T(0.25) * ih1, q2 = T(0.25) * ih2;
     V* rv = reinterpret_cast<V*>(r);
-    const long gv = line * M + x / 2;  // voxel pair index of (line, x)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const T* Uc = U + 3 * c * N;
-      // u[a][b][p]: corner values at x - 1, x, x + 1 (p = 0, 1, 2)
-      T u[2][2][3];
+      // u[a][b][p]: corner values at x - 1 + p, p = 0..W
+      T u[2][2][W + 1];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const V w = *reinterpret_cast<const V*>(Uc + row[a][b] + x);
           u[a][b][0] = Uc[row[a][b] + xm];
-          u[a][b][1] = w.x;
-          u[a][b][2] = w.y;
-        }
-      T Z[3][2];
 #pragma unroll
-      for (int v = 0; v < 2; ++v) {
+          for (int q = 0; q < W; ++q) u[a][b][q + 1] = reinterpret_cast<const T*>(&w)[q];
+        }
+      T Z[3][W];
+#pragma unroll
+      for (int v = 0; v < W; ++v) {
         const int lo = v, hi = v + 1;  // corners below / above voxel x + v along N2
         Z[0][v] = q0 * ((u[0][0][hi] + u[0][1][hi] + u[0][0][lo] + u[0][1][lo]) -
                         (u[1][0][hi] + u[1][1][hi] + u[1][0][lo] + u[1][1][lo]));
@@ -71,16 +77,21 @@ k_cg_grad(const T* __restrict__ U, T* __restrict__ r, const KrylovScalars* __res
       }
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        V* dst = rv + (3 * c + j) * (N / 2) + gv;
+        V* dst = rv + (3 * c + j) * (N / W) + g;
+        V ro;
         if (mode == 0) {
-          V ro = *dst;
-          ro.x -= alpha * Z[j][0];
-          ro.y -= alpha * Z[j][1];
-          *dst = ro;
-          acc += (double)ro.x * (double)ro.x + (double)ro.y * (double)ro.y;
+          ro = *dst;
+#pragma unroll
+          for (int v = 0; v < W; ++v) {
+            T& e = reinterpret_cast<T*>(&ro)[v];
+            e -= alpha * Z[j][v];
+            acc += (double)e * (double)e;
+          }
         } else {
-          *dst = mk<V>(Z[j][0], Z[j][1]);
+#pragma unroll
+          for (int v = 0; v < W; ++v) reinterpret_cast<T*>(&ro)[v] = Z[j][v];
         }
+        *dst = ro;
       }
     }
   }
@@ -88,6 +99,23 @@ k_cg_grad(const T* __restrict__ U, T* __restrict__ r, const KrylovScalars* __res
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) partials[(long)item * gridDim.x + blockIdx.x] = s;
   }
+}
+
+// Launch over all items; returns the number of partials per item.
+template <typename T>
+int launch_cg_grad(const T* U, T* r, const KrylovScalars* ks, double* partials, int n0, int n1, int n2, int nitems,
+                   const double h[3], int mode, hipStream_t s) {
+  const long N = (long)n0 * n1 * n2;
+  const T ih0 = (T)(1.0 / h[0]), ih1 = (T)(1.0 / h[1]), ih2 = (T)(1.0 / h[2]);
+  if (sizeof(T) == 4 && n2 % 4 == 0) {
+    const dim3 grid((unsigned)((N / 4 + 255) / 256), (unsigned)nitems);
+    hipLaunchKernelGGL((k_cg_grad<T, (sizeof(T) == 4 ? 4 : 2)>), grid, dim3(256), 0, s, U, r, ks, partials, n0, n1,
+                       n2, ih0, ih1, ih2, mode);
+    return (int)grid.x;
+  }
+  const dim3 grid((unsigned)((N / 2 + 255) / 256), (unsigned)nitems);
+  hipLaunchKernelGGL((k_cg_grad<T, 2>), grid, dim3(256), 0, s, U, r, ks, partials, n0, n1, n2, ih0, ih1, ih2, mode);
+  return (int)grid.x;
 }
 
 }  // namespace fg

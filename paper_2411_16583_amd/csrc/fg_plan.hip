@@ -532,17 +532,14 @@ void cg_iteration(fg_plan* P) {
     launch_zgrad<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip, P->stream, nit, tile_zproj<T>(P));
   }
   inv_potential<T>(P, S, skip);
-  const dim3 gg((unsigned)((P->N / 2 + 255) / 256), (unsigned)nit);
+  int nbg;
   {
     ProfScope ps(P, FG_PASS_GRAD);
-    hipLaunchKernelGGL((k_cg_grad<T>), gg, dim3(256), 0, P->stream, (const T*)S, (T*)P->r,
-                       (const KrylovScalars*)ks, P->part2, P->n0, P->n1, P->n2, (T)(1.0 / P->h[0]),
-                       (T)(1.0 / P->h[1]), (T)(1.0 / P->h[2]), 0);
+    nbg = launch_cg_grad<T>((const T*)S, (T*)P->r, ks, P->part2, P->n0, P->n1, P->n2, nit, P->h, 0, P->stream);
   }
   {
     ProfScope ps(P, FG_PASS_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3(nit), dim3(1024), 0, P->stream, P->part2, (int)gg.x, ks, (double*)nullptr,
-                       1, 0);
+    hipLaunchKernelGGL(k_finalize, dim3(nit), dim3(1024), 0, P->stream, P->part2, nbg, ks, (double*)nullptr, 1, 0);
   }
   check_launch();
 }
@@ -1228,9 +1225,8 @@ fg_status fg_project_grad(fg_plan* P, const double* x, double* y) {
     launch_zgrad<double>(P->n0, P->S64, P->n1, P->M, P->t64.spec(), 1.0 / (double)P->N, Skip{}, P->stream, 1,
                          tile_zproj<double>(P));
     inv_potential<double>(P, P->S64, Skip{});
-    hipLaunchKernelGGL((k_cg_grad<double>), dim3((unsigned)((P->N / 2 + 255) / 256), 1), dim3(256), 0, P->stream,
-                       (const double*)P->S64, y, (const KrylovScalars*)nullptr, (double*)nullptr, P->n0, P->n1,
-                       P->n2, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2], 1);
+    launch_cg_grad<double>((const double*)P->S64, y, (const KrylovScalars*)nullptr, (double*)nullptr, P->n0, P->n1,
+                           P->n2, 1, P->h, 1, P->stream);
     check_launch();
   });
 }

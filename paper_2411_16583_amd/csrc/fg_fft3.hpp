@@ -23,6 +23,9 @@ template <> struct Line3Shape<256> {
 template <> struct Line3Shape<128> {
   static constexpr int R1 = 4, R2 = 4, R3 = 8, T = 16;
 };
+template <> struct Line3Shape<96> {
+  static constexpr int R1 = 4, R2 = 4, R3 = 6, T = 8;
+};
 
 template <int L> struct Line3 {
   static constexpr int R1 = Line3Shape<L>::R1, R2 = Line3Shape<L>::R2, R3 = Line3Shape<L>::R3;
@@ -157,6 +160,9 @@ template <> struct ZLineSel<256> {
 template <> struct ZLineSel<128> {
   using type = Line3<128>;
 };
+template <> struct ZLineSel<96> {
+  using type = Line3<96>;
+};
 template <int L> using ZLine = typename ZLineSel<L>::type;
 
 template <typename R, int L>
@@ -286,18 +292,35 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   C acc[LS::E];
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) acc[e] = mk<C>(R(0), R(0));
+  // double precision: component l + 1 is loaded while component l is
+  // transformed, where the extra registers fit (up to 8 complex per thread);
+  // measured slower in single precision
+  constexpr bool PREFETCH = sizeof(R) == 8 && sizeof(C) * LS::E <= 128;
+  C v[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = base[LS::idxA(t, e) * plane];
 #pragma unroll 1
   for (int l = 0; l < 3; ++l) {
-    const C* src = base + l * comp;
-    C v[LS::E];
+    C vn[LS::E];
+    if (!PREFETCH && l > 0) {
 #pragma unroll
-    for (int e = 0; e < LS::E; ++e) v[e] = src[LS::idxA(t, e) * plane];
+      for (int e = 0; e < LS::E; ++e) v[e] = base[l * comp + LS::idxA(t, e) * plane];
+    }
+    if (PREFETCH && l < 2) {
+      const C* src = base + (l + 1) * comp;
+#pragma unroll
+      for (int e = 0; e < LS::E; ++e) vn[e] = src[LS::idxA(t, e) * plane];
+    }
     LS::template fwd<false>(v, lds + col, B, t, stw);
 #pragma unroll
     for (int e = 0; e < LS::E; ++e) {
       const int kz = LS::idxB(t, e);
       const R rl = (l == 0) ? ssz[kz] * fx0 : scz[kz] * (l == 1 ? fx1 : fx2);
       acc[e] = mk<C>(acc[e].x + v[e].x * rl, acc[e].y + v[e].y * rl);
+    }
+    if (PREFETCH && l < 2) {
+#pragma unroll
+      for (int e = 0; e < LS::E; ++e) v[e] = vn[e];
     }
   }
 #pragma unroll

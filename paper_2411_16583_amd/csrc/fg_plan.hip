@@ -60,6 +60,7 @@ int column_tile(int L, int M, int elem_bytes) { return column_tile_t(line_thread
 int zline_threads(int L) {
   if (L == 256) return Line3<256>::T;
   if (L == 128) return Line3<128>::T;
+  if (L == 96) return Line3<96>::T;
   return line_threads(L);
 }
 

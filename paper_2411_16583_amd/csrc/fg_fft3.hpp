@@ -288,7 +288,11 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
   // -i e^{i (qy + qx) / 2}; the kz factor is applied per element
   const C eyx = mul_mi(cmul(mk<C>(cy, tb.sny[ky]), mk<C>(cx, tb.snx[kx])));
-  C* base = reinterpret_cast<C*>(data) + (long)(3 * i) * comp + (long)ky * M + kx;
+  // workgroup-uniform base of the row's first component and a 32-bit
+  // element offset per thread (col + kz plane; a component is < 2^32 bytes)
+  C* base = reinterpret_cast<C*>(data) + (long)(3 * i) * comp + (long)ky * M + (kx - col);
+  const unsigned uplane = (unsigned)plane;
+  const unsigned ucomp = (unsigned)comp;
   C acc[LS::E];
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) acc[e] = mk<C>(R(0), R(0));
@@ -298,18 +302,18 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   constexpr bool PREFETCH = sizeof(R) == 8 && sizeof(C) * LS::E <= 128;
   C v[LS::E];
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) v[e] = base[LS::idxA(t, e) * plane];
+  for (int e = 0; e < LS::E; ++e) v[e] = base[(unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
 #pragma unroll 1
   for (int l = 0; l < 3; ++l) {
     C vn[LS::E];
     if (!PREFETCH && l > 0) {
 #pragma unroll
-      for (int e = 0; e < LS::E; ++e) v[e] = base[l * comp + LS::idxA(t, e) * plane];
+      for (int e = 0; e < LS::E; ++e) v[e] = base[(unsigned)l * ucomp + (unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
     }
     if (PREFETCH && l < 2) {
-      const C* src = base + (l + 1) * comp;
 #pragma unroll
-      for (int e = 0; e < LS::E; ++e) vn[e] = src[LS::idxA(t, e) * plane];
+      for (int e = 0; e < LS::E; ++e)
+        vn[e] = base[(unsigned)(l + 1) * ucomp + (unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
     }
     LS::template fwd<false>(v, lds + col, B, t, stw);
 #pragma unroll
@@ -334,7 +338,7 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   LS::inv(acc, lds + col, B, t, stw);
   if (kx != 0) {
 #pragma unroll
-    for (int e = 0; e < LS::E; ++e) base[LS::idxA(t, e) * plane] = acc[e];
+    for (int e = 0; e < LS::E; ++e) base[(unsigned)col + (unsigned)LS::idxA(t, e) * uplane] = acc[e];
   }
 }
 

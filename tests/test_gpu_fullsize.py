@@ -1,0 +1,208 @@
+"""Parity at the benchmark's sizes, in the launch configuration the benchmark
+times (256^3 plans, the 48 x 6 batch), through properties that hold at any
+size and outputs the oracle computes voxel by voxel:
+
+* the CG's projection route (potential + corner stencil) equals the
+  9-component projection, is idempotent and symmetric (eq. (28));
+* the stress of sampled voxels equals the oracle's constitutive law;
+* the operator of eq. (30) is self-adjoint and positive on compatible
+  fields and maps into them;
+* a Newton increment of the polydisperse workload reaches err_res <= tol by
+  an independent recomputation, keeps <F> = Fbar and satisfies Hill-Mandel;
+  the mixed form lands within 1e-6 of FP64;
+* every item of the 48-RVE x 6-case batch converges and its C_eff lies
+  between the Reuss and Voigt bounds.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import constitutive as cm
+from paper_2411_16583_amd import Batch, Plan, make_opts
+from paper_2411_16583_amd.homogenize import voigt_stiffness
+from tests.gpu_util import DEV, dt, host, plan_for
+
+pytestmark = pytest.mark.gpu
+
+N256 = (256, 256, 256)
+
+
+def _dot(a, b):
+    return float(torch.dot(a.reshape(-1), b.reshape(-1)).item())
+
+
+def _nrm(a):
+    return float(torch.linalg.vector_norm(a).item())
+
+
+@pytest.fixture(scope="module")
+def plan256():
+    work = synth.homogeneous_workload(N256, 1.0)
+    plan = plan_for(work)
+    yield plan, work
+    plan.close()
+
+
+def test_projection_routes_agree_256(plan256):
+    print("projection routes 256^3", flush=True)
+    plan, _ = plan256
+    g = torch.Generator(device="cpu").manual_seed(256001)
+    x = torch.randn((9,) + N256, generator=g, dtype=torch.float64).to(DEV)
+    z = torch.randn((9,) + N256, generator=g, dtype=torch.float64).to(DEV)
+    y1 = torch.empty_like(x)
+    y2 = torch.empty_like(x)
+    plan.project(x, y1)
+    plan.project_grad(x, y2)
+    torch.cuda.synchronize()
+    assert _nrm(y1 - y2) <= 1e-13 * _nrm(y1)
+    y3 = torch.empty_like(x)
+    plan.project_grad(y2, y3)
+    gz = torch.empty_like(z)
+    plan.project_grad(z, gz)
+    torch.cuda.synchronize()
+    assert _nrm(y3 - y2) <= 1e-13 * _nrm(y2)
+    assert abs(_dot(y2, z) - _dot(x, gz)) <= 1e-12 * _nrm(x) * _nrm(z)
+
+
+def _state256(seed):
+    rng = np.random.default_rng(seed)
+    F = np.eye(3).reshape(3, 3, 1, 1, 1) + 0.05 * rng.standard_normal((3, 3) + N256)
+    c = rng.uniform(0.0, 0.5, N256)
+    d = rng.uniform(0.0, 0.5, N256)
+    E = rng.uniform(5e9, 200e9, N256)
+    nu = rng.uniform(0.2, 0.35, N256)
+    Om = rng.uniform(0.0, 0.05, N256)
+    return F, c, d, E, nu, Om
+
+
+def test_sampled_stress_256():
+    print("sampled stress 256^3", flush=True)
+    F, c, d, E, nu, Om = _state256(256002)
+    plan = Plan(N256, (1.0 / 256,) * 3)
+    mats = [dt(a) for a in (E, nu, Om)]
+    plan.set_material(*mats)
+    Ft, ct, dt_ = dt(F), dt(c), dt(d)
+    plan.set_state(Ft, ct, dt_)
+    P = torch.empty_like(Ft)
+    plan.stress(P)
+    torch.cuda.synchronize()
+    Pg = host(P, (3, 3, -1))
+    idx = np.random.default_rng(256003).integers(0, int(np.prod(N256)), size=512)
+    Fs = F.reshape(3, 3, -1)[:, :, idx]
+    Po = cm.stress(Fs, c.ravel()[idx], d.ravel()[idx], E.ravel()[idx], nu.ravel()[idx], Om.ravel()[idx])
+    err = np.abs(Pg[:, :, idx] - Po).max() / np.abs(Po).max()
+    print(f"sampled stress max rel {err:.1e}", flush=True)
+    assert err <= 1e-13
+    plan.close()
+
+
+def test_operator_self_adjoint_256(plan256):
+    print("operator 256^3", flush=True)
+    F, c, d, E, nu, Om = _state256(256004)
+    plan = Plan(N256, (1.0 / 256,) * 3)
+    mats = [dt(a) for a in (E, nu, Om)]
+    plan.set_material(*mats)
+    Ft = dt(np.eye(3).reshape(3, 3, 1, 1, 1) + 0.2 * (F - np.eye(3).reshape(3, 3, 1, 1, 1)))
+    ct, dt_ = dt(c), dt(d)
+    plan.set_state(Ft, ct, dt_)
+    g = torch.Generator(device="cpu").manual_seed(256005)
+    x = torch.randn((9,) + N256, generator=g, dtype=torch.float64).to(DEV)
+    y = torch.randn((9,) + N256, generator=g, dtype=torch.float64).to(DEV)
+    plan.project(x, x)
+    plan.project(y, y)
+    Ax = torch.empty_like(x)
+    Ay = torch.empty_like(y)
+    plan.apply_operator(x, Ax)
+    plan.apply_operator(y, Ay)
+    GAx = torch.empty_like(x)
+    plan.project(Ax, GAx)
+    torch.cuda.synchronize()
+    assert _nrm(GAx - Ax) <= 1e-13 * _nrm(Ax)
+    assert abs(_dot(Ax, y) - _dot(x, Ay)) <= 1e-12 * _nrm(Ax) * _nrm(y)
+    assert _dot(Ax, x) > 0 and _dot(Ay, y) > 0
+    plan.close()
+
+
+@pytest.fixture(scope="module")
+def poly256():
+    return synth.polydisperse_workload(n=256)
+
+
+def _increment(work, precision):
+    shape = work["shape"]
+    plan = plan_for(work, precision)
+    F = torch.zeros((9,) + shape, dtype=torch.float64, device=DEV)
+    F[0] = 1.0
+    F[4] = 1.0
+    F[8] = 1.0
+    c = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    d = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    plan.set_state(F, c, d)
+    Fbar = work["loads"][0]
+    st = plan.newton_solve(Fbar, make_opts(1e-8, 1e-10))
+    return plan, F, Fbar, st
+
+
+def test_newton_increment_256(poly256):
+    print("newton increment 256^3 fp64 + mixed", flush=True)
+    work = poly256
+    out = {}
+    for precision in ("fp64", "mixed"):
+        plan, F, Fbar, st = _increment(work, precision)
+        err = plan.residual(Fbar)
+        Pm = plan.homogenized_stress()
+        Fm = host(F.reshape(9, -1).mean(dim=1)).reshape(3, 3)
+        P = torch.empty_like(F)
+        plan.stress(P)
+        Ft = F.reshape(3, 3, -1) - torch.tensor(Fbar, dtype=torch.float64, device=DEV).reshape(3, 3, 1)
+        Pr = P.reshape(3, 3, -1)
+        # Hill-Mandel: <P_ij Ft_kj> = 0 for compatible Ft and equilibrated P
+        hm = np.array([[sum(_dot(Pr[i, j], Ft[k, j]) for j in range(3)) for k in range(3)]
+                       for i in range(3)]) / F[0].numel()
+        print(f"{precision}: newton {st['newton_iters']} cg {st['lin_history']} err_res {st['err_res']:.2e} "
+              f"recomputed {err:.2e} |<F>-Fbar| {np.abs(Fm - Fbar).max():.1e} |HM| {np.abs(hm).max():.1e}",
+              flush=True)
+        assert err <= 1e-8 and abs(err - st["err_res"]) <= 1e-3 * max(err, 1e-300) + 1e-15
+        assert np.abs(Fm - Fbar).max() <= 1e-13
+        assert np.abs(hm).max() <= 1e-7 * np.abs(Pm).max() * float(torch.abs(Ft).max())
+        out[precision] = Pm
+        plan.close()
+        del F, P, Ft, Pr
+        torch.cuda.empty_cache()
+    assert np.abs(out["mixed"] - out["fp64"]).max() <= 1e-6 * np.abs(out["fp64"]).max()
+
+
+def test_batch_c4_full():
+    print("batch 48 x 6 full size", flush=True)
+    items = synth.batch_workloads(48)
+    eps = 1e-3
+    loads = items[0]["loads"]
+    b = Batch([w["shape"] for w in items], [w["spacing"] for w in items], len(loads), "fp64")
+    for k, w in enumerate(items):
+        b.set_material(k, dt(w["E"]), dt(w["nu"]), dt(w["Omega"]))
+    P, stats, st = b.newton_solve(loads, make_opts(1e-8, 1e-10), graph_ticks=16)
+    b.close()
+    assert st == 0
+    assert max(s["err_res"] for s in stats) <= 1e-8
+
+    def C_iso(E, nu):
+        lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+        G = E / (2 * (1 + nu))
+        C = np.zeros((6, 6))
+        C[:3, :3] = lam
+        C[np.arange(3), np.arange(3)] += 2 * G
+        C[np.arange(3, 6), np.arange(3, 6)] = G
+        return C
+
+    rng = np.random.default_rng(256006)
+    for k, w in enumerate(items):
+        C = voigt_stiffness(P[k], eps)
+        phi = float(w["phase"].mean())
+        Ci, Cm = C_iso(100e9, 0.25), C_iso(10e9, 0.3)
+        voigt = phi * Ci + (1 - phi) * Cm
+        reuss = np.linalg.inv(phi * np.linalg.inv(Ci) + (1 - phi) * np.linalg.inv(Cm))
+        for _ in range(10):
+            e = rng.standard_normal(6)
+            q = e @ (0.5 * (C + C.T)) @ e
+            assert e @ reuss @ e * (1 - 1e-2) <= q <= e @ voigt @ e * (1 + 1e-2), k

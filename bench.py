@@ -60,6 +60,8 @@ def parse():
                          "FP64 and mixed against the 288 single-item FP64 solves")
     ap.add_argument("--batch-items", type=int, default=48)
     ap.add_argument("--graph-ticks", type=int, default=16)
+    ap.add_argument("--newton-every", type=int, default=4,
+                    help="batched form: the Newton step in every k-th step (graph_ticks a multiple of k)")
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 9 N doubles device-to-device 3 times (a plain copy kernel of known size, "
@@ -230,6 +232,7 @@ def run_batch(args):
         b = Batch([w["shape"] for w in items], [w["spacing"] for w in items], ncase, form)
         for k, w in enumerate(items):
             b.set_material(k, t(w["E"]), t(w["nu"]), t(w["Omega"]))
+        b.set_schedule(args.newton_every)
         b.newton_solve(loads, opts, graph_ticks=args.graph_ticks)  # warm: graph capture, first touch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -297,7 +300,8 @@ def run_batch(args):
         "data": "synthetic",
         "config": {"workload": f"{len(items)} Boolean-sphere RVEs, N ~ U{{32,48,64,96}}, phi ~ U(0.1,0.4), "
                                f"contrast 10, 6 load cases eps = 1e-3, from the reference state",
-                   "voxels": sum(Ns), "graph_ticks": args.graph_ticks, "groups": f64["groups"]},
+                   "voxels": sum(Ns), "graph_ticks": args.graph_ticks, "newton_every": args.newton_every,
+                   "groups": f64["groups"]},
         "batched_fp64": dict(seconds=round(f64["elapsed"], 4), cg_iters=f64["cg"],
                              voxel_cg_iters_per_s=f64["voxel_iters"] / f64["elapsed"],
                              C_eff_rel_diff=cdiff(f64["P"]) if seq else 0.0),

@@ -248,6 +248,12 @@ fg_status fg_batch_set_material(fg_batch* batch, int rve, const double* E, const
  * index in fg_batch_last_error; every item's outputs are written anyway. */
 fg_status fg_batch_newton_solve(fg_batch* batch, const double* F_macro, const fg_solver_opts* opts, int graph_ticks,
                                 double* P_avg, fg_stats* stats);
+/* Schedule of the batched solve: the Newton step (with its masked launches
+ * over every item of every group) runs in every newton_every-th step of the
+ * sequence, 1 <= newton_every <= 64 (default 1); an item whose CG has ended
+ * waits for the next such step.  graph_ticks must then be a multiple of
+ * newton_every.  Results do not depend on the schedule.  Errors: FG_E_ARG. */
+fg_status fg_batch_set_schedule(fg_batch* batch, int newton_every);
 /* Copy F of item (rve, lcase) into F (device, 9 N_rve doubles). */
 fg_status fg_batch_state(fg_batch* batch, int rve, int lcase, double* F);
 const char* fg_batch_last_error(const fg_batch* batch);

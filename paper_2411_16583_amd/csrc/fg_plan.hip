@@ -1379,6 +1379,8 @@ struct fg_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_ticks = 0;
+  int graph_every = 0;         // newton_every at capture
+  int newton_every = 1;        // the Newton step runs in every k-th tick
   std::vector<int> graph_gen;  // tiles_gen of each group at capture
   NewtonCtl* hnc = nullptr;  // pinned, max items of a group
   int* hactive = nullptr;    // pinned, one per group
@@ -1418,8 +1420,9 @@ inline dim3 item_grid(long n, int nitems) {
 // One tick of a group: a CG iteration for the items whose solve runs, then
 // the Newton step for the items whose solve has ended.
 template <typename T>
-void batch_tick(fg_plan* P, fg_batch::Group& g) {
+void batch_tick(fg_plan* P, fg_batch::Group& g, bool newton) {
   cg_iteration<T>(P);
+  if (!newton) return;
   const int nit = P->nitems;
   const long n9 = 9 * P->N;
   const dim3 gi = item_grid(n9, nit);
@@ -1466,10 +1469,11 @@ void batch_enqueue(fg_batch* B, int ticks) {
   for (auto& g : B->groups) {
     FG_HIP(hipStreamWaitEvent(g.s, B->ev_fork, 0));
     for (int t = 0; t < ticks; ++t) {
+      const bool newton = (t % B->newton_every) == 0;
       if (B->prec == FG_FP64)
-        batch_tick<double>(g.P, g);
+        batch_tick<double>(g.P, g, newton);
       else
-        batch_tick<float>(g.P, g);
+        batch_tick<float>(g.P, g, newton);
     }
     FG_HIP(hipEventRecord(g.ev_join, g.s));
     FG_HIP(hipStreamWaitEvent(B->s0, g.ev_join, 0));
@@ -1479,7 +1483,7 @@ void batch_enqueue(fg_batch* B, int ticks) {
 void batch_capture(fg_batch* B, int ticks) {
   std::vector<int> gen;
   for (auto& g : B->groups) gen.push_back(g.P->tiles_gen);
-  if (B->exec && B->graph_ticks == ticks && gen == B->graph_gen) return;
+  if (B->exec && B->graph_ticks == ticks && B->graph_every == B->newton_every && gen == B->graph_gen) return;
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   B->exec = nullptr;
@@ -1496,6 +1500,7 @@ void batch_capture(fg_batch* B, int ticks) {
   FG_HIP(hipStreamEndCapture(B->s0, &B->graph));
   FG_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
   B->graph_ticks = ticks;
+  B->graph_every = B->newton_every;
   B->graph_gen = gen;
 }
 
@@ -1791,6 +1796,10 @@ fg_status fg_batch_newton_solve(fg_batch* B, const double* F_macro, const fg_sol
   if (!B || !F_macro || !opts) return FG_E_ARG;
   if (opts->max_lin <= 0 && opts->fixed_lin <= 0) return FG_E_ARG;
   if (graph_ticks < 0) return FG_E_ARG;
+  if (graph_ticks > 0 && graph_ticks % B->newton_every != 0) {
+    B->err = "graph_ticks must be a multiple of the Newton schedule (fg_batch_set_schedule)";
+    return FG_E_ARG;
+  }
   return batch_run(B, [&]() {
     if (!B->ws) throw Status(FG_E_STATE, "workspace not set");
     for (int r = 0; r < B->n_rve; ++r)
@@ -1801,9 +1810,11 @@ fg_status fg_batch_newton_solve(fg_batch* B, const double* F_macro, const fg_sol
       batch_prologue(B, g, F_macro, opts);
     }
     const int maxit = (opts->fixed_lin > 0) ? opts->fixed_lin : opts->max_lin;
-    // every Newton step takes at most maxit CG ticks and one tick of its own
-    const long cap = (long)(opts->max_newton + 1) * (maxit + 1) + 2;
-    const int per = graph_ticks > 0 ? graph_ticks : 8;
+    const int k = B->newton_every;
+    // every Newton step takes at most maxit CG ticks, then waits at most k
+    // ticks for a tick with the Newton step
+    const long cap = (long)(opts->max_newton + 1) * (maxit + k) + 2 * k;
+    const int per = graph_ticks > 0 ? graph_ticks : 8 * k;
     if (graph_ticks > 0) batch_capture(B, graph_ticks);
     for (long ticks = 0; ticks < cap; ticks += per) {
       if (graph_ticks > 0)
@@ -1834,6 +1845,12 @@ fg_status fg_batch_state(fg_batch* B, int rve, int lcase, double* F) {
     FG_HIP(hipMemcpyAsync(F, g.F + w.second * n9, n9 * sizeof(double), hipMemcpyDeviceToDevice, g.s));
     FG_HIP(hipStreamSynchronize(g.s));
   });
+}
+
+fg_status fg_batch_set_schedule(fg_batch* B, int newton_every) {
+  if (!B || newton_every < 1 || newton_every > 64) return FG_E_ARG;
+  B->newton_every = newton_every;
+  return FG_OK;
 }
 
 fg_plan* fg_batch_plan(fg_batch* B, int group) {

@@ -27,7 +27,7 @@ EXPORTED = [
     "fg_apply_operator", "fg_project", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
     "fg_batch_create", "fg_batch_workspace_bytes", "fg_batch_groups", "fg_batch_set_workspace",
     "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
-    "fg_batch_plan", "fg_batch_group_info", "fg_plan_tile_candidates", "fg_plan_set_tiles", "fg_plan_get_tiles",
+    "fg_batch_plan", "fg_batch_group_info", "fg_batch_set_schedule", "fg_plan_tile_candidates", "fg_plan_set_tiles", "fg_plan_get_tiles",
     "fg_plan_time_pass",
     "fg_profile_begin", "fg_profile_end", "fg_status_string", "fg_last_error", "fg_plan_destroy",
 ]
@@ -127,6 +127,7 @@ def load_library(path=LIB_PATH):
         "fg_batch_last_error": ([vp], ctypes.c_char_p),
         "fg_batch_destroy": ([vp], None),
         "fg_batch_plan": ([vp, c_int], vp),
+        "fg_batch_set_schedule": ([vp, c_int], c_int),
         "fg_batch_group_info": ([vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)], c_int),
         "fg_plan_tile_candidates": ([vp, c_int, ctypes.POINTER(c_int), c_int], c_int),
         "fg_plan_set_tiles": ([vp, ctypes.POINTER(c_int)], c_int),
@@ -395,6 +396,9 @@ class Batch:
         if raise_on_error:
             self._check(st, "fg_batch_newton_solve")
         return P.reshape(self.n_rve, self.n_cases, 3, 3), [s.to_dict() for s in stats], st
+
+    def set_schedule(self, newton_every):
+        self._check(self.lib.fg_batch_set_schedule(self.handle, int(newton_every)), "fg_batch_set_schedule")
 
     def autotune(self, cache_path=None, reps=10, force=False):
         from .autotune import tune_batch

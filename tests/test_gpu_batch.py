@@ -156,6 +156,23 @@ def test_batch_graph_equals_eager(rves, fp64_eager):
     b.close()
 
 
+@pytest.mark.parametrize("every,ticks", [(3, 0), (4, 8)])
+def test_batch_schedule_does_not_change_results(rves, fp64_eager, every, ticks):
+    """The Newton step every k-th step (direct launches or graph): the same
+    bits, iteration counts unchanged."""
+    P0, stats0, F0 = fp64_eager
+    b = make_batch(rves)
+    b.set_schedule(every)
+    P, stats, st = b.newton_solve(CASES, make_opts(**OPTS), graph_ticks=ticks)
+    F = batch_fields(b, rves)
+    b.close()
+    assert np.array_equal(P, P0)
+    for key in F0:
+        assert np.array_equal(F[key], F0[key]), key
+    for s, s0 in zip(stats, stats0):
+        assert s["newton_iters"] == s0["newton_iters"] and s["lin_iters_total"] == s0["lin_iters_total"]
+
+
 def test_batch_mixed_matches_fp64(rves, fp64_eager):
     """Mixed form of the batch (FP32 CG operator, FP64 Newton residual)."""
     P0, stats0, F0 = fp64_eager

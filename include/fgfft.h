@@ -278,8 +278,11 @@ int fg_batch_group_info(const fg_batch* batch, int group, int grid[3], int* nite
  * passes).  Results do not depend on
  * the tile: every column is transformed by the same arithmetic.  A tile of
  * the projection passes (1, 3) may carry FG_TILE_KY_MAJOR: its workgroups are
- * then ordered ky fastest instead of kx tile fastest. */
-enum { FG_TILE_KY_MAJOR = 0x10000 };
+ * then ordered ky fastest instead of kx tile fastest.  A tile of the
+ * single-precision N1 pass (2) may carry FG_TILE_COLUMN_PAIRS: each thread
+ * then owns two adjacent columns (one 16-byte access; tile / 2 x threads per
+ * line <= 256). */
+enum { FG_TILE_KY_MAJOR = 0x10000, FG_TILE_COLUMN_PAIRS = 0x20000 };
 /* Valid tiles of pass `which` into out[cap] (ascending, then for the
  * projection passes the same widths with FG_TILE_KY_MAJOR); returns how many
  * there are (may exceed cap), -1 on bad arguments. */

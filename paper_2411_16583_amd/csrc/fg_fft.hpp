@@ -389,8 +389,10 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
 // Element e of the line of column col: base + e * estride, with
 // base = data + blockIdx.y * ystride + blockIdx.z * zstride + blockIdx.x * B + col
 // (complex units).  Used for the N1 pass (estride = M) and, in the diagnostic
-// transforms, for the N0 pass (estride = N1 M).
-template <typename R, int L, bool INV>
+// transforms, for the N0 pass (estride = N1 M).  CPT = 2 (single precision):
+// each thread owns two adjacent columns, loaded and stored as one 16-byte
+// vector, so a tile of B columns takes T B / 2 threads.
+template <typename R, int L, bool INV, int CPT>
 __global__ void __launch_bounds__(256)
 k_fft_axis(R* data, long estride, long ystride, long zstride, int B, const cplx<R>* __restrict__ tw,
            Skip skip) {
@@ -399,16 +401,33 @@ k_fft_axis(R* data, long estride, long ystride, long zstride, int B, const cplx<
   extern __shared__ char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   if (skip((long)blockIdx.y + (long)gridDim.y * blockIdx.z)) return;  // unit: plane (y) of line set (z)
-  const int col = threadIdx.x % B;
-  const int t = threadIdx.x / B;
+  const int BC = B / CPT;  // column groups per tile
+  const int cg = threadIdx.x % BC;
+  const int t = threadIdx.x / BC;
   C* base = reinterpret_cast<C*>(data) + (long)blockIdx.y * ystride + (long)blockIdx.z * zstride +
-            (long)blockIdx.x * B + col;
-  C v[LS::E];
+            (long)blockIdx.x * B + CPT * cg;
+  if constexpr (CPT == 1) {
+    C v[LS::E];
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) v[e] = base[(long)LS::idxA(t, e) * estride];
-  line_fft_AB<L, INV>(v, lds + col, B, t, tw);
+    for (int e = 0; e < LS::E; ++e) v[e] = base[(long)LS::idxA(t, e) * estride];
+    line_fft_AB<L, INV>(v, lds + cg, B, t, tw);
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) base[(long)LS::idxB(t, e) * estride] = v[e];
+    for (int e = 0; e < LS::E; ++e) base[(long)LS::idxB(t, e) * estride] = v[e];
+  } else {
+    static_assert(CPT == 2 && sizeof(R) == 4, "column pairs in single precision");
+    C v0[LS::E], v1[LS::E];
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const float4 w = *reinterpret_cast<const float4*>(base + (long)LS::idxA(t, e) * estride);
+      v0[e] = mk<C>(w.x, w.y);
+      v1[e] = mk<C>(w.z, w.w);
+    }
+    line_fft_AB<L, INV>(v0, lds + 2 * cg, B, t, tw);
+    line_fft_AB<L, INV>(v1, lds + 2 * cg + 1, B, t, tw);
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e)
+      *reinterpret_cast<float4*>(base + (long)LS::idxB(t, e) * estride) = make_float4(v0[e].x, v0[e].y, v1[e].x, v1[e].y);
+  }
 }
 
 // ----------------------------------------------------------------------------

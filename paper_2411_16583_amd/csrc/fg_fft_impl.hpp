@@ -51,19 +51,34 @@ int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb,
 template <typename R>
 void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
                  const cplx<R>* tw, const Skip& skip, hipStream_t s, int tile) {
-  const int B = tile > 0 ? tile : column_tile(L, M, (int)sizeof(cplx<R>));
+  // single precision, on request: two columns per thread (16-byte accesses)
+  int cpt = (sizeof(R) == 4 && (tile & kTileColumnPairs)) ? 2 : 1;
+  tile &= ~kTileColumnPairs;
   const int T = line_threads(L);
+  const int B = tile > 0 ? tile : column_tile_cpt(L, M, (int)sizeof(cplx<R>), cpt);
+  if (B % cpt != 0) cpt = 1;
   const size_t shm = (size_t)L * B * sizeof(cplx<R>);
   dim3 grid((unsigned)(M / B), (unsigned)gy, (unsigned)gz);
+  const dim3 block((unsigned)(T * B / cpt));
+  constexpr int CP = (sizeof(R) == 4) ? 2 : 1;
   switch (L) {
-#define FG_CASE(L_)                                                                                  \
-  case L_:                                                                                           \
-    if (inv)                                                                                         \
-      hipLaunchKernelGGL((k_fft_axis<R, L_, true>), grid, dim3(T * B), shm, s, data, estride, ystride, \
-                         zstride, B, tw, skip);                                                      \
-    else                                                                                             \
-      hipLaunchKernelGGL((k_fft_axis<R, L_, false>), grid, dim3(T * B), shm, s, data, estride,       \
-                         ystride, zstride, B, tw, skip);                                             \
+#define FG_CASE(L_)                                                                                    \
+  case L_:                                                                                             \
+    if (cpt == 2) {                                                                                    \
+      if (inv)                                                                                         \
+        hipLaunchKernelGGL((k_fft_axis<R, L_, true, CP>), grid, block, shm, s, data, estride, ystride, \
+                           zstride, B, tw, skip);                                                      \
+      else                                                                                             \
+        hipLaunchKernelGGL((k_fft_axis<R, L_, false, CP>), grid, block, shm, s, data, estride, ystride, \
+                           zstride, B, tw, skip);                                                      \
+    } else {                                                                                           \
+      if (inv)                                                                                         \
+        hipLaunchKernelGGL((k_fft_axis<R, L_, true, 1>), grid, block, shm, s, data, estride, ystride,  \
+                           zstride, B, tw, skip);                                                      \
+      else                                                                                             \
+        hipLaunchKernelGGL((k_fft_axis<R, L_, false, 1>), grid, block, shm, s, data, estride, ystride, \
+                           zstride, B, tw, skip);                                                      \
+    }                                                                                                  \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE

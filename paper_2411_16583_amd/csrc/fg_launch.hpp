@@ -14,6 +14,8 @@ bool fft_axis_length_supported(int L);  // N0, N1
 // an exchange buffer of L * B complex values within 64 KiB.
 int column_tile(int L, int M, int elem_bytes);
 int column_tile_t(int T, int L, int M, int elem_bytes);
+// largest tile for cpt columns per thread: T tile / cpt <= 256 threads
+int column_tile_cpt(int L, int M, int elem_bytes, int cpt);
 int line_threads(int L);
 int zline_threads(int L);  // threads per line of the fused N0 projection pass
 
@@ -46,6 +48,9 @@ void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
                   hipStream_t s, int nitems = 1, int tile = 0);
 // Flag on a projection-pass tile: workgroups ordered ky fastest.
 constexpr int kTileKyMajor = 1 << 16;
+// Flag on an N1-pass tile in single precision: two adjacent columns per
+// thread (one 16-byte access; measured slower at 256^3, kept for the tuner).
+constexpr int kTileColumnPairs = 1 << 17;
 // Tile widths a pass accepts: powers of two dividing M with T tile <= 256
 // threads and an L x tile exchange buffer (plus the pass's tables) within
 // 64 KiB.  zproj: the fused N0 projection pass (L = N0), else the N1 pass.

@@ -57,6 +57,14 @@ int column_tile_t(int T, int L, int M, int elem_bytes) {
 
 int column_tile(int L, int M, int elem_bytes) { return column_tile_t(line_threads(L), L, M, elem_bytes); }
 
+int column_tile_cpt(int L, int M, int elem_bytes, int cpt) {
+  const int T = line_threads(L);
+  if (cpt <= 1 || M % cpt != 0) return column_tile_t(T, L, M, elem_bytes);
+  int B = cpt;
+  while ((M % (2 * B)) == 0 && T * 2 * B / cpt <= 256 && (long)L * 2 * B * elem_bytes <= 65536) B *= 2;
+  return B;
+}
+
 int zline_threads(int L) {
   if (L == 256) return Line3<256>::T;
   if (L == 128) return Line3<128>::T;
@@ -65,12 +73,21 @@ int zline_threads(int L) {
 }
 
 static_assert(kTileKyMajor == FG_TILE_KY_MAJOR, "public tile flag");
+static_assert(kTileColumnPairs == FG_TILE_COLUMN_PAIRS, "public tile flag");
 
 bool tile_valid(bool zproj, int L, int M, int elem_bytes, int tile) {
+  bool pairs = false;
   if (zproj && (tile & kTileKyMajor)) tile &= ~kTileKyMajor;
+  if (!zproj && elem_bytes == 8 && (tile & kTileColumnPairs)) {
+    tile &= ~kTileColumnPairs;
+    pairs = true;
+  }
   if (tile < 1 || (tile & (tile - 1)) != 0 || M % tile != 0) return false;
   const int T = zproj ? zline_threads(L) : line_threads(L);
-  if (T * tile > 256) return false;
+  // single-precision N1 pass with column pairs: tile / 2 column groups
+  if (pairs && tile % 2 != 0) return false;
+  const int cpt = pairs ? 2 : 1;
+  if (T * tile / cpt > 256) return false;
   // exchange buffer, plus the twiddles and kz tables of the projection pass
   // (the potential form of the projection stages one more kz table)
   const long lds = (long)L * tile * elem_bytes + (zproj ? 5L * L * elem_bytes / 2 : 0L);
@@ -1929,10 +1946,13 @@ int fg_plan_tile_candidates(const fg_plan* P, int which, int* out, int cap) {
   if (!P || which < 0 || which > 3 || (cap > 0 && !out)) return -1;
   const TilePass tp = tile_pass(which);
   int n = 0;
-  for (int order = 0; order < (tp.zproj ? 2 : 1); ++order)
-    for (int b = 1; b <= 256; b *= 2)
-      if (fg::tile_valid(tp.zproj, tile_len(P, which), P->M, tp.elem, b)) {
-        if (n < cap) out[n] = b | (order ? fg::kTileKyMajor : 0);
+  // variants: the projection passes in both workgroup orders; the
+  // single-precision N1 pass with one or two columns per thread
+  const int flag = tp.zproj ? fg::kTileKyMajor : (tp.elem == 8 ? fg::kTileColumnPairs : 0);
+  for (int variant = 0; variant < (flag ? 2 : 1); ++variant)
+    for (int b = 1; b <= 512; b *= 2)
+      if (fg::tile_valid(tp.zproj, tile_len(P, which), P->M, tp.elem, b | (variant ? flag : 0))) {
+        if (n < cap) out[n] = b | (variant ? flag : 0);
         ++n;
       }
   return n;
@@ -1958,8 +1978,9 @@ fg_status fg_plan_get_tiles(const fg_plan* P, int tiles[4]) {
     const TilePass tp = tile_pass(w);
     const int L = tile_len(P, w);
     const int T = tp.zproj ? fg::zline_threads(L) : fg::line_threads(L);
-    tiles[w] = P->tiles[w] > 0 ? P->tiles[w]
-                               : (fg::column_tile_t(T, L, P->M, tp.elem) | (tp.zproj ? fg::kTileKyMajor : 0));
+    const int built_in = tp.zproj ? (fg::column_tile_t(T, L, P->M, tp.elem) | fg::kTileKyMajor)
+                                  : fg::column_tile_t(T, L, P->M, tp.elem);
+    tiles[w] = P->tiles[w] > 0 ? P->tiles[w] : built_in;
   }
   return FG_OK;
 }

@@ -12,6 +12,7 @@ import torch
 import synth
 from oracle import constitutive as cm
 from oracle import mechanics, spectral
+from paper_2411_16583_amd import make_opts
 from tests.gpu_util import DEV, dt, host, plan_for, rel
 
 pytestmark = pytest.mark.gpu
@@ -193,3 +194,55 @@ def test_inclusion_newton_fp64_tight_matches_discrete_solution():
     Fg, sg = gpu[-1]
     fl = F - mechanics.uniform_field(work["loads"][-1], work["shape"])
     assert rel(Fg, F, fl) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_homogeneous_cell_exact_without_iterations(precision):
+    """Uniform material, c and d (any Fbar): F = Fbar exactly and no Newton
+    iteration (the normaliser floor of eq. (31) and exact zeros of the
+    transform of a constant field)."""
+    shape = (16, 24, 32)
+    work = synth.homogeneous_workload(shape, (1.0, 1.3, 0.8), E=37e9, nu=0.27, Omega=0.02)
+    plan = plan_for(work, precision)
+    F = dt(mechanics.uniform_field(np.eye(3), shape))
+    c = dt(np.full(shape, 0.3))
+    d = dt(np.full(shape, 0.2))
+    plan.set_state(F, c, d)
+    Fbar = np.eye(3) + np.array([[0.02, 0.005, 0.0], [-0.01, 0.01, 0.003], [0.0, 0.004, -0.015]])
+    st = plan.newton_solve(Fbar, make_opts(1e-12, 1e-12))
+    Fg = host(F, (3, 3) + shape)
+    print(f"homogeneous {precision}: newton {st['newton_iters']} err {st['err_res']:.1e}", flush=True)
+    assert st["newton_iters"] == 0 and st["err_res"] == 0.0
+    assert np.max(np.abs(Fg - mechanics.uniform_field(Fbar, shape))) <= 4e-16
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_laminate_exact_on_gpu(axis, precision, tol):
+    """Two-phase laminate normal to each axis: the GPU Newton-CG solution
+    equals the exact piecewise-constant solution voxel-wise (its spectrum
+    lies on the q_n axis, where the rotated vector is parallel to e_n)."""
+    from oracle import laminate
+
+    shape = [8, 8, 8]
+    shape[axis] = 12
+    shape = tuple(shape)
+    work = synth.homogeneous_workload(shape, (1.0, 1.2, 0.9))
+    mask = synth.laminate_mask(shape, axis, 5.0 / 12.0)
+    matA = dict(E=80e9, nu=0.21, Omega=0.03, c=0.2, d=0.3)
+    matB = dict(E=9e9, nu=0.34, Omega=0.0, c=0.0, d=0.0)
+    for k in ("E", "nu", "Omega"):
+        work[k] = np.where(mask, matA[k], matB[k])
+    c = np.where(mask, matA["c"], matB["c"])
+    d = np.where(mask, matA["d"], matB["d"])
+    Fbar = np.eye(3) + np.array([[0.04, 0.01, -0.02], [0.015, -0.01, 0.0], [0.0, 0.02, 0.01]])
+    FA, FB, a = laminate.laminate_solution(Fbar, axis, 5.0 / 12.0, matA, matB)
+    exact = np.where(mask[None, None], FA.reshape(3, 3, 1, 1, 1), FB.reshape(3, 3, 1, 1, 1))
+    plan = plan_for(work, precision)
+    F = dt(mechanics.uniform_field(np.eye(3), shape))
+    plan.set_state(F, dt(c), dt(d))
+    st = plan.newton_solve(Fbar, make_opts(1e-12, 1e-12))
+    Fg = host(F, (3, 3) + shape)
+    e = np.max(np.abs(Fg - exact)) / np.max(np.abs(exact - mechanics.uniform_field(Fbar, shape)))
+    print(f"laminate axis {axis} {precision}: newton {st['newton_iters']} rel {e:.1e}", flush=True)
+    assert e <= tol

@@ -293,11 +293,6 @@ struct C2REpi {
   bool self_dot;     // sum y*y
   double* partials;  // nullptr: no reduction
   Skip skip;         // per-item early exit (units: lines)
-  // CG residual update instead of a store: rupd <- rupd - alpha * y with the
-  // item's alpha (ks[item].alpha), partial sums of the new rupd . rupd
-  // (out unused).
-  void* rupd = nullptr;
-  const KrylovScalars* ks = nullptr;
 };
 
 template <typename R, int M>
@@ -344,24 +339,6 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
   const C* dv = reinterpret_cast<const C*>(epi.dotv) + line * M;
   const R sg = (R)epi.scale;
   double acc = 0.0;
-  if (epi.rupd) {
-    C* ru = reinterpret_cast<C*>(epi.rupd) + line * M;
-    const R al = (R)epi.ks[lm.item].alpha;
-#pragma unroll
-    for (int e = 0; e < LS::E; ++e) {
-      const int n = LS::idxB(t, e);
-      if (active) {
-        const C y = cscale(v[e], sg);
-        const C ro = ru[n];
-        const C rn = mk<C>(ro.x - al * y.x, ro.y - al * y.y);
-        ru[n] = rn;
-        acc += (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y;
-      }
-    }
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) epi.partials[blockIdx.x] = s;
-    return;
-  }
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
     const int n = LS::idxB(t, e);

@@ -700,8 +700,8 @@ void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_sol
   FG_HIP(hipMemcpyAsync(P->Fu, W, 9 * sizeof(double), hipMemcpyHostToDevice, P->stream));
   hipLaunchKernelGGL((k_fill_uniform9<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, pbuf, (const double*)P->Fu,
                      N);
-  hipLaunchKernelGGL((k_contract<T>), dim3(blocks_for(N / 2)), dim3(256), 0, P->stream, S, pbuf, (const T*)nullptr,
-                     (const T*)P->st, (const KrylovScalars*)nullptr, N, 0);
+  hipLaunchKernelGGL((k_contract<T>), dim3(blocks_for(N / 2)), dim3(256), 0, P->stream, S, (const T*)pbuf,
+                     (const T*)P->st, N);
   check_launch();
   {
     // b = -G*(G*(K:W)): the second projection keeps the right-hand side
@@ -1200,9 +1200,8 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
     const unsigned nbN = blocks_for(P->N);
     if (P->prec == FG_FP64) {
       constitutive(P, nullptr, nullptr, P->st, nullptr);
-      hipLaunchKernelGGL((k_contract<double>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, y, (double*)x,
-                         (const double*)nullptr,
-                         (const double*)P->st, (const KrylovScalars*)nullptr, P->N, 0);
+      hipLaunchKernelGGL((k_contract<double>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, y, x,
+                         (const double*)P->st, P->N);
       check_launch();
       C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
       project9<double>(P, y, y, y, epi);
@@ -1212,9 +1211,8 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
       float* yf = (float*)P->S;
       hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, xf, x,
                          n9);
-      hipLaunchKernelGGL((k_contract<float>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, yf, xf,
-                         (const float*)nullptr,
-                         (const float*)P->st, (const KrylovScalars*)nullptr, P->N, 0);
+      hipLaunchKernelGGL((k_contract<float>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, yf,
+                         (const float*)xf, (const float*)P->st, P->N);
       check_launch();
       C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
       project9<float>(P, yf, yf, yf, epi);

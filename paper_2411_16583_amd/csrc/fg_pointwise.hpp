@@ -139,51 +139,27 @@ k_tangent_apply_f64(const double* __restrict__ F, const double* __restrict__ c, 
   for (int k = 0; k < 9; ++k) Y[k * N + i] = y[k];
 }
 
-// CG direction update fused with the tangent contraction:
-//   p <- r (first iteration) or r + beta p;  Y = K : p.
-// With update == false: Y = K : p for the given p (no CG state).
-// Two voxels per thread (one 2-vector load per plane); N is even.
+// Tangent contraction Y = K : X from the 12-word state (one application of
+// K outside the CG, e.g. the operator diagnostic and the adjoint's
+// right-hand side).  Two voxels per thread (one 2-vector load per plane); N
+// is even.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_contract(T* __restrict__ Y, T* __restrict__ p, const T* __restrict__ r, const T* __restrict__ st,
-           const KrylovScalars* __restrict__ ks, long N, int update) {
+k_contract(T* __restrict__ Y, const T* __restrict__ X, const T* __restrict__ st, long N) {
   using V = cplx<T>;
-  if (ks && ks->done) return;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N2v = N / 2;
   if (i >= N2v) return;
-  V* pv = reinterpret_cast<V*>(p);
-  const V* rv = reinterpret_cast<const V*>(r);
+  const V* xv = reinterpret_cast<const V*>(X);
   const V* sv = reinterpret_cast<const V*>(st);
   V* yv = reinterpret_cast<V*>(Y);
-  T X0[9], X1[9];
-  if (update) {
-    const bool first = ks->iter == 0;
-    const T beta = (T)ks->beta;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const V rk = rv[k * N2v + i];
-      V pk = rk;
-      if (!first) {
-        const V po = pv[k * N2v + i];
-        pk = mk<V>(rk.x + beta * po.x, rk.y + beta * po.y);
-      }
-      pv[k * N2v + i] = pk;
-      X0[k] = pk.x;
-      X1[k] = pk.y;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const V pk = pv[k * N2v + i];
-      X0[k] = pk.x;
-      X1[k] = pk.y;
-    }
-  }
-  T A0[9], A1[9];
+  T X0[9], X1[9], A0[9], A1[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
+    const V x = xv[k * N2v + i];
     const V a = sv[k * N2v + i];
+    X0[k] = x.x;
+    X1[k] = x.y;
     A0[k] = a.x;
     A1[k] = a.y;
   }

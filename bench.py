@@ -17,6 +17,7 @@ its average launch duration comes from HIP events on the plan stream.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--n 256] [--no-cpu]
     python bench.py --batch [--batch-items 48] [--graph-ticks 16]   (batched form)
+    python bench.py --coupled [--steps 3] [--warmup 1]   (coupled path, particle 128^3)
 """
 from __future__ import annotations
 
@@ -38,8 +39,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # fields; the spectrum occupies the same bytes as the real field).
 WORDS_PER_VOXEL = {
     "front": 66,      # read r, p, x (27) + state (12); write x, p, spectrum (27)
-    "axis": 18,       # N1 pass of the 9-component spectrum: read 9, write 9
-    "zproj": 12,      # N0 pass + projection to the potential: read 9, write 3
+    "axis": 15,       # N1 pass of the 9-component spectrum: read 9, write 6 (2 merged fields per row)
+    "zproj": 9,       # N0 pass + projection to the potential: read 6, write 3
     "axis3": 6,       # inverse N1 pass of the potential: read 3, write 3
     "c2r3": 6,        # inverse N2 pass of the potential: read 3, write 3
     "grad": 21,       # corner-stencil gradient + r -= alpha Ap: read U 3 + r 9, write r 9
@@ -58,6 +59,9 @@ def parse():
     ap.add_argument("--batch", action="store_true",
                     help="the batched form instead: 48 ragged RVEs x 6 load cases (effective stiffness), batched "
                          "FP64 and mixed against the 288 single-item FP64 solves")
+    ap.add_argument("--coupled", action="store_true",
+                    help="the coupled path instead: staggered steps (Fick, Newton-CG, phase field) of the 128^3 "
+                         "particle workload, FP64 and mixed")
     ap.add_argument("--batch-items", type=int, default=48)
     ap.add_argument("--graph-ticks", type=int, default=16)
     ap.add_argument("--newton-every", type=int, default=4,
@@ -316,6 +320,99 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def run_coupled(args):
+    """Coupled path: time steps of Alg. 4 on the particle workload (inward
+    flux on the particle's inner shell, swelling, damage), each step one
+    backward-Euler Fick step, then Newton-CG and the phase-field PCG
+    alternating until the equilibrium residual with the new damage is below
+    tol.  value = time steps per second (FP64); the mixed form runs the same
+    steps, and the final c, d and F of both forms are compared."""
+    import torch
+
+    import synth
+    from paper_2411_16583_amd import Plan
+    from paper_2411_16583_amd.driver import staggered_step
+
+    n = args.n if args.n != 256 else 128
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    work = synth.particle_workload(n=n)
+    shape = work["shape"]
+    N = int(np.prod(shape))
+    res, fields = {}, {}
+    for form in ("fp64", "mixed"):
+        plan = Plan(shape, work["spacing"], form)
+        mats = [t(work[k]) for k in ("E", "nu", "Omega", "D", "sigma_max")]
+        plan.set_material(*mats, gc=work["gc"], lc=work["lc"], RT=work["RT"], c_max=work["c_max"])
+        F = torch.zeros((9,) + shape, dtype=torch.float64, device=dev)
+        F[0] = 1.0
+        F[4] = 1.0
+        F[8] = 1.0
+        c, d, H = t(work["c0"]), t(work["d0"]), torch.zeros(shape, dtype=torch.float64, device=dev)
+        plan.set_state(F, c, d, H)
+        cdot = t(work["cdot_B"])
+        kw = dict(dt=work["dt"], cdot_B=cdot, chemistry=True)
+        for k in range(args.warmup):
+            staggered_step(plan, work["loads"][k], **kw)
+        torch.cuda.synchronize()
+        plan.profile_begin()
+        cg = pcg = chem = stag = 0
+        t0 = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            st = staggered_step(plan, work["loads"][k], **kw)
+            cg += sum(s_["lin_iters_total"] for s_ in st["newton"])
+            pcg += sum(s_["lin_iters_last"] for s_ in st["pff"])
+            chem += st["chem"]["lin_iters_total"]
+            stag += st["stag_iters"]
+            print(f"[coupled {form}] step {k + 1}: staggered {st['stag_iters']}, newton CG "
+                  f"{[s_['lin_iters_total'] for s_ in st['newton']]}, pff {[s_['lin_iters_last'] for s_ in st['pff']]}, "
+                  f"fick {st['chem']['newton_iters']} Newton / {st['chem']['lin_iters_total']} PCG, "
+                  f"err {st['err_res']:.1e}", flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = plan.profile_end()
+        res[form] = dict(elapsed=el, cg=cg, pcg=pcg, chem=chem, stag=stag, prof=prof)
+        fields[form] = (c.cpu().numpy(), d.cpu().numpy(), F.cpu().numpy())
+        plan.close()
+        del F, c, d, H, mats, cdot
+        torch.cuda.empty_cache()
+
+    def rdiff(a, b, ref):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(ref), 1e-300))
+
+    cf, df, Ff = fields["fp64"]
+    cm_, dm, Fm = fields["mixed"]
+    c0 = work["c0"]
+    eye = np.eye(3).reshape(9, 1, 1, 1)
+    f64, mx = res["fp64"], res["mixed"]
+    line = {
+        "metric": f"coupled staggered time steps/s (particle {n}^3: Fick BE + Newton-CG + phase-field PCG)",
+        "value": args.steps / f64["elapsed"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * f64["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"particle {n}^3 (ellipsoid 40/32/28 voxels at 128^3, buffer 1e-3 E), flux "
+                               f"4e-10 m/s on the inner shell, dt = {work['dt']} s, Omega = 0.03, sigma_max = 20 MPa",
+                   "voxels": N},
+        "fp64": dict(cg_iters=f64["cg"], pff_pcg_iters=f64["pcg"], fick_pcg_iters=f64["chem"],
+                     staggered_iters=f64["stag"], per_class=per_class(f64["prof"], N, 8),
+                     voxel_cg_iters_per_s=N * f64["cg"] / f64["elapsed"]),
+        "mixed": dict(ms_per_step=1e3 * mx["elapsed"] / args.steps, cg_iters=mx["cg"], pff_pcg_iters=mx["pcg"],
+                      fick_pcg_iters=mx["chem"], staggered_iters=mx["stag"],
+                      speedup_per_step=f64["elapsed"] / mx["elapsed"],
+                      rel_diff_c=rdiff(cm_, cf, cf - c0), rel_diff_d=rdiff(dm, df, df) if np.any(df) else 0.0,
+                      rel_diff_F=rdiff(Fm, Ff, Ff - eye)),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -326,6 +423,9 @@ def main():
 
     if args.batch:
         run_batch(args)
+        return
+    if args.coupled:
+        run_coupled(args)
         return
     t0 = time.perf_counter()
     work = synth.polydisperse_workload(n=args.n)

@@ -12,6 +12,8 @@
 // (k1, k2) = (g % R1, g / R1), g = t + T z, e = z R3 + k3.
 // The inverse runs the stages backwards with conjugate twiddles (B -> A).
 #pragma once
+#include <type_traits>
+
 #include "fg_fft.hpp"
 
 namespace fg {
@@ -240,6 +242,87 @@ k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip
 }
 
 
+// Element at a 32-bit byte offset from a base pointer.
+template <typename T> __device__ __forceinline__ T& at_bytes(T* base, unsigned byte_off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
+// Forward N1 pass of the projection in its potential form, one row i of the
+// 3x3 field per workgroup.  With the rotated-scheme vector r of eq. (28),
+//   sum_l A_il r_l = sz (cy cx A_i0) + cz (sy cx A_i1 + cy sx A_i2)
+// (c* = cos(q/2), s* = (2/h) sin(q/2) per axis), so the two terms sharing the
+// N0 factor cz are merged here, after their N1 transform, and the fused N0
+// pass transforms two fields per row instead of three.  Writes
+//   slot 3i     <- cy cx A_i0
+//   slot 3i + 1 <- sy cx A_i1 + cy sx A_i2
+// and leaves slot 3i + 2, which nothing reads afterwards.  The kx = 0 column
+// packs the real columns kx = 0 and kx = N2/2, whose factors differ: it is
+// stored transformed, unscaled and unmerged in all three slots (k_fft_z_dc
+// separates it).  Grid (M/B, N0, 3 rows per item); element e of component l
+// of the row: data + blockIdx.z * zstride + blockIdx.y * ystride + l * cstride
+// + e * estride + kx.  The line transform's twiddles are staged in LDS.
+// The loads of the next component are issued before the current one is
+// transformed (its registers are free by then).
+// Line transform of k_fft_axis_rows: three stages in double precision (two
+// 16-element lines per thread would not fit the registers), two stages in
+// single precision (measured faster at N1 = 256).
+template <typename R, int L> using RowLine = typename std::conditional<sizeof(R) == 8, ZLine<L>, Line2Ops<L>>::type;
+
+template <typename R, int L>
+__global__ void __launch_bounds__(256)
+k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride, int B, SpecTables<R> tb,
+                Skip skip) {
+  using C = cplx<R>;
+  using LS = RowLine<R, L>;
+  extern __shared__ char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C* stw = lds + L * B;
+  if (skip((long)blockIdx.y + (long)gridDim.y * blockIdx.z)) return;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) stw[k] = tb.tw1[k];
+  __syncthreads();
+  const R* scy = tb.cy;
+  const R* ssy = tb.sy;
+  const int col = threadIdx.x % B;
+  const int t = threadIdx.x / B;
+  const int kx = blockIdx.x * B + col;
+  const bool dc = kx == 0;
+  const R cx = tb.cx[kx], sx = tb.sx[kx];
+  // workgroup-uniform bases of the three slots and a 32-bit element offset
+  // per thread (within one plane of one component)
+  C* b0 = reinterpret_cast<C*>(data) + (long)blockIdx.z * zstride + (long)blockIdx.y * ystride + (long)blockIdx.x * B;
+  C* b1 = b0 + cstride;
+  C* b2 = b1 + cstride;
+  // byte offsets in 32 bits (one plane of one component), so that every
+  // access is a uniform base plus one 32-bit register
+  const unsigned ues = (unsigned)(estride * (long)sizeof(C));
+  const unsigned ucol = (unsigned)(col * sizeof(C));
+  auto offA = [&](int e) { return ucol + (unsigned)LS::idxA(t, e) * ues; };
+  auto offB = [&](int e) { return ucol + (unsigned)LS::idxB(t, e) * ues; };
+  C v[LS::E], acc[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = at_bytes(b0, offA(e));
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) acc[e] = at_bytes(b1, offA(e));
+  LS::template fwd<false>(v, lds + col, B, t, stw);
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) at_bytes(b0, offB(e)) = dc ? v[e] : cscale(v[e], scy[LS::idxB(t, e)] * cx);
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = at_bytes(b2, offA(e));
+  LS::template fwd<false>(acc, lds + col, B, t, stw);
+  LS::template fwd<false>(v, lds + col, B, t, stw);
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    const int ky = LS::idxB(t, e);
+    if (dc) {
+      at_bytes(b2, offB(e)) = v[e];
+    } else {
+      const R f1 = ssy[ky] * cx, f2 = scy[ky] * sx;
+      acc[e] = mk<C>(acc[e].x * f1 + v[e].x * f2, acc[e].y * f1 + v[e].y * f2);
+    }
+    at_bytes(b1, offB(e)) = acc[e];
+  }
+}
+
 // LDS bytes of k_fft_z_grad3 beyond the L x B exchange buffer: the stage
 // twiddles and three kz tables (cos, scaled sin, sin).
 template <typename R> constexpr size_t zgrad_extra_lds(int L) {
@@ -253,11 +336,13 @@ template <typename R> constexpr size_t zgrad_extra_lds(int L) {
 //   (D_j U)[n] = 1/(4 h_j) sum over the 4 edges of the voxel parallel to j
 //                of the corner difference (corner n - 1/2 stored at n - 1)
 // has the symbol i e^{-i Phi} r_j.  Only U is transformed back (one inverse
-// per row instead of three); U_i is stored in component slot 3 i of the item
-// (the slot of A_i0, which only this workgroup reads for its columns), and
-// the gradient is formed in real space by k_cg_grad.  Grid (M/B, N1, 3 rows
-// per item), or (N1, M/B, rows) with kymajor.  The kx = 0 column is left to
-// k_fft_z_dc<OP = 2>.
+// per row instead of three); U_i is stored in component slot 3 i of the item,
+// and the gradient is formed in real space by k_cg_grad.  The input is the
+// output of k_fft_axis_rows: slot 3i holds cy cx A_i0 and slot 3i + 1 holds
+// sy cx A_i1 + cy sx A_i2, so that sum_l A_il r_l = sz X_0 + cz X_1 after the
+// N0 transforms X_0, X_1 of the two slots (two forward transforms and one
+// inverse per row).  Grid (M/B, N1, 3 rows per item), or (N1, M/B, rows) with
+// kymajor.  The kx = 0 column is left to k_fft_z_dc<OP = 2>.
 template <typename R, int L>
 __global__ void __launch_bounds__(256)
 k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor) {
@@ -284,56 +369,31 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   const int i = blockIdx.z;  // row of the 3x3 field, items consecutive
   const long plane = (long)N1 * M;
   const long comp = (long)L * plane;
+  // workgroup-uniform base of the row's first slot and a 32-bit element
+  // offset per thread (col + kz plane; a component is < 2^32 bytes)
+  C* base = reinterpret_cast<C*>(data) + (long)(3 * i) * comp + (long)ky * M + (kx - col);
+  const unsigned uplane = (unsigned)plane;
+  const unsigned ucomp = (unsigned)comp;
+  C v[LS::E], acc[LS::E];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) v[e] = base[(unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) acc[e] = base[ucomp + (unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
   const R cy = tb.cy[ky], sy = tb.sy[ky], cx = tb.cx[kx], sx = tb.sx[kx];
   const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
   // -i e^{i (qy + qx) / 2}; the kz factor is applied per element
   const C eyx = mul_mi(cmul(mk<C>(cy, tb.sny[ky]), mk<C>(cx, tb.snx[kx])));
-  // workgroup-uniform base of the row's first component and a 32-bit
-  // element offset per thread (col + kz plane; a component is < 2^32 bytes)
-  C* base = reinterpret_cast<C*>(data) + (long)(3 * i) * comp + (long)ky * M + (kx - col);
-  const unsigned uplane = (unsigned)plane;
-  const unsigned ucomp = (unsigned)comp;
-  C acc[LS::E];
-#pragma unroll
-  for (int e = 0; e < LS::E; ++e) acc[e] = mk<C>(R(0), R(0));
-  // double precision: component l + 1 is loaded while component l is
-  // transformed, where the extra registers fit (up to 8 complex per thread);
-  // measured slower in single precision
-  constexpr bool PREFETCH = sizeof(R) == 8 && sizeof(C) * LS::E <= 128;
-  C v[LS::E];
-#pragma unroll
-  for (int e = 0; e < LS::E; ++e) v[e] = base[(unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
-#pragma unroll 1
-  for (int l = 0; l < 3; ++l) {
-    C vn[LS::E];
-    if (!PREFETCH && l > 0) {
-#pragma unroll
-      for (int e = 0; e < LS::E; ++e) v[e] = base[(unsigned)l * ucomp + (unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
-    }
-    if (PREFETCH && l < 2) {
-#pragma unroll
-      for (int e = 0; e < LS::E; ++e)
-        vn[e] = base[(unsigned)(l + 1) * ucomp + (unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
-    }
-    LS::template fwd<false>(v, lds + col, B, t, stw);
-#pragma unroll
-    for (int e = 0; e < LS::E; ++e) {
-      const int kz = LS::idxB(t, e);
-      const R rl = (l == 0) ? ssz[kz] * fx0 : scz[kz] * (l == 1 ? fx1 : fx2);
-      acc[e] = mk<C>(acc[e].x + v[e].x * rl, acc[e].y + v[e].y * rl);
-    }
-    if (PREFETCH && l < 2) {
-#pragma unroll
-      for (int e = 0; e < LS::E; ++e) v[e] = vn[e];
-    }
-  }
+  LS::template fwd<false>(v, lds + col, B, t, stw);
+  LS::template fwd<false>(acc, lds + col, B, t, stw);
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
     const int kz = LS::idxB(t, e);
-    const R a = ssz[kz] * fx0, b = scz[kz] * fx1, c = scz[kz] * fx2;
+    const R sz = ssz[kz], cz = scz[kz];
+    const R a = sz * fx0, b = cz * fx1, c = cz * fx2;
     const R r2 = a * a + b * b + c * c;
     const R f = (r2 > R(0)) ? scale / r2 : R(0);
-    acc[e] = cmul(cscale(acc[e], f), cmul(mk<C>(scz[kz], snz[kz]), eyx));
+    const C w = mk<C>((v[e].x * sz + acc[e].x * cz) * f, (v[e].y * sz + acc[e].y * cz) * f);
+    acc[e] = cmul(w, cmul(mk<C>(cz, snz[kz]), eyx));
   }
   LS::inv(acc, lds + col, B, t, stw);
   if (kx != 0) {

@@ -87,6 +87,32 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 }
 
 template <typename R>
+void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
+                      int nitems, int tile) {
+  tile &= ~kTileColumnPairs;
+  const int T = sizeof(R) == 8 ? zline_threads(N1) : line_threads(N1);  // threads of RowLine<R, N1>
+  int B = tile > 0 ? tile : column_tile_t(T, N1, M, (int)sizeof(cplx<R>));
+  // the N1 tile is shared with launch_axis, whose lines take fewer threads:
+  // halve it until the workgroup and its LDS (exchange buffer + twiddles) fit
+  while (B > 1 && (T * B > 256 || (size_t)N1 * (B + 1) * sizeof(cplx<R>) > 65536)) B /= 2;
+  const size_t shm = (size_t)N1 * (B + 1) * sizeof(cplx<R>);
+  const long plane = (long)N1 * M;
+  // planes y = i0, z = row (3 per item); components of a row n0 planes apart
+  dim3 grid((unsigned)(M / B), (unsigned)N0, (unsigned)(3 * nitems));
+  const Skip sk = skip.unit(3L * N0);
+  switch (N1) {
+#define FG_CASE(L_)                                                                                    \
+  case L_:                                                                                             \
+    hipLaunchKernelGGL((k_fft_axis_rows<R, L_>), grid, dim3(T * B), shm, s, data, (long)M, plane,       \
+                       3L * N0 * plane, (long)N0 * plane, B, tb, sk);                                  \
+    return;
+    FG_FOR_AXIS(FG_CASE)
+#undef FG_CASE
+  }
+  throw std::invalid_argument("unsupported axis length");
+}
+
+template <typename R>
 void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
                   hipStream_t s, int nitems, int tile) {
   const int T = zline_threads(N0);
@@ -182,6 +208,7 @@ int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const K
   template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t); \
   template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const Skip&, \
                                hipStream_t, int);                                                       \
+  template void launch_axis_rows<R>(int, R*, int, int, const SpecTables<R>&, const Skip&, hipStream_t, int, int); \
   template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
   template void launch_zgrad<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
   template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const Skip&, \

@@ -36,13 +36,21 @@ int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb,
 template <typename R>
 void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
                  const cplx<R>* tw, const Skip& skip, hipStream_t s, int tile = 0);
+// Forward N1 pass of the potential-form projection for nitems 9-component
+// fields: per row, the two terms sharing the N0 factor are merged (slots
+// 3i, 3i + 1 written; kx = 0 column unmerged in all three slots).  tile as
+// for launch_axis (a column-pair flag is ignored).
+template <typename R>
+void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
+                      int nitems = 1, int tile = 0);
 // N0 pass fused with the projection, for nitems 9-component fields (3 rows
 // each).
 template <typename R>
 void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
                   hipStream_t s, int nitems = 1, int tile = 0);
-// N0 pass fused with the projection in the potential form (3 components
-// written per item, slots 0..2), and its kx = 0 companion.
+// N0 pass fused with the projection in the potential form, on the output of
+// launch_axis_rows (the potential U_i written to slot 3i of each item), and
+// its kx = 0 companion.
 template <typename R>
 void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
                   hipStream_t s, int nitems = 1, int tile = 0);

@@ -517,8 +517,9 @@ void inv_potential(fg_plan* P, R* data, const Skip& skip) {
 // One CG iteration for every item of the plan (items whose solve is done
 // skip every kernel):
 //   x += alpha_{k-1} p_{k-1}; p = r + beta p; Y = K:p; p.Y; N2 pass of Y
-//   alpha = r.r / p.Kp; N1 pass (9 components); N0 pass reducing the
-//   projection to the 3-component potential; N1 and N2 inverse passes of
+//   alpha = r.r / p.Kp; N1 pass (9 components in, the two terms of each row
+//   that share the N0 factor merged); N0 pass reducing the projection to
+//   the 3-component potential; N1 and N2 inverse passes of
 //   the potential; r -= alpha G(K p) with G(K p) = D U from the corner
 //   stencil, r.r; beta, convergence.
 template <typename T>
@@ -542,8 +543,7 @@ void cg_iteration(fg_plan* P) {
   }
   {
     ProfScope ps(P, FG_PASS_AXIS);
-    launch_axis<T>(P->n1, false, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * nit, 1, tb.tw1,
-                   skip.unit(9L * P->n0), P->stream, tile_axis<T>(P));
+    launch_axis_rows<T>(P->n1, S, P->n0, P->M, tb, skip, P->stream, nit, tile_axis<T>(P));
   }
   {
     ProfScope ps(P, FG_PASS_ZPROJ);
@@ -1237,7 +1237,11 @@ fg_status fg_project_grad(fg_plan* P, const double* x, double* y) {
   if (!P || !x || !y || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
-    fwd_xy<double>(P, x, P->S64, 9, Skip{});
+    {
+      ProfScope ps(P, FG_PASS_R2C);
+      launch_r2c<double>(P->M, x, P->S64, 9L * P->n0 * P->n1, P->t64.spec(), Skip{}, P->stream);
+    }
+    launch_axis_rows<double>(P->n1, P->S64, P->n0, P->M, P->t64.spec(), Skip{}, P->stream, 1, tile_axis<double>(P));
     launch_zgrad<double>(P->n0, P->S64, P->n1, P->M, P->t64.spec(), 1.0 / (double)P->N, Skip{}, P->stream, 1,
                          tile_zproj<double>(P));
     inv_potential<double>(P, P->S64, Skip{});
@@ -1909,11 +1913,15 @@ void time_pass_impl(fg_plan* P, bool zproj, int tile, int reps, double* ms) {
   check_launch();
   const SpecTables<R> tb = tabs<R>(P).spec();
   auto launch = [&]() {
-    if (zproj)
+    if (zproj) {
       launch_zgrad<R>(P->n0, S, P->n1, P->M, tb, (R)(1.0 / (double)P->N), Skip{}, P->stream, P->nitems, tile);
-    else
-      launch_axis<R>(P->n1, false, S, P->M, (long)P->n1 * P->M, 0, P->M, 9 * P->n0 * P->nitems, 1, tb.tw1, Skip{},
-                     P->stream, tile);
+    } else {
+      // the N1 work of a CG iteration: the forward row pass and the inverse
+      // pass of the potential
+      launch_axis_rows<R>(P->n1, S, P->n0, P->M, tb, Skip{}, P->stream, P->nitems, tile);
+      launch_axis<R>(P->n1, true, S, P->M, (long)P->n1 * P->M, 3L * P->n0 * P->n1 * P->M, P->M, P->n0,
+                     3 * P->nitems, tb.tw1, Skip{}, P->stream, tile);
+    }
   };
   hipEvent_t e0, e1;
   FG_HIP(hipEventCreate(&e0));

@@ -118,7 +118,7 @@ def test_bench_byte_model_and_roofline():
 
     N = 256 ** 3
     # words per voxel per CG iteration of the kernels on the path
-    assert sum(bench.WORDS_PER_VOXEL[k] for k in ("front", "axis", "zproj", "axis3", "c2r3", "grad")) == 129
+    assert sum(bench.WORDS_PER_VOXEL[k] for k in ("front", "axis", "zproj", "axis3", "c2r3", "grad")) == 123
     prof = {k: (0.0, 0) for k in ["front", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive",
                                   "zscalar", "axis3", "c2r3", "grad"]}
     prof["front"] = (1693.2 * 10 / 1e3, 10)  # 10 launches of 1693.2 us

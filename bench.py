@@ -38,12 +38,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # mechanics CG iteration, in words of the working precision (9-component
 # fields; the spectrum occupies the same bytes as the real field).
 WORDS_PER_VOXEL = {
-    "front": 66,      # read r, p, x (27) + state (12); write x, p, spectrum (27)
+    "front": 36,      # read rho, pi, xi (9) + state (12); write xi, pi (6), spectrum (9)
     "axis": 15,       # N1 pass of the 9-component spectrum: read 9, write 6 (2 merged fields per row)
     "zproj": 9,       # N0 pass + projection to the potential: read 6, write 3
     "axis3": 6,       # inverse N1 pass of the potential: read 3, write 3
     "c2r3": 6,        # inverse N2 pass of the potential: read 3, write 3
-    "grad": 21,       # corner-stencil gradient + r -= alpha Ap: read U 3 + r 9, write r 9
+    "grad": 9,        # rho -= alpha U and |D rho|^2: read U 3 + rho 3, write rho 3
 }
 
 

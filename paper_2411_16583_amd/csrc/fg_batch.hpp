@@ -122,22 +122,6 @@ k_newton_cg_start(const double* __restrict__ partials, int nparts, KrylovScalars
 }
 
 // Per-item field kernels: grid.y = item, n values per item; masked by idle.
-// x += alpha p (the last deferred CG update), as k_cg_final_x.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_items_final_x(T* __restrict__ x, const T* __restrict__ p, const KrylovScalars* __restrict__ ks,
-                const int* __restrict__ idle, long n) {
-  const int b = blockIdx.y;
-  if (idle[b]) return;
-  const KrylovScalars& k = ks[b];
-  if (k.flag == 1 || k.iter == 0) return;
-  const T alpha = (T)k.alpha;
-  x += (long)b * n;
-  p += (long)b * n;
-  const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] += alpha * p[i];
-}
-
 // F += dF (dF in type T).
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -148,35 +132,6 @@ k_items_axpy(double* __restrict__ F, const T* __restrict__ dF, const int* __rest
   dF += (long)b * n;
   const long stride = (long)gridDim.x * blockDim.x;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) F[i] += (double)dF[i];
-}
-
-// dst = (B) src.
-template <typename A, typename B>
-__global__ void __launch_bounds__(256)
-k_items_convert(B* __restrict__ dst, const A* __restrict__ src, const int* __restrict__ idle, long n) {
-  const int b = blockIdx.y;
-  if (idle[b]) return;
-  dst += (long)b * n;
-  src += (long)b * n;
-  const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (B)src[i];
-}
-
-// CG start of an item: r = (T) b, x = 0.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_items_rhs(T* __restrict__ r, T* __restrict__ x, const double* __restrict__ rhs, const int* __restrict__ idle,
-            long n) {
-  const int b = blockIdx.y;
-  if (idle[b]) return;
-  r += (long)b * n;
-  x += (long)b * n;
-  rhs += (long)b * n;
-  const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    r[i] = (T)rhs[i];
-    x[i] = T(0);
-  }
 }
 
 }  // namespace fg

@@ -1,8 +1,11 @@
-// Front kernel of one CG iteration on the operator of eq. (30), fused:
-//   x <- x + alpha_{k-1} p_{k-1}          (deferred solution update, k > 0)
-//   p <- r (k = 0) or r + beta p          (search direction)
-//   Y  = K : p                            (tangent contraction, 12-word state)
-//   p . Y per block (FP64)                (= p . G(K p) since p is compatible)
+// Front kernel of one CG iteration on the operator of eq. (30), fused, with
+// the CG vectors held as 3-component potentials (r = D rho, p = D pi,
+// x = D xi, D the corner-stencil gradient of fg_potential.hpp):
+//   xi <- xi + alpha_{k-1} pi_{k-1}        (deferred solution update, k > 0)
+//   pi <- rho (k = 0) or rho + beta pi     (search direction)
+//   p  = D pi                              (9 components, never stored)
+//   Y  = K : p                             (tangent contraction, 12-word state)
+//   p . Y per block (FP64)                 (= p . G(K p) since p is compatible)
 //   Y -> packed real-to-complex transform along N2, written as the spectrum.
 // The contracted field never goes to HBM: it is staged in LDS, line by line,
 // and transformed there.
@@ -10,9 +13,13 @@
 // A workgroup owns LB grid lines (i0, i1) and all 9 components of them:
 // phase A is one thread per 2 or 4 voxels (coalesced along N2), phase B is the
 // two-stage line FFT of the 9 LB complex lines with T threads each
-// (9 LB T = 144 threads).
+// (9 LB T = 144 threads).  The stencil needs pi at the corners of the lines
+// (i0 - 1, i1), (i0, i1 - 1), (i0 - 1, i1 - 1) too; it recomputes them from
+// rho and the old pi there (read through the caches), and the new pi goes to
+// the other parity half, so no workgroup reads what another one writes.
 #pragma once
 #include "fg_fft.hpp"
+#include "fg_potential.hpp"
 #include "fg_tangent.hpp"
 
 namespace fg {
@@ -50,9 +57,9 @@ template <int M> struct FrontShape {
 
 template <typename R, int M>
 __global__ void __launch_bounds__(FrontShape<M>::THREADS)
-k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* __restrict__ r,
+k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, const R* __restrict__ rbuf,
            const R* __restrict__ st, const KrylovScalars* __restrict__ ksb, double* __restrict__ partials,
-           long N, long nlines, SpecTables<R> tb) {
+           long N, int n0, int n1, SpecTables<R> tb, R q0, R q1, R q2) {
   using C = cplx<R>;
   using LS = Line<M>;
   using FS = FrontShape<M>;
@@ -60,6 +67,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
   constexpr int LB = FS::LB;
   __shared__ C buf[9 * LB * FS::LSTRIDE];
   __shared__ double red[16];
+  const long nlines = (long)n0 * n1;
   // batch item of this workgroup (items are nlines lines of 9 components
   // each, item-major; ceil(nlines / LB) workgroups per item)
   const long bpi = (nlines + LB - 1) / LB;
@@ -67,15 +75,19 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
   const KrylovScalars* ks = ksb + item;
   if (ks->done) return;
   spec += (long)item * 9 * N;
-  p += (long)item * 9 * N;
-  x += (long)item * 9 * N;
-  r += (long)item * 9 * N;
+  pbuf += (long)item * 9 * N;
+  xbuf += (long)item * 9 * N;
+  rbuf += (long)item * 9 * N;
   st += (long)item * 12 * N;
   const int tid = threadIdx.x;
   const long line0 = ((long)blockIdx.x - (long)item * bpi) * LB;
-  const bool first = ks->iter == 0;
+  const int iter = ks->iter;
+  const bool first = iter == 0;
   const R alpha = (R)ks->alpha;
   const R beta = (R)ks->beta;
+  const R* rho = rbuf + pot_half(iter, N);
+  const R* po = pbuf + pot_half(iter + 1, N);
+  R* pn = pbuf + pot_half(iter, N);
   double acc = 0.0;
   // ---- phase A: pointwise, W voxels per thread and step (one W-vector
   // access per plane; W = 4 in single precision, else 2)
@@ -83,41 +95,49 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
   using PV = typename FrontPack<R, W>::type;
   constexpr int GPL = 2 * M / W;  // voxel groups per line
   const long Nw = N / W;
-  const PV* rv = reinterpret_cast<const PV*>(r);
   const PV* sv = reinterpret_cast<const PV*>(st);
-  PV* pv = reinterpret_cast<PV*>(p);
-  PV* xv = reinterpret_cast<PV*>(x);
   for (int v = tid; v < LB * GPL; v += FS::THREADS) {
     const int l = v / GPL;
     const int n = v % GPL;  // voxels W n .. W n + W - 1 of line l
     if (line0 + l >= nlines) continue;
     const long g = (line0 + l) * GPL + n;
-    PV rk[9], po[9], A[9];
+    const StencilLines sl = stencil_lines(line0 + l, W * n, n0, n1, N2);
+    R X[W][9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      rk[k] = rv[k * Nw + g];
-      if (!first) po[k] = pv[k * Nw + g];
+    for (int c = 0; c < 3; ++c) {
+      R u[2][2][W + 1];
+      load_corners<R, W>(rho + c * N, sl, u);
+      if (!first) {
+        R uo[2][2][W + 1];
+        load_corners<R, W>(po + c * N, sl, uo);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q <= W; ++q) u[a][b][q] += beta * uo[a][b][q];
+        // deferred solution update at the thread's own voxels
+        PV* xv = reinterpret_cast<PV*>(xbuf + c * N) + g;
+        PV xo = *xv;
+#pragma unroll
+        for (int w = 0; w < W; ++w) pk_set<R>(xo, w, pk_get<R>(xo, w) + alpha * uo[0][0][w + 1]);
+        pk_stream<R, W>(xv, xo);
+      }
+      PV pk;
+#pragma unroll
+      for (int w = 0; w < W; ++w) pk_set<R>(pk, w, u[0][0][w + 1]);
+      pk_stream<R, W>(reinterpret_cast<PV*>(pn + c * N) + g, pk);
+      R Z[3][W];
+      corner_grad<R, W>(u, q0, q1, q2, Z);
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int w = 0; w < W; ++w) X[w][3 * c + j] = Z[j][w];
     }
+    PV A[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) A[k] = sv[k * Nw + g];
     const PV al = sv[9 * Nw + g], be = sv[10 * Nw + g], ga = sv[11 * Nw + g];
-    R X[W][9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      PV pk = rk[k];
-      if (!first) {
-        PV xo = xv[k * Nw + g];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          pk_set<R>(xo, w, pk_get<R>(xo, w) + alpha * pk_get<R>(po[k], w));
-          pk_set<R>(pk, w, pk_get<R>(rk[k], w) + beta * pk_get<R>(po[k], w));
-        }
-        pk_stream<R, W>(xv + k * Nw + g, xo);
-      }
-      pk_stream<R, W>(pv + k * Nw + g, pk);
-#pragma unroll
-      for (int w = 0; w < W; ++w) X[w][k] = pk_get<R>(pk, w);
-    }
 #pragma unroll
     for (int w = 0; w < W; w += 2) {
       R A0[9], A1[9], Y0[9], Y1[9];
@@ -171,20 +191,23 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ p, R* __restrict__ x, const R* 
   if (tid == 0) partials[blockIdx.x] = s;
 }
 
-// x += alpha p once after the CG loop (the last deferred update), unless
-// the loop ended on a breakdown (then the front kernel already applied the
-// last valid step).
+// xi += alpha pi once after the CG loop (the last deferred update, with pi of
+// the last iteration), unless the loop ended on a breakdown (then the front
+// kernel already applied the last valid step).  grid.y = batch item; n = N
+// values per component; items with idle[b] != 0 are left alone.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_cg_final_x(T* __restrict__ x, const T* __restrict__ p, const KrylovScalars* __restrict__ ks, long n) {
-  // grid.y = batch item, n = values per item
-  const KrylovScalars* k = ks + blockIdx.y;
+k_cg_final_xi(T* __restrict__ xbuf, const T* __restrict__ pbuf, const KrylovScalars* __restrict__ ks,
+              const int* __restrict__ idle, long n) {
+  const int b = blockIdx.y;
+  if (idle && idle[b]) return;
+  const KrylovScalars* k = ks + b;
   if (k->flag == 1 || k->iter == 0) return;
   const T alpha = (T)k->alpha;
-  x += (long)blockIdx.y * n;
-  p += (long)blockIdx.y * n;
+  T* xi = xbuf + (long)b * 9 * n;
+  const T* pi = pbuf + (long)b * 9 * n + pot_half(k->iter - 1, n);
   const long stride = (long)gridDim.x * blockDim.x;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] += alpha * p[i];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n; i += stride) xi[i] += alpha * pi[i];
 }
 
 }  // namespace fg

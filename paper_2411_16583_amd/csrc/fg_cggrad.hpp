@@ -1,121 +1,163 @@
 // Back end of one CG iteration in the potential form of the projection
-// (k_fft_z_grad3): the projected field G(K p) = D U is formed from the real
-// 3-component potential U by the corner stencil of the rotated scheme and
-// used at once, so the 9-component field is never transformed back:
-//   (D_j U_i)[n] = 1/(4 h_j) * sum over the four voxel edges parallel to
-//                  axis j of (U_i at the upper corner - U_i at the lower one),
-// with the corner n - 1/2 (in every axis) stored at index n - 1 (periodic).
-//   mode 0 (CG):  r <- r - alpha D U (alpha of the item), per-block partial
-//                 sums of the new r . r;
-//   mode 1:       r <- D U (the projection itself; r is the output).
-// U: component slots 0, 3, 6 of the item's 9-component buffer (real after
-// the inverse passes).  Grid (ceil(N / (256 W)), items), one thread per W
-// consecutive voxels along N2.
+// (k_fft_z_grad3 and the inverse passes leave the real 3-component potential
+// U with D U = G(K p), D the corner stencil of fg_potential.hpp), and the
+// stencil kernels around the CG:
+//   k_cg_rupd   mode 0 (CG):   rho <- rho - alpha U (so r = D rho is updated
+//                              by -alpha G(K p)), per-block partial sums of
+//                              the new r . r = |D rho|^2;
+//               mode 2 (start): partial sums of |D rho|^2 of the initial rho.
+//   k_grad_store               Z = D U as a 9-component field (the
+//                              projection itself, or the CG solution x = D xi
+//                              in double precision).
+// Grid (ceil(N / (256 W)), items), one thread per W consecutive voxels along
+// N2.
 #pragma once
 #include "fg_fft.hpp"
+#include "fg_potential.hpp"
 
 namespace fg {
 
-// W consecutive voxels of a line per thread (W = 4 in single precision when
-// N2 % 4 == 0, else 2): one W-vector access per plane and line.
-template <typename T, int W> struct GradPack;
-template <> struct GradPack<double, 2> { using type = double2; };
-template <> struct GradPack<float, 2> { using type = float2; };
-template <> struct GradPack<float, 4> { using type = float4; };
-
 template <typename T, int W>
 __global__ void __launch_bounds__(256)
-k_cg_grad(const T* __restrict__ U, T* __restrict__ r, const KrylovScalars* __restrict__ ks,
-          double* __restrict__ partials, int n0, int n1, int n2, T ih0, T ih1, T ih2, int mode) {
-  using V = typename GradPack<T, W>::type;
+k_cg_rupd(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const KrylovScalars* __restrict__ ks,
+          const int* __restrict__ idle, double* __restrict__ partials, int n0, int n1, int n2, T q0, T q1, T q2,
+          int mode) {
+  using V = typename VecW<T, W>::type;
   __shared__ double red[16];
   const int item = blockIdx.y;
   if (mode == 0 && ks[item].done) return;
+  if (idle && idle[item]) return;
   const long N = (long)n0 * n1 * n2;
+  const int iter = (mode == 0) ? ks[item].iter : 0;
   U += (long)item * 9 * N;
-  r += (long)item * 9 * N;
+  const T* ro = rbuf + (long)item * 9 * N + pot_half(iter, N);
+  T* rn = rbuf + (long)item * 9 * N + pot_half(iter + 1, N);
   const int G = n2 / W;  // voxel groups per line
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double acc = 0.0;
   if (g < N / W) {
     const long line = g / G;
-    const int x = W * (int)(g - line * G);
-    const int i0 = (int)(line / n1), i1 = (int)(line - (long)i0 * n1);
-    const int i0m = (i0 == 0) ? n0 - 1 : i0 - 1;
-    const int i1m = (i1 == 0) ? n1 - 1 : i1 - 1;
-    const int xm = (x == 0) ? n2 - 1 : x - 1;
-    // the four lines (i0 - a, i1 - b), a, b in {0, 1}
-    const long row[2][2] = {{((long)i0 * n1 + i1) * n2, ((long)i0 * n1 + i1m) * n2},
-                            {((long)i0m * n1 + i1) * n2, ((long)i0m * n1 + i1m) * n2}};
+    const StencilLines sl = stencil_lines(line, W * (int)(g - line * G), n0, n1, n2);
     const T alpha = (mode == 0) ? (T)ks[item].alpha : T(0);
-    const T q0 = T(0.25) * ih0, q1 = T(0.25) * ih1, q2 = T(0.25) * ih2;
-    V* rv = reinterpret_cast<V*>(r);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T* Uc = U + 3 * c * N;
-      // u[a][b][p]: corner values at x - 1 + p, p = 0..W
       T u[2][2][W + 1];
+      load_corners<T, W>(ro + c * N, sl, u);
+      if (mode == 0) {
+        T du[2][2][W + 1];
+        load_corners<T, W>(U + c * ucs, sl, du);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const V w = *reinterpret_cast<const V*>(Uc + row[a][b] + x);
-          u[a][b][0] = Uc[row[a][b] + xm];
+          for (int b = 0; b < 2; ++b)
 #pragma unroll
-          for (int q = 0; q < W; ++q) u[a][b][q + 1] = reinterpret_cast<const T*>(&w)[q];
-        }
+            for (int q = 0; q <= W; ++q) u[a][b][q] -= alpha * du[a][b][q];
+        V w;
+#pragma unroll
+        for (int q = 0; q < W; ++q) reinterpret_cast<T*>(&w)[q] = u[0][0][q + 1];
+        reinterpret_cast<V*>(rn + c * N)[g] = w;
+      }
       T Z[3][W];
+      corner_grad<T, W>(u, q0, q1, q2, Z);
 #pragma unroll
-      for (int v = 0; v < W; ++v) {
-        const int lo = v, hi = v + 1;  // corners below / above voxel x + v along N2
-        Z[0][v] = q0 * ((u[0][0][hi] + u[0][1][hi] + u[0][0][lo] + u[0][1][lo]) -
-                        (u[1][0][hi] + u[1][1][hi] + u[1][0][lo] + u[1][1][lo]));
-        Z[1][v] = q1 * ((u[0][0][hi] + u[1][0][hi] + u[0][0][lo] + u[1][0][lo]) -
-                        (u[0][1][hi] + u[1][1][hi] + u[0][1][lo] + u[1][1][lo]));
-        Z[2][v] = q2 * ((u[0][0][hi] + u[0][1][hi] + u[1][0][hi] + u[1][1][hi]) -
-                        (u[0][0][lo] + u[0][1][lo] + u[1][0][lo] + u[1][1][lo]));
-      }
+      for (int j = 0; j < 3; ++j)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        V* dst = rv + (3 * c + j) * (N / W) + g;
-        V ro;
-        if (mode == 0) {
-          ro = *dst;
-#pragma unroll
-          for (int v = 0; v < W; ++v) {
-            T& e = reinterpret_cast<T*>(&ro)[v];
-            e -= alpha * Z[j][v];
-            acc += (double)e * (double)e;
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < W; ++v) reinterpret_cast<T*>(&ro)[v] = Z[j][v];
-        }
-        *dst = ro;
-      }
+        for (int v = 0; v < W; ++v) acc += (double)Z[j][v] * (double)Z[j][v];
     }
   }
-  if (mode == 0) {
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[(long)item * gridDim.x + blockIdx.x] = s;
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[(long)item * gridDim.x + blockIdx.x] = s;
+}
+
+// Z = D U: component 3 c + j of Z (N values apart, zis per item) is D_j of
+// component c of U (ucs apart, uis per item), evaluated in TO precision.
+template <typename TI, typename TO, int W>
+__global__ void __launch_bounds__(256)
+k_grad_store(const TI* __restrict__ U, long ucs, long uis, TO* __restrict__ Z, long zis, const int* __restrict__ idle,
+             int n0, int n1, int n2, TO q0, TO q1, TO q2) {
+  using VO = typename VecW<TO, W>::type;
+  const int item = blockIdx.y;
+  if (idle && idle[item]) return;
+  const long N = (long)n0 * n1 * n2;
+  U += (long)item * uis;
+  Z += (long)item * zis;
+  const int G = n2 / W;
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N / W) return;
+  const long line = g / G;
+  const StencilLines sl = stencil_lines(line, W * (int)(g - line * G), n0, n1, n2);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    TI ui[2][2][W + 1];
+    load_corners<TI, W>(U + c * ucs, sl, ui);
+    TO u[2][2][W + 1];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int q = 0; q <= W; ++q) u[a][b][q] = (TO)ui[a][b][q];
+    TO D[3][W];
+    corner_grad<TO, W>(u, q0, q1, q2, D);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      VO w;
+#pragma unroll
+      for (int v = 0; v < W; ++v) reinterpret_cast<TO*>(&w)[v] = D[j][v];
+      reinterpret_cast<VO*>(Z + (3 * c + j) * N)[g] = w;
+    }
   }
 }
 
-// Launch over all items; returns the number of partials per item.
+// CG start of an item: rho (half 0) = sign * U (U: 3 components ucs apart in
+// double precision, uis per item), xi = 0.  grid.y = item.
 template <typename T>
-int launch_cg_grad(const T* U, T* r, const KrylovScalars* ks, double* partials, int n0, int n1, int n2, int nitems,
-                   const double h[3], int mode, hipStream_t s) {
+__global__ void __launch_bounds__(256)
+k_cg_start_pot(T* __restrict__ rbuf, T* __restrict__ xbuf, const double* __restrict__ U, long ucs, long uis,
+               double sign, const int* __restrict__ idle, long n) {
+  const int b = blockIdx.y;
+  if (idle && idle[b]) return;
+  T* rho = rbuf + (long)b * 9 * n;
+  T* xi = xbuf + (long)b * 9 * n;
+  U += (long)b * uis;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n; i += stride) {
+    const long c = i / n, k = i - c * n;
+    rho[i] = (T)(sign * U[c * ucs + k]);
+    xi[i] = T(0);
+  }
+}
+
+inline int stencil_width(int n2, int elem_bytes) { return (elem_bytes == 4 && n2 % 4 == 0) ? 4 : 2; }
+
+// CG residual update (mode 0) or initial |D rho|^2 (mode 2) over all items;
+// returns the number of partials per item.
+template <typename T>
+int launch_cg_rupd(const T* U, long ucs, T* rbuf, const KrylovScalars* ks, const int* idle, double* partials, int n0,
+                   int n1, int n2, int nitems, const double h[3], int mode, hipStream_t s) {
   const long N = (long)n0 * n1 * n2;
-  const T ih0 = (T)(1.0 / h[0]), ih1 = (T)(1.0 / h[1]), ih2 = (T)(1.0 / h[2]);
-  if (sizeof(T) == 4 && n2 % 4 == 0) {
+  const T q0 = (T)(0.25 / h[0]), q1 = (T)(0.25 / h[1]), q2 = (T)(0.25 / h[2]);
+  if (stencil_width(n2, (int)sizeof(T)) == 4) {
     const dim3 grid((unsigned)((N / 4 + 255) / 256), (unsigned)nitems);
-    hipLaunchKernelGGL((k_cg_grad<T, (sizeof(T) == 4 ? 4 : 2)>), grid, dim3(256), 0, s, U, r, ks, partials, n0, n1,
-                       n2, ih0, ih1, ih2, mode);
+    hipLaunchKernelGGL((k_cg_rupd<T, (sizeof(T) == 4 ? 4 : 2)>), grid, dim3(256), 0, s, U, ucs, rbuf, ks, idle,
+                       partials, n0, n1, n2, q0, q1, q2, mode);
     return (int)grid.x;
   }
   const dim3 grid((unsigned)((N / 2 + 255) / 256), (unsigned)nitems);
-  hipLaunchKernelGGL((k_cg_grad<T, 2>), grid, dim3(256), 0, s, U, r, ks, partials, n0, n1, n2, ih0, ih1, ih2, mode);
+  hipLaunchKernelGGL((k_cg_rupd<T, 2>), grid, dim3(256), 0, s, U, ucs, rbuf, ks, idle, partials, n0, n1, n2, q0, q1,
+                     q2, mode);
   return (int)grid.x;
+}
+
+// Z = D U over all items (two voxels per thread).
+template <typename TI, typename TO>
+void launch_grad_store(const TI* U, long ucs, long uis, TO* Z, long zis, const int* idle, int n0, int n1, int n2,
+                       int nitems, const double h[3], hipStream_t s) {
+  const long N = (long)n0 * n1 * n2;
+  const TO q0 = (TO)(0.25 / h[0]), q1 = (TO)(0.25 / h[1]), q2 = (TO)(0.25 / h[2]);
+  const dim3 grid((unsigned)((N / 2 + 255) / 256), (unsigned)nitems);
+  hipLaunchKernelGGL((k_grad_store<TI, TO, 2>), grid, dim3(256), 0, s, U, ucs, uis, Z, zis, idle, n0, n1, n2, q0, q1,
+                     q2);
 }
 
 }  // namespace fg

@@ -184,15 +184,18 @@ void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R s
 }
 
 template <typename R>
-int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const KrylovScalars* ks, double* partials,
-                    long N, long nlines, const SpecTables<R>& tb, hipStream_t s, int nitems) {
+int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st, const KrylovScalars* ks,
+                    double* partials, long N, int n0, int n1, const double h[3], const SpecTables<R>& tb,
+                    hipStream_t s, int nitems) {
+  const R q0 = (R)(0.25 / h[0]), q1 = (R)(0.25 / h[1]), q2 = (R)(0.25 / h[2]);
+  const long nlines = (long)n0 * n1;
   switch (M) {
 #define FG_CASE(L_)                                                                                   \
   case L_: {                                                                                          \
     using FS = FrontShape<L_>;                                                                        \
     const long blocks = nitems * ((nlines + FS::LB - 1) / FS::LB);                                    \
-    hipLaunchKernelGGL((k_cg_front<R, L_>), dim3((unsigned)blocks), dim3(FS::THREADS), 0, s, spec, p, x, r, st, \
-                       ks, partials, N, nlines, tb);                                                  \
+    hipLaunchKernelGGL((k_cg_front<R, L_>), dim3((unsigned)blocks), dim3(FS::THREADS), 0, s, spec, pbuf, xbuf, \
+                       rbuf, st, ks, partials, N, n0, n1, tb, q0, q1, q2);                            \
     return (int)blocks;                                                                               \
   }
     FG_FOR_M(FG_CASE)
@@ -202,8 +205,8 @@ int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const K
 }
 
 #define FG_INSTANTIATE_LAUNCHERS(R)                                                                     \
-  template int launch_cg_front<R>(int, R*, R*, R*, const R*, const R*, const KrylovScalars*, double*, long, \
-                                  long, const SpecTables<R>&, hipStream_t, int);                        \
+  template int launch_cg_front<R>(int, R*, R*, R*, const R*, const R*, const KrylovScalars*, double*, long, int, \
+                                  int, const double*, const SpecTables<R>&, hipStream_t, int);          \
   template void launch_r2c<R>(int, const R*, R*, long, const SpecTables<R>&, const Skip&, hipStream_t); \
   template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t); \
   template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const Skip&, \

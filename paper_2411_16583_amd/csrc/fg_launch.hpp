@@ -19,11 +19,13 @@ int column_tile_cpt(int L, int M, int elem_bytes, int cpt);
 int line_threads(int L);
 int zline_threads(int L);  // threads per line of the fused N0 projection pass
 
-// Fused CG front (deferred x update, direction update, contraction, p.Kp,
-// N2 real-to-complex pass); returns the number of partials written.
+// Fused CG front on the potentials (deferred xi update, direction update,
+// p = D pi, contraction, p.Kp, N2 real-to-complex pass); h: grid spacings;
+// returns the number of partials written.
 template <typename R>
-int launch_cg_front(int M, R* spec, R* p, R* x, const R* r, const R* st, const KrylovScalars* ks, double* partials,
-                    long N, long nlines, const SpecTables<R>& tb, hipStream_t s, int nitems = 1);
+int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st, const KrylovScalars* ks,
+                    double* partials, long N, int n0, int n1, const double h[3], const SpecTables<R>& tb,
+                    hipStream_t s, int nitems = 1);
 
 template <typename R>
 void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const Skip& skip,

@@ -492,6 +492,11 @@ void note_noop_iterations(fg_plan* P, long noop) {
   P->prof_noop[FG_PASS_FINALIZE] += 2 * noop;
 }
 
+// Grid of a per-item field kernel: up to 256 blocks per item, grid.y = item.
+inline dim3 item_grid(long n, int nitems) {
+  return dim3((unsigned)std::min<long>(256, (n + 255) / 256), (unsigned)nitems);
+}
+
 // Inverse half of the projection in the potential form for all items: the
 // 3-component potential U (slots 0, 3, 6 of each item, spectral, written by
 // launch_zgrad) back to real space: N1 pass, then N2 complex-to-real.
@@ -515,13 +520,14 @@ void inv_potential(fg_plan* P, R* data, const Skip& skip) {
 }
 
 // One CG iteration for every item of the plan (items whose solve is done
-// skip every kernel):
-//   x += alpha_{k-1} p_{k-1}; p = r + beta p; Y = K:p; p.Y; N2 pass of Y
+// skip every kernel), on the potentials rho, pi, xi of r = D rho, p = D pi,
+// x = D xi (fg_potential.hpp):
+//   xi += alpha_{k-1} pi_{k-1}; pi = rho + beta pi; Y = K:(D pi); p.Y; N2 pass of Y
 //   alpha = r.r / p.Kp; N1 pass (9 components in, the two terms of each row
 //   that share the N0 factor merged); N0 pass reducing the projection to
 //   the 3-component potential; N1 and N2 inverse passes of
-//   the potential; r -= alpha G(K p) with G(K p) = D U from the corner
-//   stencil, r.r; beta, convergence.
+//   the potential U (D U = G(K p)); rho -= alpha U, r.r = |D rho|^2; beta,
+//   convergence.
 template <typename T>
 void cg_iteration(fg_plan* P) {
   T* S = (T*)P->S;
@@ -529,12 +535,11 @@ void cg_iteration(fg_plan* P) {
   KrylovScalars* ks = P->ks;
   const SpecTables<T> tb = tabs<T>(P).spec();
   const Skip skip = Skip::done(ks);
-  const long lines = (long)P->n0 * P->n1;
   int nbf;
   {
     ProfScope ps(P, FG_PASS_FRONT);
-    nbf = launch_cg_front<T>(P->M, S, (T*)P->p, (T*)P->x, (const T*)P->r, (const T*)P->st, ks, P->part, P->N, lines,
-                             tb, P->stream, nit);
+    nbf = launch_cg_front<T>(P->M, S, (T*)P->p, (T*)P->x, (const T*)P->r, (const T*)P->st, ks, P->part, P->N, P->n0,
+                             P->n1, P->h, tb, P->stream, nit);
   }
   {
     ProfScope ps(P, FG_PASS_FINALIZE);
@@ -553,7 +558,8 @@ void cg_iteration(fg_plan* P) {
   int nbg;
   {
     ProfScope ps(P, FG_PASS_GRAD);
-    nbg = launch_cg_grad<T>((const T*)S, (T*)P->r, ks, P->part2, P->n0, P->n1, P->n2, nit, P->h, 0, P->stream);
+    nbg = launch_cg_rupd<T>((const T*)S, 3 * P->N, (T*)P->r, ks, nullptr, P->part2, P->n0, P->n1, P->n2, nit, P->h, 0,
+                            P->stream);
   }
   {
     ProfScope ps(P, FG_PASS_FINALIZE);
@@ -562,15 +568,71 @@ void cg_iteration(fg_plan* P) {
   check_launch();
 }
 
+// Potential of the 9-component FP64 fields in `field` (all items), in place:
+// N2, N1 (rows merged), N0 (projection to the potential) and the inverse N1
+// and N2 passes.  Afterwards slot 3i of each item holds the real U_i with
+// D U = G(field).
+void potential64(fg_plan* P, double* field, const Skip& skip) {
+  const SpecTables<double> tb = P->t64.spec();
+  {
+    ProfScope ps(P, FG_PASS_R2C);
+    launch_r2c<double>(P->M, field, field, 9L * P->n0 * P->n1 * P->nitems, tb, skip.unit(9L * P->n0 * P->n1),
+                       P->stream);
+  }
+  {
+    ProfScope ps(P, FG_PASS_AXIS);
+    launch_axis_rows<double>(P->n1, field, P->n0, P->M, tb, skip, P->stream, P->nitems, tile_axis<double>(P));
+  }
+  {
+    ProfScope ps(P, FG_PASS_ZPROJ);
+    launch_zgrad<double>(P->n0, field, P->n1, P->M, tb, 1.0 / (double)P->N, skip, P->stream, P->nitems,
+                         tile_zproj<double>(P));
+  }
+  inv_potential<double>(P, field, skip);
+}
+
+// CG start on the potentials for every item not idle: rho_0 = sign U with U
+// the potential of the compatible FP64 field `field` (overwritten), so that
+// r_0 = D rho_0 = sign G(field); xi = 0; per-block partial sums of
+// |r_0|^2 = |D rho_0|^2 into P->part.  Returns the partials per item (the
+// caller reduces them into the Krylov scalars).
+template <typename T>
+int cg_start(fg_plan* P, double* field, double sign, const int* idle) {
+  potential64(P, field, idle ? Skip::flags(idle) : Skip{});
+  const long N = P->N;
+  hipLaunchKernelGGL((k_cg_start_pot<T>), item_grid(3 * N, P->nitems), dim3(256), 0, P->stream, (T*)P->r, (T*)P->x,
+                     (const double*)field, 3 * N, 9 * N, sign, idle, N);
+  const int nb = launch_cg_rupd<T>((const T*)P->r, 0, (T*)P->r, P->ks, idle, P->part, P->n0, P->n1, P->n2, P->nitems,
+                                   P->h, 2, P->stream);
+  check_launch();
+  return nb;
+}
+
+// Single-item CG start: cg_start and the Krylov scalars (rr0 = rr = |r_0|^2,
+// iter = 0, done if r_0 = 0).
+template <typename T>
+void cg_start1(fg_plan* P, double* field, double sign) {
+  const int nb = cg_start<T>(P, field, sign, nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
+  check_launch();
+}
+
+// The CG solution x = D xi of every item not idle, in double precision, into
+// the 9-component field dst (after the last deferred update of xi).
+template <typename T>
+void cg_result(fg_plan* P, double* dst, const int* idle) {
+  const long N = P->N;
+  hipLaunchKernelGGL((k_cg_final_xi<T>), item_grid(3 * N, P->nitems), dim3(256), 0, P->stream, (T*)P->x,
+                     (const T*)P->p, (const KrylovScalars*)P->ks, idle, N);
+  launch_grad_store<T, double>((const T*)P->x, N, 9 * N, dst, 9 * N, idle, P->n0, P->n1, P->n2, P->nitems, P->h,
+                               P->stream);
+  check_launch();
+}
+
 template <typename T>
 void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
-  T* x = (T*)P->x;
-  T* p = (T*)P->p;
   KrylovScalars* ks = P->ks;
-  const long n9 = 9 * P->N;
-  // ks was initialised (rr0, rr, iter = 0, done) by the residual pass
-  hipLaunchKernelGGL((k_fill<T>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, x, T(0), n9);
-  check_launch();
+  // rho_0, xi = 0 and ks (rr0, rr, iter = 0, done) were set by cg_start1
   {
     // only tol2 / maxit are host-set; the rest was set on the device
     P->hd[62] = (o->fixed_lin > 0) ? 0.0 : o->tol_lin * o->tol_lin;
@@ -589,9 +651,6 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
   }
   const KrylovScalars& h = P->hks[0];
   note_noop_iterations(P, launched - h.iter);
-  // the last deferred solution update
-  hipLaunchKernelGGL((k_cg_final_x<T>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, x, p, ks, n9);
-  check_launch();
   if (stats) {
     stats->lin_iters_last = h.iter;
     stats->lin_relres = h.rr0 > 0 ? std::sqrt(h.rr / h.rr0) : 0.0;
@@ -640,44 +699,26 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
     const double tol_eff = (P->prec == FG_MIXED) ? 0.01 * o->tol_newton : o->tol_newton;
     if (err <= tol_eff) break;
     if (it >= o->max_newton) throw Status(FG_E_NOCONV, "Newton reached max_newton iterations");
-    // b = -G*(G*P): second projection of the residual (compatible rhs)
-    {
-      C2REpi epi{-1.0, nullptr, true, P->part, Skip{}};
-      const int nb = project9<double>(P, P->S64, P->S64, P->S64, epi);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
-      check_launch();
-      if (P->prec == FG_FP64) {
-        FG_HIP(hipMemcpyAsync(P->r, P->S64, n9 * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
-      } else {
-        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream,
-                           (float*)P->r, (const double*)P->S64, n9);
-        check_launch();
-      }
-    }
+    // b = -G*P (S64 holds G*P from the residual pass): r_0 = D rho_0 with
+    // rho_0 = -U, U the potential of G*P
     if (P->prec == FG_FP64) {
+      cg_start1<double>(P, P->S64, -1.0);
       cg_solve<double>(P, o, stats);
-      hipLaunchKernelGGL((k_axpy_into_f64<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->F,
-                         (const double*)P->x, n9);
+      cg_result<double>(P, P->S64, nullptr);
     } else {
       fg_solver_opts om = *o;
       // Inner forcing: the single-precision operator is accurate to a few
       // 1e-7 at 256^3 (FFT rounding), so CG is not asked for more than 1e-5;
       // the double-precision Newton residual refines the rest.
       if (om.fixed_lin <= 0) om.tol_lin = std::max(o->tol_lin, 1e-5);
+      cg_start1<float>(P, P->S64, -1.0);
       cg_solve<float>(P, &om, stats);
-      // The correction must be compatible (F~ stays a gradient field): single-
-      // precision FFT rounding leaves an incompatible part of a few 1e-7 in x
-      // that the equilibrium residual never sees, so x is projected once in
-      // double precision before the update, dF = G * x.
-      hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->S64,
-                         (const float*)P->x, n9);
-      {
-        C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
-        project9<double>(P, P->S64, P->S64, P->S64, epi);
-      }
-      hipLaunchKernelGGL((k_axpy_into_f64<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->F,
-                         (const double*)P->S64, n9);
+      // dF = D xi evaluated in double precision: a discrete gradient, hence
+      // compatible to rounding whatever the single-precision error of xi
+      cg_result<float>(P, P->S64, nullptr);
     }
+    hipLaunchKernelGGL((k_axpy_into_f64<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->F,
+                       (const double*)P->S64, n9);
     check_launch();
     if (stats) {
       if (it < 64) stats->lin_history[it] = stats->lin_iters_last;
@@ -689,11 +730,11 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
 }
 
 // Adjoint of L = sum W_ij <P_ij> at the current (converged) state: solve
-// G(K:lam) = -G(K:W) for the compatible, zero-mean lam with the same CG, then
-// the per-voxel gradients with respect to log E and Omega.
+// G(K:lam) = -G(K:W) for the compatible, zero-mean lam with the same CG (lam
+// = D xi), then the per-voxel gradients with respect to log E and Omega.
 template <typename T>
 void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_solver_opts* o, fg_stats* stats) {
-  const long N = P->N, n9 = 9 * N;
+  const long N = P->N;
   T* S = (T*)P->S;
   T* pbuf = (T*)P->p;
   constitutive(P, nullptr, nullptr, P->st, nullptr);
@@ -703,28 +744,22 @@ void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_sol
   hipLaunchKernelGGL((k_contract<T>), dim3(blocks_for(N / 2)), dim3(256), 0, P->stream, S, (const T*)pbuf,
                      (const T*)P->st, N);
   check_launch();
+  static_assert(sizeof(T) == 8, "the single-precision adjoint is adjoint_mixed");
   {
-    // b = -G*(G*(K:W)): the second projection keeps the right-hand side
-    // compatible to rounding (as for the Newton right-hand side)
-    C2REpi e1{1.0, nullptr, true, nullptr, Skip{}};
-    project9<T>(P, S, S, S, e1);
-    C2REpi e2{-1.0, nullptr, true, P->part, Skip{}};
-    const int nb = project9<T>(P, S, S, S, e2);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
-    FG_HIP(hipMemcpyAsync(P->r, S, n9 * sizeof(T), hipMemcpyDeviceToDevice, P->stream));
-    check_launch();
+    // b = -G*(K:W): r_0 = D rho_0 with rho_0 = -U, U the potential of K:W
+    // (D U = G*(K:W))
+    cg_start1<double>(P, (double*)S, -1.0);
   }
   sync_read(P);
   check_domain(P);
-  if (!P->hks[0].done) {
-    cg_solve<T>(P, o, stats);
-  } else {
-    hipLaunchKernelGGL((k_fill<T>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, (T*)P->x, T(0), n9);
-  }
+  if (!P->hks[0].done) cg_solve<T>(P, o, stats);
+  // lam = D xi (zero when the right-hand side vanishes: xi = 0)
+  double* lam = (double*)P->r;
+  cg_result<double>(P, lam, nullptr);
   const double* c = P->c ? P->c : P->zeroN;
   const double* d = P->d ? P->d : P->zeroN;
   hipLaunchKernelGGL((k_adjoint_grad<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu,
-                     P->Om, (const T*)P->x, (const double*)P->Fu, gE, gO, P->flags, N);
+                     P->Om, (const T*)lam, (const double*)P->Fu, gE, gO, P->flags, N);
   check_launch();
   sync_read(P);
   check_domain(P);
@@ -767,9 +802,8 @@ void adjoint_mixed(fg_plan* P, const double W[9], double* gE, double* gO, const 
     if (refine == 0) rr0 = rr;
     if (rr0 == 0.0 || std::sqrt(rr / rr0) <= o->tol_lin) break;
     if (refine >= 30) throw Status(FG_E_NOCONV, "mixed adjoint: refinement did not converge");
-    hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream,
-                       (float*)P->r, (const double*)P->S64, n9);
-    check_launch();
+    // inner CG on R_k (compatible, in S64): rho_0 = U of R_k, r_0 = D rho_0
+    cg_start1<float>(P, P->S64, 1.0);
     fg_solver_opts om = *o;
     // the correction reduces R_k by 1e-5 at most (single-precision operator),
     // and by no more than what is left to reach tol_lin ||R_0||
@@ -778,9 +812,8 @@ void adjoint_mixed(fg_plan* P, const double W[9], double* gE, double* gO, const 
     fg_stats inner{};
     cg_solve<float>(P, &om, &inner);
     if (stats) stats->lin_iters_total += inner.lin_iters_last;
-    // lam += G*(d) in double precision
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->S64,
-                       (const float*)P->x, n9);
+    // lam += G*(d) in double precision, d = D xi
+    cg_result<float>(P, P->S64, nullptr);
     project9<double>(P, P->S64, P->S64, P->S64, e1);
     hipLaunchKernelGGL((k_axpy_into_f64<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, lam,
                        (const double*)P->S64, n9);
@@ -1245,8 +1278,8 @@ fg_status fg_project_grad(fg_plan* P, const double* x, double* y) {
     launch_zgrad<double>(P->n0, P->S64, P->n1, P->M, P->t64.spec(), 1.0 / (double)P->N, Skip{}, P->stream, 1,
                          tile_zproj<double>(P));
     inv_potential<double>(P, P->S64, Skip{});
-    launch_cg_grad<double>((const double*)P->S64, y, (const KrylovScalars*)nullptr, (double*)nullptr, P->n0, P->n1,
-                           P->n2, 1, P->h, 1, P->stream);
+    launch_grad_store<double, double>((const double*)P->S64, 3 * P->N, 9 * P->N, y, 9 * P->N, nullptr, P->n0, P->n1,
+                                      P->n2, 1, P->h, P->stream);
     check_launch();
   });
 }
@@ -1432,9 +1465,6 @@ fg_status batch_run(fg_batch* B, const std::function<void()>& fn) {
   }
 }
 
-inline dim3 item_grid(long n, int nitems) {
-  return dim3((unsigned)std::min<long>(256, (n + 255) / 256), (unsigned)nitems);
-}
 
 // One tick of a group: a CG iteration for the items whose solve runs, then
 // the Newton step for the items whose solve has ended.
@@ -1447,21 +1477,12 @@ void batch_tick(fg_plan* P, fg_batch::Group& g, bool newton) {
   const dim3 gi = item_grid(n9, nit);
   hipLaunchKernelGGL(k_newton_gate, dim3(1), dim3(1024), 0, P->stream, (const KrylovScalars*)P->ks, g.nc, g.idle,
                      g.active, nit, (int)FG_E_BREAKDOWN, (int)FG_E_NOCONV);
-  hipLaunchKernelGGL((k_items_final_x<T>), gi, dim3(256), 0, P->stream, (T*)P->x, (const T*)P->p,
-                     (const KrylovScalars*)P->ks, (const int*)g.idle, n9);
   const Skip idle = Skip::flags(g.idle);
-  if (P->prec == FG_FP64) {
-    hipLaunchKernelGGL((k_items_axpy<double>), gi, dim3(256), 0, P->stream, P->F, (const double*)P->x,
-                       (const int*)g.idle, n9);
-  } else {
-    // dF = G * x in double precision (as in the single-item mixed form)
-    hipLaunchKernelGGL((k_items_convert<float, double>), gi, dim3(256), 0, P->stream, P->S64, (const float*)P->x,
-                       (const int*)g.idle, n9);
-    C2REpi e{1.0, nullptr, true, nullptr, idle};
-    project9<double>(P, P->S64, P->S64, P->S64, e);
-    hipLaunchKernelGGL((k_items_axpy<double>), gi, dim3(256), 0, P->stream, P->F, (const double*)P->S64,
-                       (const int*)g.idle, n9);
-  }
+  // F += D xi, evaluated in double precision (a discrete gradient: compatible
+  // to rounding also in the mixed form)
+  cg_result<T>(P, P->S64, g.idle);
+  hipLaunchKernelGGL((k_items_axpy<double>), gi, dim3(256), 0, P->stream, P->F, (const double*)P->S64,
+                     (const int*)g.idle, n9);
   constitutive(P, nullptr, P->S64, P->st, nullptr, g.idle);
   {
     // err_res of eq. (31) and the Newton test
@@ -1471,14 +1492,11 @@ void batch_tick(fg_plan* P, fg_batch::Group& g, bool newton) {
                        g.idle, (int)FG_E_NOCONV);
   }
   {
-    // b = -G*(G*P) and a fresh CG
-    C2REpi e{-1.0, nullptr, true, P->part, idle};
-    const int nb = project9<double>(P, P->S64, P->S64, P->S64, e);
-    hipLaunchKernelGGL(k_newton_cg_start, dim3(nit), dim3(1024), 0, P->stream, (const double*)P->part, nb / nit,
-                       P->ks, g.nc, (const int*)g.idle);
+    // b = -G*P (S64 holds G*P): rho_0 = -U, xi = 0, and a fresh CG
+    const int nb = cg_start<T>(P, P->S64, -1.0, g.idle);
+    hipLaunchKernelGGL(k_newton_cg_start, dim3(nit), dim3(1024), 0, P->stream, (const double*)P->part, nb, P->ks, g.nc,
+                       (const int*)g.idle);
   }
-  hipLaunchKernelGGL((k_items_rhs<T>), gi, dim3(256), 0, P->stream, (T*)P->r, (T*)P->x, (const double*)P->S64,
-                     (const int*)g.idle, n9);
   check_launch();
 }
 

@@ -118,14 +118,14 @@ def test_bench_byte_model_and_roofline():
 
     N = 256 ** 3
     # words per voxel per CG iteration of the kernels on the path
-    assert sum(bench.WORDS_PER_VOXEL[k] for k in ("front", "axis", "zproj", "axis3", "c2r3", "grad")) == 123
+    assert sum(bench.WORDS_PER_VOXEL[k] for k in ("front", "axis", "zproj", "axis3", "c2r3", "grad")) == 81
     prof = {k: (0.0, 0) for k in ["front", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive",
                                   "zscalar", "axis3", "c2r3", "grad"]}
     prof["front"] = (1693.2 * 10 / 1e3, 10)  # 10 launches of 1693.2 us
     prof["axis"] = (0.4402 * 10, 10)
     r = bench.roofline(dict(prof=prof), N, 8)
     assert r["kernel"] == "front"
-    assert r["bytes_per_launch"] == 66 * 8 * N
-    assert r["achieved"] == pytest.approx(66 * 8 * N / 1693.2e-6 / 1e9, rel=1e-3)
+    assert r["bytes_per_launch"] == 36 * 8 * N
+    assert r["achieved"] == pytest.approx(36 * 8 * N / 1693.2e-6 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
     assert set(r["per_class"]) == {"front", "axis"}

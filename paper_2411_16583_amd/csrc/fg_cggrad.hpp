@@ -2,61 +2,116 @@
 // (k_fft_z_grad3 and the inverse passes leave the real 3-component potential
 // U with D U = G(K p), D the corner stencil of fg_potential.hpp), and the
 // stencil kernels around the CG:
-//   k_cg_rupd   mode 0 (CG):   rho <- rho - alpha U (so r = D rho is updated
-//                              by -alpha G(K p)), per-block partial sums of
-//                              the new r . r = |D rho|^2;
-//               mode 2 (start): partial sums of |D rho|^2 of the initial rho.
-//   k_grad_store               Z = D U as a 9-component field (the
-//                              projection itself, or the CG solution x = D xi
-//                              in double precision).
-// Grid (ceil(N / (256 W)), items), one thread per W consecutive voxels along
-// N2.
+//   k_cg_rupd_march  mode 0 (CG):    rho <- rho - alpha U (so r = D rho is
+//                                     updated by -alpha G(K p)), per-block
+//                                     partial sums of the new r . r = |D rho|^2;
+//                    mode 2 (start): partial sums of |D rho|^2 of the initial
+//                                     rho.
+//   k_grad_store                      Z = D U as a 9-component field (the
+//                                     projection itself, or the CG solution
+//                                     x = D xi in double precision).
 #pragma once
 #include "fg_fft.hpp"
 #include "fg_potential.hpp"
 
 namespace fg {
 
+// Marching residual update: a thread owns W voxels of one line (i1, x) of
+// one component c, for a run of up to K consecutive planes i0, and carries
+// the new rho of the previous plane in registers, so the stencil's lower
+// plane is never read again; only the line i1 - 1 is read beside the own
+// line (by the neighbouring workgroup too, which runs on the same XCD at the
+// same time: xcd_contiguous).  |D rho|^2 is a sum over components, so the
+// components run in separate workgroups (fewer registers per thread, more
+// waves in flight).  All loads of a plane are issued before its store.
+// Grid (3 * ceil(n0 / K) * ceil(n1 G / 256) * items) in one dimension,
+// G = n2 / W; partials per item = blocks per item.  Accesses are a per-item
+// base plus a 32-bit byte offset (the host checks that an item's 9 N values
+// fit in 4 GiB).
 template <typename T, int W>
 __global__ void __launch_bounds__(256)
-k_cg_rupd(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const KrylovScalars* __restrict__ ks,
-          const int* __restrict__ idle, double* __restrict__ partials, int n0, int n1, int n2, T q0, T q1, T q2,
-          int mode) {
+k_cg_rupd_march(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const KrylovScalars* __restrict__ ks,
+                const int* __restrict__ idle, double* __restrict__ partials, int n0, int n1, int n2, int K, T q0,
+                T q1, T q2, int mode) {
   using V = typename VecW<T, W>::type;
   __shared__ double red[16];
-  const int item = blockIdx.y;
+  const int G = n2 / W;
+  const unsigned bx = (unsigned)((n1 * (long)G + 255) / 256);  // blocks per plane run
+  const unsigned nseg = (unsigned)((n0 + K - 1) / K);
+  const unsigned per_item = 3 * bx * nseg;
+  const unsigned lb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int item = (int)(lb / per_item);
+  const unsigned rem = lb - (unsigned)item * per_item;
+  const int c = (int)(rem / (bx * nseg));
+  const unsigned rc = rem - (unsigned)c * bx * nseg;
+  const int seg = (int)(rc / bx);
+  const unsigned blk = rc - (unsigned)seg * bx;
   if (mode == 0 && ks[item].done) return;
   if (idle && idle[item]) return;
   const long N = (long)n0 * n1 * n2;
   const int iter = (mode == 0) ? ks[item].iter : 0;
-  U += (long)item * 9 * N;
-  const T* ro = rbuf + (long)item * 9 * N + pot_half(iter, N);
-  T* rn = rbuf + (long)item * 9 * N + pot_half(iter + 1, N);
-  const int G = n2 / W;  // voxel groups per line
-  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  U += (long)item * 9 * N + c * ucs;
+  const T* ro = rbuf + (long)item * 9 * N + pot_half(iter, N) + c * N;
+  T* rn = rbuf + (long)item * 9 * N + pot_half(iter + 1, N) + c * N;
+  const T alpha = (mode == 0) ? (T)ks[item].alpha : T(0);
+  const long gl = (long)blk * 256 + threadIdx.x;  // (i1, x group) in the plane
   double acc = 0.0;
-  if (g < N / W) {
-    const long line = g / G;
-    const StencilLines sl = stencil_lines(line, W * (int)(g - line * G), n0, n1, n2);
-    const T alpha = (mode == 0) ? (T)ks[item].alpha : T(0);
+  if (gl < (long)n1 * G) {
+    const int i1 = (int)(gl / G);
+    const int x = W * (int)(gl - (long)i1 * G);
+    const int i1m = (i1 == 0) ? n1 - 1 : i1 - 1;
+    const int xm = (x == 0) ? n2 - 1 : x - 1;
+    constexpr unsigned E = sizeof(T);
+    const unsigned plane_b = (unsigned)n1 * (unsigned)n2 * E;
+    const unsigned lo[2] = {((unsigned)i1 * (unsigned)n2 + (unsigned)x) * E,
+                            ((unsigned)i1m * (unsigned)n2 + (unsigned)x) * E};
+    const unsigned dxm = (unsigned)(xm - x) * E;  // x - 1 (or n2 - 1) relative to x, mod 2^32
+    const int i0s = seg * K, i0e = min(n0, i0s + K);
+    // new rho at the corners x - 1 .. x + W - 1 of lines i1 - b of plane i0
+    auto corners = [&](int i0, T (&u)[2][W + 1]) {
+      const unsigned pb = (unsigned)i0 * plane_b;
+      T d[2][W + 1];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      T u[2][2][W + 1];
-      load_corners<T, W>(ro + c * N, sl, u);
+      for (int b = 0; b < 2; ++b) {
+        const unsigned o = pb + lo[b];
+        const V w = at_bytes(reinterpret_cast<const V*>(ro), o);
+        u[b][0] = at_bytes(ro, o + dxm);
+#pragma unroll
+        for (int q = 0; q < W; ++q) u[b][q + 1] = reinterpret_cast<const T*>(&w)[q];
+        if (mode == 0) {
+          const V wu = at_bytes(reinterpret_cast<const V*>(U), o);
+          d[b][0] = at_bytes(U, o + dxm);
+#pragma unroll
+          for (int q = 0; q < W; ++q) d[b][q + 1] = reinterpret_cast<const T*>(&wu)[q];
+        }
+      }
       if (mode == 0) {
-        T du[2][2][W + 1];
-        load_corners<T, W>(U + c * ucs, sl, du);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int q = 0; q <= W; ++q) u[a][b][q] -= alpha * du[a][b][q];
+          for (int q = 0; q <= W; ++q) u[b][q] -= alpha * d[b][q];
+      }
+    };
+    T prev[2][W + 1];
+    corners(i0s == 0 ? n0 - 1 : i0s - 1, prev);
+    for (int i0 = i0s; i0 < i0e; ++i0) {
+      T cur[2][W + 1];
+      corners(i0, cur);
+      if (mode == 0) {
         V w;
 #pragma unroll
-        for (int q = 0; q < W; ++q) reinterpret_cast<T*>(&w)[q] = u[0][0][q + 1];
-        reinterpret_cast<V*>(rn + c * N)[g] = w;
+        for (int q = 0; q < W; ++q) reinterpret_cast<T*>(&w)[q] = cur[0][q + 1];
+        at_bytes(reinterpret_cast<V*>(rn), (unsigned)i0 * plane_b + lo[0]) = w;
       }
+      T u[2][2][W + 1];
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int q = 0; q <= W; ++q) {
+          u[0][b][q] = cur[b][q];
+          u[1][b][q] = prev[b][q];
+          prev[b][q] = cur[b][q];
+        }
       T Z[3][W];
       corner_grad<T, W>(u, q0, q1, q2, Z);
 #pragma unroll
@@ -66,7 +121,7 @@ k_cg_rupd(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const KrylovS
     }
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[(long)item * gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[(long)item * per_item + rem] = s;
 }
 
 // Z = D U: component 3 c + j of Z (N values apart, zis per item) is D_j of
@@ -130,23 +185,29 @@ k_cg_start_pot(T* __restrict__ rbuf, T* __restrict__ xbuf, const double* __restr
 
 inline int stencil_width(int n2, int elem_bytes) { return (elem_bytes == 4 && n2 % 4 == 0) ? 4 : 2; }
 
+// Planes per thread of the marching residual update.
+constexpr int kRupdPlanes = 16;
+
 // CG residual update (mode 0) or initial |D rho|^2 (mode 2) over all items;
 // returns the number of partials per item.
 template <typename T>
 int launch_cg_rupd(const T* U, long ucs, T* rbuf, const KrylovScalars* ks, const int* idle, double* partials, int n0,
                    int n1, int n2, int nitems, const double h[3], int mode, hipStream_t s) {
-  const long N = (long)n0 * n1 * n2;
   const T q0 = (T)(0.25 / h[0]), q1 = (T)(0.25 / h[1]), q2 = (T)(0.25 / h[2]);
+  if ((double)9 * n0 * n1 * n2 * sizeof(T) >= 4294967296.0)
+    throw std::invalid_argument("grid too large for 32-bit offsets in the residual update");
+  const int K = kRupdPlanes;
+  const long nseg = (n0 + K - 1) / K;
   if (stencil_width(n2, (int)sizeof(T)) == 4) {
-    const dim3 grid((unsigned)((N / 4 + 255) / 256), (unsigned)nitems);
-    hipLaunchKernelGGL((k_cg_rupd<T, (sizeof(T) == 4 ? 4 : 2)>), grid, dim3(256), 0, s, U, ucs, rbuf, ks, idle,
-                       partials, n0, n1, n2, q0, q1, q2, mode);
-    return (int)grid.x;
+    const long bx = ((long)n1 * (n2 / 4) + 255) / 256;
+    hipLaunchKernelGGL((k_cg_rupd_march<T, (sizeof(T) == 4 ? 4 : 2)>), dim3((unsigned)(3 * bx * nseg * nitems)),
+                       dim3(256), 0, s, U, ucs, rbuf, ks, idle, partials, n0, n1, n2, K, q0, q1, q2, mode);
+    return (int)(3 * bx * nseg);
   }
-  const dim3 grid((unsigned)((N / 2 + 255) / 256), (unsigned)nitems);
-  hipLaunchKernelGGL((k_cg_rupd<T, 2>), grid, dim3(256), 0, s, U, ucs, rbuf, ks, idle, partials, n0, n1, n2, q0, q1,
-                     q2, mode);
-  return (int)grid.x;
+  const long bx = ((long)n1 * (n2 / 2) + 255) / 256;
+  hipLaunchKernelGGL((k_cg_rupd_march<T, 2>), dim3((unsigned)(3 * bx * nseg * nitems)), dim3(256), 0, s, U, ucs, rbuf,
+                     ks, idle, partials, n0, n1, n2, K, q0, q1, q2, mode);
+  return (int)(3 * bx * nseg);
 }
 
 // Z = D U over all items (two voxels per thread).

@@ -138,4 +138,13 @@ template <int R, int S, bool INV, typename C> struct Dft {
   }
 };
 
+// Element at a 32-bit byte offset from a base pointer (a workgroup-uniform
+// base plus one 32-bit register per access).
+template <typename T> __device__ __forceinline__ T& at_bytes(T* base, unsigned byte_off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+template <typename T> __device__ __forceinline__ const T& at_bytes(const T* base, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 }  // namespace fg

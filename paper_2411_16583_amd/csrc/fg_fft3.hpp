@@ -242,11 +242,6 @@ k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip
 }
 
 
-// Element at a 32-bit byte offset from a base pointer.
-template <typename T> __device__ __forceinline__ T& at_bytes(T* base, unsigned byte_off) {
-  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
-}
-
 // Forward N1 pass of the projection in its potential form, one row i of the
 // 3x3 field per workgroup.  With the rotated-scheme vector r of eq. (28),
 //   sum_l A_il r_l = sz (cy cx A_i0) + cz (sy cx A_i1 + cy sx A_i2)

@@ -252,9 +252,19 @@ k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const
 }
 
 // Sum of nparts partials in a fixed order by one block (deterministic).
+// Each thread keeps eight independent running sums, so that eight loads are
+// in flight per thread instead of one (the partials come from other XCDs'
+// L2 or from HBM).
 __device__ __forceinline__ double sum_partials(const double* __restrict__ partials, int nparts, double* red) {
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += blockDim.x) acc += partials[k];
+  const int bd = blockDim.x;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int k = threadIdx.x;
+  for (; k + 7 * bd < nparts; k += 8 * bd) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += partials[k + u * bd];
+  }
+  for (; k < nparts; k += bd) a[0] += partials[k];
+  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   return block_sum(acc, red);
 }
 

@@ -72,6 +72,16 @@ __device__ __forceinline__ void corner_grad(const T (&u)[2][2][W + 1], T q0, T q
   }
 }
 
+// Logical workgroup index that gives each XCD a contiguous range: the
+// hardware deals workgroups out to the 8 XCDs round-robin in launch order,
+// so workgroup `flat` is the k-th one of XCD flat % 8.  Neighbouring logical
+// workgroups then share an L2.
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned flat, unsigned total) {
+  const unsigned q = total / 8, r = total % 8;
+  const unsigned x = flat % 8, k = flat / 8;
+  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Storage of the CG potentials of one item: rho (residual), pi (direction)
 // and xi (solution), 3 components of N values each, at the start of the
 // item's 9 N-value regions of the r, p and x buffers.  rho and pi alternate

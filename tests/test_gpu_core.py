@@ -186,6 +186,37 @@ def test_inclusion_newton_mixed_matches_oracle():
     assert e <= 1e-6
 
 
+@pytest.mark.parametrize("precision,k,tol", [("fp64", 1, 1e-11), ("fp64", 4, 1e-11), ("fp64", 12, 1e-11),
+                                             ("mixed", 12, 1e-5)])
+def test_cg_iterates_match_oracle_cg(precision, k, tol):
+    """k iterations of the GPU CG, which stores the residual, direction and
+    solution as 3-component potentials, give the k-th iterate of the
+    oracle's 9-component Hestenes-Stiefel CG of Alg. 1 on the same Newton
+    system (the first Newton step of the 16^3 inclusion workload)."""
+    from oracle import krylov
+
+    work = synth.inclusion_workload()
+    shape, spacing = work["shape"], work["spacing"]
+    Fbar = work["loads"][0]
+    F0 = mechanics.uniform_field(Fbar, shape)
+    c0, d0 = work["c0"], work["d0"]
+    GP, _ = mechanics.residual_rhs(F0, c0, d0, work, spacing)
+    b = -spectral.project(GP, spacing)
+    K = cm.tangent(F0, c0, d0, work["E"], work["nu"], work["Omega"])
+    dF, n, _ = krylov.cg(lambda X: mechanics.operator(K, X, spacing), b, 1e-10, 100, fixed_iters=k)
+    assert n == k
+    plan = plan_for(work, precision)
+    F = dt(F0)
+    plan.set_state(F, dt(c0), dt(d0), dt(np.zeros(shape)))
+    st = plan.newton_solve(Fbar, make_opts(1e-30, 1e-10, max_newton=1, fixed_lin=k), raise_on_error=False)
+    dFg = host(F, (3, 3) + shape) - F0
+    e = rel(dFg, dF)
+    print(f"{precision} k={k}: cg {st['lin_history']} rel {e:.2e}", flush=True)
+    assert st["lin_history"][0] == k
+    assert e <= tol
+    plan.close()
+
+
 def test_inclusion_newton_fp64_tight_matches_discrete_solution():
     """FP64 at tight tolerances reaches the discrete solution to 1e-10."""
     work = synth.inclusion_workload(n_inc=1, total_strain=0.002)

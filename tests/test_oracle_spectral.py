@@ -49,6 +49,20 @@ def test_projector_keeps_gradients(shape, spacing):
     assert np.max(np.abs(res)) < 1e-11 * np.max(np.abs(D.T @ xi.ravel()))
 
 
+@pytest.mark.parametrize("shape,spacing", [((4, 6, 4), (0.5, 0.25, 1.0)), ((3, 4, 5), (1.0, 1.0, 1.0))])
+def test_projector_range_is_gradient_range(shape, spacing):
+    """range(G) = range(D): G is the orthogonal projector onto the corner-
+    stencil gradients, G = D (D^T D)^+ D^T.  So every compatible field (each
+    CG residual, direction and solution of the mechanics) is D of a
+    3-component potential, which is what the GPU CG stores."""
+    n9 = 9 * int(np.prod(shape))
+    G = np.stack([spectral.project(e.reshape((3, 3) + shape), spacing).ravel() for e in np.eye(n9)], axis=1)
+    D = dense.corner_gradient_matrix(shape, spacing)
+    PD = D @ np.linalg.pinv(D)
+    assert np.max(np.abs(G - PD)) < 1e-10
+    assert np.linalg.matrix_rank(D) == round(np.trace(G))
+
+
 def test_rotated_vector_matches_complex_symbol():
     """k_j = i r_j exp(i sum q / 2) with r real, and k equals the symbol of
     the dense 8-corner stencil applied to plane waves."""

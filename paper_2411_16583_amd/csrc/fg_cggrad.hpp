@@ -94,9 +94,8 @@ k_cg_rupd_march(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const K
     };
     T prev[2][W + 1];
     corners(i0s == 0 ? n0 - 1 : i0s - 1, prev);
-    for (int i0 = i0s; i0 < i0e; ++i0) {
-      T cur[2][W + 1];
-      corners(i0, cur);
+    // one plane: store the own voxels, add |D rho|^2 against the lower plane
+    auto plane_step = [&](int i0, const T (&cur)[2][W + 1]) {
       if (mode == 0) {
         V w;
 #pragma unroll
@@ -118,6 +117,15 @@ k_cg_rupd_march(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const K
       for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int v = 0; v < W; ++v) acc += (double)Z[j][v] * (double)Z[j][v];
+    };
+    // two planes per step, their loads issued together (the second one
+    // repeats the last plane when the run has an odd length)
+    for (int i0 = i0s; i0 < i0e; i0 += 2) {
+      T ca[2][W + 1], cb[2][W + 1];
+      corners(i0, ca);
+      corners(min(i0 + 1, i0e - 1), cb);
+      plane_step(i0, ca);
+      if (i0 + 1 < i0e) plane_step(i0 + 1, cb);
     }
   }
   const double s = block_sum(acc, red);

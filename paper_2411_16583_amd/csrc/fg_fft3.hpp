@@ -332,8 +332,9 @@ template <typename R> constexpr size_t zgrad_extra_lds(int L) {
 //                of the corner difference (corner n - 1/2 stored at n - 1)
 // has the symbol i e^{-i Phi} r_j.  Only U is transformed back (one inverse
 // per row instead of three); U_i is stored in component slot 3 i of the item,
-// and the gradient is formed in real space by k_cg_grad.  The input is the
-// output of k_fft_axis_rows: slot 3i holds cy cx A_i0 and slot 3i + 1 holds
+// and its gradient is formed in real space by the corner stencil
+// (k_cg_rupd_march, k_grad_store).  The input is the output of
+// k_fft_axis_rows: slot 3i holds cy cx A_i0 and slot 3i + 1 holds
 // sy cx A_i1 + cy sx A_i2, so that sum_l A_il r_l = sz X_0 + cz X_1 after the
 // N0 transforms X_0, X_1 of the two slots (two forward transforms and one
 // inverse per row).  Grid (M/B, N1, 3 rows per item), or (N1, M/B, rows) with

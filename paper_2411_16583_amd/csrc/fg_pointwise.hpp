@@ -198,7 +198,8 @@ template <typename T, typename V> __device__ __forceinline__ void vset(V& v, int
 }
 
 // x += alpha p, r -= alpha q, per-block partial sums of r.r.  16-byte
-// accesses; n must be a multiple of the vector width (9N always is).
+// accesses; n must be a multiple of the vector width (the scalar fields of
+// the preconditioned solvers: N is even).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,

@@ -220,6 +220,35 @@ __device__ __forceinline__ double block_sum(double v, double* red /*>= 16 double
   return s;  // valid in thread 0 only
 }
 
+// Sum of nparts partials in a fixed order by one block (deterministic).
+// Each thread keeps eight independent running sums, so that eight loads are
+// in flight per thread instead of one (the partials come from other XCDs'
+// L2 or from HBM).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partials, int nparts, double* red) {
+  const int bd = blockDim.x;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int k = threadIdx.x;
+  for (; k + 7 * bd < nparts; k += 8 * bd) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += partials[k + u * bd];
+  }
+  for (; k < nparts; k += bd) a[0] += partials[k];
+  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  return block_sum(acc, red);
+}
+
+// CG step length from s = p.Ap (or p.Aq): alpha = r.r / s (r.z / s
+// preconditioned), or breakdown when s <= 0.  One thread.
+__device__ __forceinline__ void krylov_alpha(KrylovScalars* ks, double s, int pcg) {
+  ks->pAp = s;
+  if (!(s > 0.0)) {
+    ks->done = 1;
+    ks->flag = 1;
+  } else {
+    ks->alpha = (pcg ? ks->rz : ks->rr) / s;
+  }
+}
+
 // Tables of one 3-D plan (device pointers), in the working precision R.
 template <typename R> struct SpecTables {
   const cplx<R>* tw0;   // W_{N0}^j, j < N0

@@ -266,13 +266,21 @@ template <typename R, int L> using RowLine = typename std::conditional<sizeof(R)
 template <typename R, int L>
 __global__ void __launch_bounds__(256)
 k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride, int B, SpecTables<R> tb,
-                Skip skip) {
+                Skip skip, const double* __restrict__ pap_partials, int nparts, KrylovScalars* ks) {
   using C = cplx<R>;
   using LS = RowLine<R, L>;
   extern __shared__ char smem_raw[];
+  __shared__ double red[16];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C* stw = lds + L * B;
   if (skip((long)blockIdx.y + (long)gridDim.y * blockIdx.z)) return;
+  if (pap_partials && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z % 3 == 0) {
+    // in the CG: the step length of the item from the front's partial sums
+    // of p.Ap (nothing before the residual update reads it)
+    const int item = blockIdx.z / 3;
+    const double s = sum_partials(pap_partials + (long)item * nparts, nparts, red);
+    if (threadIdx.x == 0) krylov_alpha(ks + item, s, 0);
+  }
   for (int k = threadIdx.x; k < L; k += blockDim.x) stw[k] = tb.tw1[k];
   __syncthreads();
   const R* scy = tb.cy;

@@ -88,7 +88,7 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 
 template <typename R>
 void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
-                      int nitems, int tile) {
+                      int nitems, int tile, const double* pap_partials, int nparts, KrylovScalars* ks) {
   tile &= ~kTileColumnPairs;
   const int T = sizeof(R) == 8 ? zline_threads(N1) : line_threads(N1);  // threads of RowLine<R, N1>
   int B = tile > 0 ? tile : column_tile_t(T, N1, M, (int)sizeof(cplx<R>));
@@ -104,7 +104,7 @@ void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, c
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \
     hipLaunchKernelGGL((k_fft_axis_rows<R, L_>), grid, dim3(T * B), shm, s, data, (long)M, plane,       \
-                       3L * N0 * plane, (long)N0 * plane, B, tb, sk);                                  \
+                       3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks);        \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE
@@ -211,7 +211,8 @@ int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st
   template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t); \
   template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const Skip&, \
                                hipStream_t, int);                                                       \
-  template void launch_axis_rows<R>(int, R*, int, int, const SpecTables<R>&, const Skip&, hipStream_t, int, int); \
+  template void launch_axis_rows<R>(int, R*, int, int, const SpecTables<R>&, const Skip&, hipStream_t, int, int,    \
+                                    const double*, int, KrylovScalars*);                                        \
   template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
   template void launch_zgrad<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
   template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const Skip&, \

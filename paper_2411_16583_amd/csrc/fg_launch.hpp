@@ -41,10 +41,13 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 // Forward N1 pass of the potential-form projection for nitems 9-component
 // fields: per row, the two terms sharing the N0 factor are merged (slots
 // 3i, 3i + 1 written; kx = 0 column unmerged in all three slots).  tile as
-// for launch_axis (a column-pair flag is ignored).
+// for launch_axis (a column-pair flag is ignored).  With pap_partials (in
+// the CG), one workgroup per item also sets the item's step length from
+// the front's nparts partial sums of p.Ap (k_finalize mode 0).
 template <typename R>
 void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
-                      int nitems = 1, int tile = 0);
+                      int nitems = 1, int tile = 0, const double* pap_partials = nullptr, int nparts = 0,
+                      KrylovScalars* ks = nullptr);
 // N0 pass fused with the projection, for nitems 9-component fields (3 rows
 // each).
 template <typename R>

@@ -489,7 +489,7 @@ void note_noop_iterations(fg_plan* P, long noop) {
   P->prof_noop[FG_PASS_AXIS3] += noop;
   P->prof_noop[FG_PASS_C2R3] += noop;
   P->prof_noop[FG_PASS_GRAD] += noop;
-  P->prof_noop[FG_PASS_FINALIZE] += 2 * noop;
+  P->prof_noop[FG_PASS_FINALIZE] += noop;
 }
 
 // Grid of a per-item field kernel: up to 256 blocks per item, grid.y = item.
@@ -522,12 +522,12 @@ void inv_potential(fg_plan* P, R* data, const Skip& skip) {
 // One CG iteration for every item of the plan (items whose solve is done
 // skip every kernel), on the potentials rho, pi, xi of r = D rho, p = D pi,
 // x = D xi (fg_potential.hpp):
-//   xi += alpha_{k-1} pi_{k-1}; pi = rho + beta pi; Y = K:(D pi); p.Y; N2 pass of Y
-//   alpha = r.r / p.Kp; N1 pass (9 components in, the two terms of each row
-//   that share the N0 factor merged); N0 pass reducing the projection to
-//   the 3-component potential; N1 and N2 inverse passes of
-//   the potential U (D U = G(K p)); rho -= alpha U, r.r = |D rho|^2; beta,
-//   convergence.
+//   xi += alpha_{k-1} pi_{k-1}; pi = rho + beta pi; Y = K:(D pi); p.Y; N2
+//   pass of Y; N1 pass (9 components in, the two terms of each row that
+//   share the N0 factor merged; alpha = r.r / p.Kp by one workgroup per
+//   item); N0 pass reducing the projection to the 3-component potential; N1
+//   and N2 inverse passes of the potential U (D U = G(K p)); rho -= alpha U,
+//   r.r = |D rho|^2; beta, convergence.
 template <typename T>
 void cg_iteration(fg_plan* P) {
   T* S = (T*)P->S;
@@ -542,13 +542,9 @@ void cg_iteration(fg_plan* P) {
                              P->n1, P->h, tb, P->stream, nit);
   }
   {
-    ProfScope ps(P, FG_PASS_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3(nit), dim3(1024), 0, P->stream, P->part, nbf / nit, ks, (double*)nullptr, 0,
-                       0);
-  }
-  {
+    // alpha = r.r / p.Ap is formed by the row pass (one workgroup per item)
     ProfScope ps(P, FG_PASS_AXIS);
-    launch_axis_rows<T>(P->n1, S, P->n0, P->M, tb, skip, P->stream, nit, tile_axis<T>(P));
+    launch_axis_rows<T>(P->n1, S, P->n0, P->M, tb, skip, P->stream, nit, tile_axis<T>(P), P->part, nbf / nit, ks);
   }
   {
     ProfScope ps(P, FG_PASS_ZPROJ);

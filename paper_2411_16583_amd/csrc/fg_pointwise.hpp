@@ -252,23 +252,6 @@ k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// Sum of nparts partials in a fixed order by one block (deterministic).
-// Each thread keeps eight independent running sums, so that eight loads are
-// in flight per thread instead of one (the partials come from other XCDs'
-// L2 or from HBM).
-__device__ __forceinline__ double sum_partials(const double* __restrict__ partials, int nparts, double* red) {
-  const int bd = blockDim.x;
-  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int k = threadIdx.x;
-  for (; k + 7 * bd < nparts; k += 8 * bd) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += partials[k + u * bd];
-  }
-  for (; k < nparts; k += bd) a[0] += partials[k];
-  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  return block_sum(acc, red);
-}
-
 // mode 0: alpha = rz / pAp (rz = rr for plain CG), breakdown check.
 // mode 1: plain CG: rr_new, iteration count, convergence, beta.
 // mode 2: store the sum into out[0] (norms).
@@ -286,13 +269,7 @@ k_finalize(const double* __restrict__ partials, int nparts, KrylovScalars* ks, d
   const double s = sum_partials(partials, nparts, red);
   if (threadIdx.x != 0) return;
   if (mode == 0) {
-    ks->pAp = s;
-    if (!(s > 0.0)) {
-      ks->done = 1;
-      ks->flag = 1;
-    } else {
-      ks->alpha = (pcg ? ks->rz : ks->rr) / s;
-    }
+    krylov_alpha(ks, s, pcg);
   } else if (mode == 1) {
     const double rr = s;
     ks->iter += 1;

@@ -521,21 +521,24 @@ k_fft_z_scalar(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, double 
 // OP = 1: scalar symbol (grid.y = 1);
 // OP = 2: projection to the 3-component potential (see k_fft_z_grad3), one
 //         row per workgroup (grid.y = 3 rows per item), U_i into slot 3 i.
+// LDS of z_dc_body in complex values: exchange buffer of the column pair
+// and the spectra of the components read.
+template <int L, int OP> constexpr int z_dc_lds() { return 2 * L + ((OP == 1) ? 1 : 3) * 2 * L; }
+
+// Body of k_fft_z_dc for the column pair (ky0, -ky0) of row `row` (OP 0, 2)
+// with xbuf (2 L) and spec (NC 2 L complex) in LDS; any block size of at
+// least 2 T threads (the others take part in the barriers only).
 template <typename R, int L, int OP>
-__global__ void __launch_bounds__(64)
-k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, Skip skip) {
+__device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0,
+                                          double a1, int ky0, int row, cplx<R>* xbuf, cplx<R>* spec) {
   using C = cplx<R>;
   using LS = Line<L>;
   constexpr int NC = (OP == 1) ? 1 : 3;    // components read per row
   constexpr int NOUT = (OP == 0) ? 3 : 1;  // components written per row
-  __shared__ C xbuf[2 * L];
-  __shared__ C spec[NC * 2 * L];
-  if (skip(blockIdx.y)) return;
   const int col = threadIdx.x % 2;
   const int t = threadIdx.x / 2;
   // idle lanes (t >= T) still take part in every barrier below
   const bool lane_ok = t < LS::T;
-  const int ky0 = blockIdx.x;
   const int ky1 = (N1 - ky0) % N1;
   const int myky = col ? ky1 : ky0;
   const long plane = (long)N1 * M;
@@ -544,7 +547,7 @@ k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double 
   const bool store = lane_ok && (col == 0 || ky1 != ky0);
   {
     // first component read and written by this workgroup's row
-    const int cin = (OP == 1) ? 0 : 3 * (int)blockIdx.y;
+    const int cin = (OP == 1) ? 0 : 3 * row;
     const int cout = cin;
     for (int l = 0; l < NC; ++l) {
       C v[LS::E];
@@ -582,18 +585,24 @@ k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double 
         for (int e = 0; e < LS::E; ++e) spec[(l * 2 + col) * L + LS::idxB(t, e)] = v[e];
     }
     __syncthreads();
-    // separate, apply, recombine: thread (t, col) owns kz = idxB(t, e) of its column
-    C tA[LS::E], tB[LS::E];
+    // separate, apply, recombine: thread (t, col) owns kz = idxB(t, e) of its column.
+    // With one output (OP 1, 2) the recombined value goes straight into v1;
+    // the projection (OP 0, three outputs) keeps tA, tB.
+    constexpr int TE = (NOUT == 1) ? 1 : LS::E;
+    C tA[TE], tB[TE], v1[LS::E];
 #pragma unroll
-    for (int e = 0; e < LS::E; ++e) {
+    for (int e = 0; e < TE; ++e) {
       tA[e] = mk<C>(R(0), R(0));
       tB[e] = mk<C>(R(0), R(0));
     }
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) v1[e] = mk<C>(R(0), R(0));
     if (lane_ok) {
 #pragma unroll
       for (int e = 0; e < LS::E; ++e) {
         const int kz = LS::idxB(t, e);
         const int kzm = (L - kz) % L;
+        C ta = mk<C>(R(0), R(0)), tbv = mk<C>(R(0), R(0));
         if constexpr (OP != 1) {
           const RVec<R> rA = rot_vec(tb, kz, myky, 0);
           const RVec<R> rB = rot_vec(tb, kz, myky, M);
@@ -603,13 +612,13 @@ k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double 
             const C A = cscale(cadd(P, cconj(Pm)), R(0.5));
             const C Bv = cscale(mul_mi(csub(P, cconj(Pm))), R(0.5));
             const R ra = rget(rA, l), rb = rget(rB, l);
-            tA[e] = mk<C>(tA[e].x + A.x * ra, tA[e].y + A.y * ra);
-            tB[e] = mk<C>(tB[e].x + Bv.x * rb, tB[e].y + Bv.y * rb);
+            ta = mk<C>(ta.x + A.x * ra, ta.y + A.y * ra);
+            tbv = mk<C>(tbv.x + Bv.x * rb, tbv.y + Bv.y * rb);
           }
           const R a2 = rA.x * rA.x + rA.y * rA.y + rA.z * rA.z;
           const R b2 = rB.x * rB.x + rB.y * rB.y + rB.z * rB.z;
-          tA[e] = cscale(tA[e], a2 > R(0) ? scale / a2 : R(0));
-          tB[e] = cscale(tB[e], b2 > R(0) ? scale / b2 : R(0));
+          ta = cscale(ta, a2 > R(0) ? scale / a2 : R(0));
+          tbv = cscale(tbv, b2 > R(0) ? scale / b2 : R(0));
         } else {
           const C P = spec[col * L + kz];
           const C Pm = spec[(1 - col) * L + kzm];
@@ -617,8 +626,20 @@ k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double 
           const C Bv = cscale(mul_mi(csub(P, cconj(Pm))), R(0.5));
           const double dA = a0 + a1 * (double)lap_sym(tb, kz, myky, 0);
           const double dB = a0 + a1 * (double)lap_sym(tb, kz, myky, M);
-          tA[e] = cscale(A, (R)((double)scale / dA));
-          tB[e] = cscale(Bv, (R)((double)scale / dB));
+          ta = cscale(A, (R)((double)scale / dA));
+          tbv = cscale(Bv, (R)((double)scale / dB));
+        }
+        if constexpr (OP == 2) {
+          // potential U = -i e^{i Phi} w: at qx = 0, U_A = -i e^{i Phi_A} tA;
+          // at qx = pi, e^{i Phi_B} = i e^{i Phi_A}, so U_B = e^{i Phi_A} tB;
+          // packed as U_A + i U_B
+          const C ph = cmul(mk<C>(tb.cz[kz], tb.snz[kz]), mk<C>(tb.cy[myky], tb.sny[myky]));  // e^{i Phi_A}
+          v1[e] = cadd(mul_mi(cmul(ta, ph)), mul_pi(cmul(tbv, ph)));
+        } else if constexpr (OP == 1) {
+          v1[e] = cadd(ta, mul_pi(tbv));
+        } else {
+          tA[e] = ta;
+          tB[e] = tbv;
         }
       }
     }
@@ -626,21 +647,13 @@ k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double 
       C v[LS::E];
 #pragma unroll
       for (int e = 0; e < LS::E; ++e) {
-        const int kz = LS::idxB(t, e);
         if constexpr (OP == 0) {
+          const int kz = LS::idxB(t, e);
           const C a = cscale(tA[e], rget(rot_vec(tb, kz, myky, 0), j));
           const C b = cscale(tB[e], rget(rot_vec(tb, kz, myky, M), j));
           v[e] = cadd(a, mul_pi(b));  // A' + i B'
-        } else if constexpr (OP == 2) {
-          // potential U = -i e^{i Phi} w: at qx = 0, U_A = -i e^{i Phi_A} tA;
-          // at qx = pi, e^{i Phi_B} = i e^{i Phi_A}, so U_B = e^{i Phi_A} tB;
-          // packed as U_A + i U_B
-          const C ph = cmul(mk<C>(tb.cz[kz], tb.snz[kz]), mk<C>(tb.cy[myky], tb.sny[myky]));  // e^{i Phi_A}
-          const C a = mul_mi(cmul(tA[e], ph));
-          const C b = cmul(tB[e], ph);
-          v[e] = cadd(a, mul_pi(b));
         } else {
-          v[e] = cadd(tA[e], mul_pi(tB[e]));
+          v[e] = v1[e];
         }
       }
       if constexpr (LS::R2 == 1) {
@@ -673,6 +686,14 @@ k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double 
         for (int e = 0; e < LS::E; ++e) base[(cout + j) * comp + LS::idxA(t, e) * plane] = v[e];
     }
   }
+}
+
+template <typename R, int L, int OP>
+__global__ void __launch_bounds__(64)
+k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, Skip skip) {
+  __shared__ cplx<R> lds[z_dc_lds<L, OP>()];
+  if (skip(blockIdx.y)) return;
+  z_dc_body<R, L, OP>(data, N1, M, tb, scale, a0, a1, (int)blockIdx.x, (int)blockIdx.y, lds, lds + 2 * L);
 }
 
 }  // namespace fg

@@ -10,6 +10,8 @@
 //   k_grad_store                      Z = D U as a 9-component field (the
 //                                     projection itself, or the CG solution
 //                                     x = D xi in double precision).
+//   k_grad_norm                       partial sums of |D U|^2 (the Newton
+//                                     residual norm |G*P| from U(P)).
 #pragma once
 #include "fg_fft.hpp"
 #include "fg_potential.hpp"
@@ -172,6 +174,40 @@ k_grad_store(const TI* __restrict__ U, long ucs, long uis, TO* __restrict__ Z, l
   }
 }
 
+// Per-block partial sums of |D U|^2 (U: 3 components ucs apart, uis per
+// item; grid (ceil(N / (256 W)), items)), items with idle[b] != 0 skipped:
+// the norm of the projection G*X = D U(X) from its potential.
+template <typename T, int W>
+__global__ void __launch_bounds__(256)
+k_grad_norm(const T* __restrict__ U, long ucs, long uis, const int* __restrict__ idle, double* __restrict__ partials,
+            int n0, int n1, int n2, T q0, T q1, T q2) {
+  __shared__ double red[16];
+  const int item = blockIdx.y;
+  if (idle && idle[item]) return;
+  const long N = (long)n0 * n1 * n2;
+  U += (long)item * uis;
+  const int G = n2 / W;
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (g < N / W) {
+    const long line = g / G;
+    const StencilLines sl = stencil_lines(line, W * (int)(g - line * G), n0, n1, n2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T u[2][2][W + 1];
+      load_corners<T, W>(U + c * ucs, sl, u);
+      T Z[3][W];
+      corner_grad<T, W>(u, q0, q1, q2, Z);
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int v = 0; v < W; ++v) acc += (double)Z[j][v] * (double)Z[j][v];
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[(long)item * gridDim.x + blockIdx.x] = s;
+}
+
 // CG start of an item: rho (half 0) = sign * U (U: 3 components ucs apart in
 // double precision, uis per item), xi = 0.  grid.y = item.
 template <typename T>
@@ -216,6 +252,17 @@ int launch_cg_rupd(const T* U, long ucs, T* rbuf, const KrylovScalars* ks, const
   hipLaunchKernelGGL((k_cg_rupd_march<T, 2>), dim3((unsigned)(3 * bx * nseg * nitems)), dim3(256), 0, s, U, ucs, rbuf,
                      ks, idle, partials, n0, n1, n2, K, q0, q1, q2, mode);
   return (int)(3 * bx * nseg);
+}
+
+// |D U|^2 partial sums over all items (two voxels per thread); returns the
+// partials per item.
+inline int launch_grad_norm(const double* U, long ucs, long uis, const int* idle, double* partials, int n0, int n1,
+                            int n2, int nitems, const double h[3], hipStream_t s) {
+  const long N = (long)n0 * n1 * n2;
+  const dim3 grid((unsigned)((N / 2 + 255) / 256), (unsigned)nitems);
+  hipLaunchKernelGGL((k_grad_norm<double, 2>), grid, dim3(256), 0, s, U, ucs, uis, idle, partials, n0, n1, n2,
+                     0.25 / h[0], 0.25 / h[1], 0.25 / h[2]);
+  return (int)grid.x;
 }
 
 // Z = D U over all items (two voxels per thread).

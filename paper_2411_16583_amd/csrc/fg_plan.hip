@@ -449,11 +449,20 @@ void constitutive(fg_plan* P, const double* Fu, double* Pout, void* state, doubl
 }
 
 // ||G*P|| of the stress in S64 (in place), into dscal[slot]; G*P stays in S64.
-void residual_norm(fg_plan* P, int slot) {
-  C2REpi epi{1.0, nullptr, true, P->part, Skip{}};
-  const int nb = project9<double>(P, P->S64, P->S64, P->S64, epi);
-  reduce_to(P, P->part, nb, slot);
+void potential64(fg_plan* P, double* field, const Skip& skip);
+
+// |G*P|^2 of the FP64 9-component fields in S64 (all items not idle) by the
+// potential route: S64 is replaced by the potential U(P) (slot 3i of each
+// item, D U = G*P) and the partial sums of |D U|^2 go to P->part; returns
+// the partials per item.  A following cg_start may reuse U.
+int residual_pot(fg_plan* P, const int* idle) {
+  potential64(P, P->S64, idle ? Skip::flags(idle) : Skip{});
+  return launch_grad_norm(P->S64, 3 * P->N, 9 * P->N, idle, P->part, P->n0, P->n1, P->n2, P->nitems, P->h,
+                          P->stream);
 }
+
+// |G*P|^2 of a single-item plan into dscal[slot] (S64 ends up holding U(P)).
+void residual_norm(fg_plan* P, int slot) { reduce_to(P, P->part, residual_pot(P, nullptr), slot); }
 
 // mean of a 9-component FP64 field into dscal[8 + k]
 void mean9(fg_plan* P, const double* field) {
@@ -588,13 +597,14 @@ void potential64(fg_plan* P, double* field, const Skip& skip) {
 }
 
 // CG start on the potentials for every item not idle: rho_0 = sign U with U
-// the potential of the compatible FP64 field `field` (overwritten), so that
+// the potential of the FP64 field `field` (overwritten; with potential_ready
+// `field` already holds U, as residual_pot leaves it), so that
 // r_0 = D rho_0 = sign G(field); xi = 0; per-block partial sums of
 // |r_0|^2 = |D rho_0|^2 into P->part.  Returns the partials per item (the
 // caller reduces them into the Krylov scalars).
 template <typename T>
-int cg_start(fg_plan* P, double* field, double sign, const int* idle) {
-  potential64(P, field, idle ? Skip::flags(idle) : Skip{});
+int cg_start(fg_plan* P, double* field, double sign, const int* idle, bool potential_ready = false) {
+  if (!potential_ready) potential64(P, field, idle ? Skip::flags(idle) : Skip{});
   const long N = P->N;
   hipLaunchKernelGGL((k_cg_start_pot<T>), item_grid(3 * N, P->nitems), dim3(256), 0, P->stream, (T*)P->r, (T*)P->x,
                      (const double*)field, 3 * N, 9 * N, sign, idle, N);
@@ -607,8 +617,8 @@ int cg_start(fg_plan* P, double* field, double sign, const int* idle) {
 // Single-item CG start: cg_start and the Krylov scalars (rr0 = rr = |r_0|^2,
 // iter = 0, done if r_0 = 0).
 template <typename T>
-void cg_start1(fg_plan* P, double* field, double sign) {
-  const int nb = cg_start<T>(P, field, sign, nullptr);
+void cg_start1(fg_plan* P, double* field, double sign, bool potential_ready = false) {
+  const int nb = cg_start<T>(P, field, sign, nullptr, potential_ready);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part, nb, P->ks, (double*)nullptr, 5, 0);
   check_launch();
 }
@@ -695,10 +705,10 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
     const double tol_eff = (P->prec == FG_MIXED) ? 0.01 * o->tol_newton : o->tol_newton;
     if (err <= tol_eff) break;
     if (it >= o->max_newton) throw Status(FG_E_NOCONV, "Newton reached max_newton iterations");
-    // b = -G*P (S64 holds G*P from the residual pass): r_0 = D rho_0 with
-    // rho_0 = -U, U the potential of G*P
+    // b = -G*P: r_0 = D rho_0 with rho_0 = -U(P), the potential the residual
+    // pass left in S64
     if (P->prec == FG_FP64) {
-      cg_start1<double>(P, P->S64, -1.0);
+      cg_start1<double>(P, P->S64, -1.0, true);
       cg_solve<double>(P, o, stats);
       cg_result<double>(P, P->S64, nullptr);
     } else {
@@ -707,7 +717,7 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
       // 1e-7 at 256^3 (FFT rounding), so CG is not asked for more than 1e-5;
       // the double-precision Newton residual refines the rest.
       if (om.fixed_lin <= 0) om.tol_lin = std::max(o->tol_lin, 1e-5);
-      cg_start1<float>(P, P->S64, -1.0);
+      cg_start1<float>(P, P->S64, -1.0, true);
       cg_solve<float>(P, &om, stats);
       // dF = D xi evaluated in double precision: a discrete gradient, hence
       // compatible to rounding whatever the single-precision error of xi
@@ -1473,7 +1483,6 @@ void batch_tick(fg_plan* P, fg_batch::Group& g, bool newton) {
   const dim3 gi = item_grid(n9, nit);
   hipLaunchKernelGGL(k_newton_gate, dim3(1), dim3(1024), 0, P->stream, (const KrylovScalars*)P->ks, g.nc, g.idle,
                      g.active, nit, (int)FG_E_BREAKDOWN, (int)FG_E_NOCONV);
-  const Skip idle = Skip::flags(g.idle);
   // F += D xi, evaluated in double precision (a discrete gradient: compatible
   // to rounding also in the mixed form)
   cg_result<T>(P, P->S64, g.idle);
@@ -1481,15 +1490,14 @@ void batch_tick(fg_plan* P, fg_batch::Group& g, bool newton) {
                      (const int*)g.idle, n9);
   constitutive(P, nullptr, P->S64, P->st, nullptr, g.idle);
   {
-    // err_res of eq. (31) and the Newton test
-    C2REpi e{1.0, nullptr, true, P->part, idle};
-    const int nb = project9<double>(P, P->S64, P->S64, P->S64, e);
-    hipLaunchKernelGGL(k_newton_check, dim3(nit), dim3(1024), 0, P->stream, (const double*)P->part, nb / nit, g.nc,
+    // err_res of eq. (31) from |D U(P)| = |G*P| and the Newton test
+    const int nb = residual_pot(P, g.idle);
+    hipLaunchKernelGGL(k_newton_check, dim3(nit), dim3(1024), 0, P->stream, (const double*)P->part, nb, g.nc,
                        g.idle, (int)FG_E_NOCONV);
   }
   {
-    // b = -G*P (S64 holds G*P): rho_0 = -U, xi = 0, and a fresh CG
-    const int nb = cg_start<T>(P, P->S64, -1.0, g.idle);
+    // b = -G*P: rho_0 = -U(P) (left in S64), xi = 0, and a fresh CG
+    const int nb = cg_start<T>(P, P->S64, -1.0, g.idle, true);
     hipLaunchKernelGGL(k_newton_cg_start, dim3(nit), dim3(1024), 0, P->stream, (const double*)P->part, nb, P->ks, g.nc,
                        (const int*)g.idle);
   }
@@ -1555,11 +1563,7 @@ void batch_prologue(fg_batch* B, fg_batch::Group& g, const double* F_macro, cons
   // ||P(Fbar)||^2 and ||G*P(Fbar)||^2 per item
   constitutive(P, P->Fu, P->S64, nullptr, P->part2);
   reduce_items(P, P->part2, (int)blocks_for(N), 0);
-  {
-    C2REpi e{1.0, nullptr, true, P->part, Skip{}};
-    const int nb = project9<double>(P, P->S64, P->S64, P->S64, e);
-    reduce_items(P, P->part, nb / nit, 1);
-  }
+  reduce_items(P, P->part, residual_pot(P, nullptr), 1);
   sync_read(P);
   check_domain(P);
   const bool mixed = (P->prec == FG_MIXED);

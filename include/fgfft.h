@@ -313,7 +313,7 @@ enum {
   FG_PASS_ZSCALAR = 8,      /* N0 pass fused with a scalar symbol          */
   FG_PASS_AXIS3 = 9,        /* inverse N1 pass of the 3-component potential */
   FG_PASS_C2R3 = 10,        /* inverse N2 pass of the potential            */
-  FG_PASS_GRAD = 11,        /* corner-stencil gradient + r -= a Ap, r.r    */
+  FG_PASS_GRAD = 11,        /* residual update rho -= a U and |D rho|^2    */
   FG_NPASS = 12
 };
 
@@ -326,6 +326,11 @@ enum {
  * adds two event records per launch while enabled. */
 fg_status fg_profile_begin(fg_plan* plan);
 fg_status fg_profile_end(fg_plan* plan, double ms[], long launches[]);
+
+/* Restrict the timing to the kernel classes whose bit (1 << FG_PASS_*) is
+ * set in mask (default: all); the others then cost no event records.  Not
+ * while profiling is on.  Errors: FG_E_ARG. */
+fg_status fg_profile_passes(fg_plan* plan, unsigned mask);
 
 const char* fg_status_string(fg_status s);
 const char* fg_last_error(const fg_plan* plan);

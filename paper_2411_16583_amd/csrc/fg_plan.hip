@@ -177,6 +177,7 @@ struct fg_plan {
 
   // optional per-kernel-class timing with HIP events (fg_profile_*)
   bool prof_on = false;
+  unsigned prof_mask = ~0u;  // kernel classes timed while prof_on (bit = FG_PASS_*)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[FG_NPASS];
   size_t prof_used[FG_NPASS] = {};
   long prof_noop[FG_NPASS] = {};
@@ -312,7 +313,7 @@ struct ProfScope {
   int pass;
   hipEvent_t stop = nullptr;
   ProfScope(fg_plan* P_, int pass_) : P(P_), pass(pass_) {
-    if (!P->prof_on) return;
+    if (!P->prof_on || !(P->prof_mask >> pass & 1u)) return;
     auto& v = P->prof_ev[pass];
     size_t& u = P->prof_used[pass];
     if (u == v.size()) {
@@ -492,13 +493,9 @@ int next_chunk(const KrylovScalars& h, long launched) {
 // (they return at once); excluded from the profiled launch counts.
 void note_noop_iterations(fg_plan* P, long noop) {
   if (!P->prof_on || noop <= 0) return;
-  P->prof_noop[FG_PASS_FRONT] += noop;
-  P->prof_noop[FG_PASS_AXIS] += noop;
-  P->prof_noop[FG_PASS_ZPROJ] += noop;
-  P->prof_noop[FG_PASS_AXIS3] += noop;
-  P->prof_noop[FG_PASS_C2R3] += noop;
-  P->prof_noop[FG_PASS_GRAD] += noop;
-  P->prof_noop[FG_PASS_FINALIZE] += noop;
+  for (int pass : {FG_PASS_FRONT, FG_PASS_AXIS, FG_PASS_ZPROJ, FG_PASS_AXIS3, FG_PASS_C2R3, FG_PASS_GRAD,
+                   FG_PASS_FINALIZE})
+    if (P->prof_mask >> pass & 1u) P->prof_noop[pass] += noop;
 }
 
 // Grid of a per-item field kernel: up to 256 blocks per item, grid.y = item.
@@ -1345,6 +1342,12 @@ fg_status fg_profile_begin(fg_plan* P) {
       P->prof_noop[k] = 0;
     }
   });
+}
+
+fg_status fg_profile_passes(fg_plan* P, unsigned mask) {
+  if (!P || P->batch_group || P->prof_on) return FG_E_ARG;
+  P->prof_mask = mask;
+  return FG_OK;
 }
 
 fg_status fg_profile_end(fg_plan* P, double ms[], long launches[]) {

@@ -29,7 +29,8 @@ EXPORTED = [
     "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
     "fg_batch_plan", "fg_batch_group_info", "fg_batch_set_schedule", "fg_plan_tile_candidates", "fg_plan_set_tiles", "fg_plan_get_tiles",
     "fg_plan_time_pass",
-    "fg_profile_begin", "fg_profile_end", "fg_status_string", "fg_last_error", "fg_plan_destroy",
+    "fg_profile_begin", "fg_profile_end", "fg_profile_passes", "fg_status_string", "fg_last_error",
+    "fg_plan_destroy",
 ]
 PASS_NAMES = ["front", "r2c", "axis", "zproj", "c2r", "cg_update", "finalize", "constitutive", "zscalar", "axis3",
               "c2r3", "grad"]
@@ -111,6 +112,7 @@ def load_library(path=LIB_PATH):
         "pff_solve": ([vp, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
         "fick_step": ([vp, c_double, dptr, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
         "fg_profile_begin": ([vp], c_int),
+        "fg_profile_passes": ([vp, ctypes.c_uint], c_int),
         "fg_profile_end": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(ctypes.c_long)], c_int),
         "fg_status_string": ([c_int], ctypes.c_char_p),
         "fg_last_error": ([vp], ctypes.c_char_p),
@@ -304,7 +306,11 @@ class Plan:
         self._check(self.lib.fg_plan_set_tiles(self.handle, (ctypes.c_int * 4)(*[int(t) for t in tiles])),
                     "fg_plan_set_tiles")
 
-    def profile_begin(self):
+    def profile_begin(self, passes=None):
+        """Start timing the kernel classes named in passes (PASS_NAMES;
+        default: all of them)."""
+        mask = 0xFFFFFFFF if passes is None else sum(1 << PASS_NAMES.index(p) for p in passes)
+        self._check(self.lib.fg_profile_passes(self.handle, mask), "fg_profile_passes")
         self._check(self.lib.fg_profile_begin(self.handle), "fg_profile_begin")
 
     def profile_end(self):

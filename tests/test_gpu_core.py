@@ -227,6 +227,31 @@ def test_inclusion_newton_fp64_tight_matches_discrete_solution():
     assert rel(Fg, F, fl) <= 1e-10
 
 
+@pytest.mark.parametrize("shape", [(6, 12, 6), (12, 6, 24)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_newton_small_odd_grids_match_oracle(shape, precision, tol):
+    """Newton-CG on grids whose half line along N2 is odd or short (M = 3:
+    one-thread lines and two-voxel stencil groups; M = 12) with a random
+    two-phase material and a mixed macro load, against the oracle's
+    discrete solution (both converged far below the tolerance)."""
+    work = synth.homogeneous_workload(shape)
+    rng = np.random.default_rng(61206 + shape[2])
+    phase = rng.random(shape) < 0.3
+    work["E"] = np.where(phase, 100e9, 10e9)
+    work["nu"] = np.where(phase, 0.25, 0.3)
+    Fbar = np.eye(3)
+    Fbar[0, 0] += 0.004
+    Fbar[1, 2] += 0.002
+    work["loads"] = [Fbar]
+    tn = 1e-12 if precision == "fp64" else 1e-10
+    gpu = run_increments_gpu(work, precision, tol_newton=tn, tol_lin=1e-12)
+    F, _ = mechanics.solve_increments(work, tol_newton=1e-12, tol_lin=1e-12)
+    Fg, sg = gpu[-1]
+    e = rel(Fg, F, F - mechanics.uniform_field(Fbar, shape))
+    print(f"{shape} {precision}: newton {sg['newton_iters']} cg {sg['lin_history']} rel {e:.2e}", flush=True)
+    assert e <= tol
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_homogeneous_cell_exact_without_iterations(precision):
     """Uniform material, c and d (any Fbar): F = Fbar exactly and no Newton

@@ -347,9 +347,10 @@ template <typename R> constexpr size_t zgrad_extra_lds(int L) {
 // N0 transforms X_0, X_1 of the two slots (two forward transforms and one
 // inverse per row).  Grid (M/B, N1, 3 rows per item), or (N1, M/B, rows) with
 // kymajor.  The kx = 0 column is left to k_fft_z_dc<OP = 2>.
-template <typename R, int L>
+template <typename R, int L, int CPT>
 __global__ void __launch_bounds__(256)
 k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor) {
+  static_assert(CPT == 1 || (CPT == 2 && sizeof(R) == 4), "column pairs in single precision");
   using C = cplx<R>;
   using LS = ZLine<L>;
   extern __shared__ char smem_raw[];
@@ -366,43 +367,75 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
     snz[k] = tb.snz[k];
   }
   __syncthreads();
-  const int col = threadIdx.x % B;
-  const int t = threadIdx.x / B;
-  const int kx = (kymajor ? blockIdx.y : blockIdx.x) * B + col;
+  // CPT adjacent columns per thread (single precision: two, one 16-byte
+  // access per row, so that a tile row is a whole 128-byte line)
+  const int BC = B / CPT;
+  const int col0 = CPT * (int)(threadIdx.x % BC);
+  const int t = threadIdx.x / BC;
+  const int kx0 = (kymajor ? blockIdx.y : blockIdx.x) * B + col0;
   const int ky = kymajor ? blockIdx.x : blockIdx.y;
   const int i = blockIdx.z;  // row of the 3x3 field, items consecutive
   const long plane = (long)N1 * M;
   const long comp = (long)L * plane;
   // workgroup-uniform base of the row's first slot and a 32-bit element
   // offset per thread (col + kz plane; a component is < 2^32 bytes)
-  C* base = reinterpret_cast<C*>(data) + (long)(3 * i) * comp + (long)ky * M + (kx - col);
+  C* base = reinterpret_cast<C*>(data) + (long)(3 * i) * comp + (long)ky * M + (kx0 - col0);
   const unsigned uplane = (unsigned)plane;
   const unsigned ucomp = (unsigned)comp;
-  C v[LS::E], acc[LS::E];
+  C v[CPT][LS::E], acc[CPT][LS::E];
+  if constexpr (CPT == 2) {
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) v[e] = base[(unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
+    for (int e = 0; e < LS::E; ++e) {
+      const float4 a = *reinterpret_cast<const float4*>(base + (unsigned)col0 + (unsigned)LS::idxA(t, e) * uplane);
+      const float4 b = *reinterpret_cast<const float4*>(base + ucomp + (unsigned)col0 + (unsigned)LS::idxA(t, e) * uplane);
+      v[0][e] = mk<C>(a.x, a.y);
+      v[1][e] = mk<C>(a.z, a.w);
+      acc[0][e] = mk<C>(b.x, b.y);
+      acc[1][e] = mk<C>(b.z, b.w);
+    }
+  } else {
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) acc[e] = base[ucomp + (unsigned)col + (unsigned)LS::idxA(t, e) * uplane];
-  const R cy = tb.cy[ky], sy = tb.sy[ky], cx = tb.cx[kx], sx = tb.sx[kx];
-  const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
-  // -i e^{i (qy + qx) / 2}; the kz factor is applied per element
-  const C eyx = mul_mi(cmul(mk<C>(cy, tb.sny[ky]), mk<C>(cx, tb.snx[kx])));
-  LS::template fwd<false>(v, lds + col, B, t, stw);
-  LS::template fwd<false>(acc, lds + col, B, t, stw);
+    for (int e = 0; e < LS::E; ++e) v[0][e] = base[(unsigned)col0 + (unsigned)LS::idxA(t, e) * uplane];
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) {
-    const int kz = LS::idxB(t, e);
-    const R sz = ssz[kz], cz = scz[kz];
-    const R a = sz * fx0, b = cz * fx1, c = cz * fx2;
-    const R r2 = a * a + b * b + c * c;
-    const R f = (r2 > R(0)) ? scale / r2 : R(0);
-    const C w = mk<C>((v[e].x * sz + acc[e].x * cz) * f, (v[e].y * sz + acc[e].y * cz) * f);
-    acc[e] = cmul(w, cmul(mk<C>(cz, snz[kz]), eyx));
+    for (int e = 0; e < LS::E; ++e) acc[0][e] = base[ucomp + (unsigned)col0 + (unsigned)LS::idxA(t, e) * uplane];
   }
-  LS::inv(acc, lds + col, B, t, stw);
-  if (kx != 0) {
+  const R cy = tb.cy[ky], sy = tb.sy[ky];
 #pragma unroll
-    for (int e = 0; e < LS::E; ++e) base[(unsigned)col + (unsigned)LS::idxA(t, e) * uplane] = acc[e];
+  for (int c = 0; c < CPT; ++c) {
+    const int kx = kx0 + c;
+    const R cx = tb.cx[kx], sx = tb.sx[kx];
+    const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
+    // -i e^{i (qy + qx) / 2}; the kz factor is applied per element
+    const C eyx = mul_mi(cmul(mk<C>(cy, tb.sny[ky]), mk<C>(cx, tb.snx[kx])));
+    LS::template fwd<false>(v[c], lds + col0 + c, B, t, stw);
+    LS::template fwd<false>(acc[c], lds + col0 + c, B, t, stw);
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const int kz = LS::idxB(t, e);
+      const R sz = ssz[kz], cz = scz[kz];
+      const R a = sz * fx0, b = cz * fx1, cc = cz * fx2;
+      const R r2 = a * a + b * b + cc * cc;
+      const R f = (r2 > R(0)) ? scale / r2 : R(0);
+      const C w = mk<C>((v[c][e].x * sz + acc[c][e].x * cz) * f, (v[c][e].y * sz + acc[c][e].y * cz) * f);
+      acc[c][e] = cmul(w, cmul(mk<C>(cz, snz[kz]), eyx));
+    }
+    LS::inv(acc[c], lds + col0 + c, B, t, stw);
+  }
+  // the kx = 0 column is k_fft_z_dc's
+  if constexpr (CPT == 2) {
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      C* dst = base + (unsigned)col0 + (unsigned)LS::idxA(t, e) * uplane;
+      if (kx0 != 0)
+        *reinterpret_cast<float4*>(dst) = make_float4(acc[0][e].x, acc[0][e].y, acc[1][e].x, acc[1][e].y);
+      else
+        dst[1] = acc[1][e];
+    }
+  } else {
+    if (kx0 != 0) {
+#pragma unroll
+      for (int e = 0; e < LS::E; ++e) base[(unsigned)col0 + (unsigned)LS::idxA(t, e) * uplane] = acc[0][e];
+    }
   }
 }
 

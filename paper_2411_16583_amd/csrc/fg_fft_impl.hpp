@@ -119,7 +119,8 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
   // built-in choice (tile 0): the largest tile, workgroups ky fastest
   const int kymajor = (tile == 0 || (tile & kTileKyMajor)) ? 1 : 0;
   tile &= ~kTileKyMajor;
-  const int B = tile > 0 ? tile : column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
+  int B = tile > 0 ? tile : column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
+  while (B > 1 && T * B > 256) B /= 2;  // a tile chosen for the column-pair N0 pass
   const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zpass_extra_lds<R>(N0);
   dim3 grid = kymajor ? dim3((unsigned)N1, (unsigned)(M / B), (unsigned)(3 * nitems))
                       : dim3((unsigned)(M / B), (unsigned)N1, (unsigned)(3 * nitems));
@@ -143,7 +144,10 @@ void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
   const int T = zline_threads(N0);
   const int kymajor = (tile == 0 || (tile & kTileKyMajor)) ? 1 : 0;
   tile &= ~kTileKyMajor;
-  const int B = tile > 0 ? tile : column_tile_t(T, N0, M, (int)sizeof(cplx<R>));
+  // single precision: two adjacent columns per thread
+  constexpr int CPT = (sizeof(R) == 4) ? 2 : 1;
+  const int B = tile > 0 ? tile : zgrad_tile(N0, M, (int)sizeof(cplx<R>));
+  const int cpt = (B % CPT == 0) ? CPT : 1;
   const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zgrad_extra_lds<R>(N0);
   dim3 grid = kymajor ? dim3((unsigned)N1, (unsigned)(M / B), (unsigned)(3 * nitems))
                       : dim3((unsigned)(M / B), (unsigned)N1, (unsigned)(3 * nitems));
@@ -152,8 +156,12 @@ void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
   switch (N0) {
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \
-    hipLaunchKernelGGL((k_fft_z_grad3<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, sk, \
-                       kymajor);                                                                       \
+    if (cpt == 2)                                                                                      \
+      hipLaunchKernelGGL((k_fft_z_grad3<R, L_, CPT>), grid, dim3(T * B / 2), shm, s, data, N1, M, B, tb, scale, \
+                         sk, kymajor);                                                                 \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_fft_z_grad3<R, L_, 1>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, sk, \
+                         kymajor);                                                                     \
     hipLaunchKernelGGL((k_fft_z_dc<R, L_, 2>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, sk); \
     return;
     FG_FOR_AXIS(FG_CASE)

@@ -18,6 +18,7 @@ int column_tile_t(int T, int L, int M, int elem_bytes);
 int column_tile_cpt(int L, int M, int elem_bytes, int cpt);
 int line_threads(int L);
 int zline_threads(int L);  // threads per line of the fused N0 projection pass
+int zgrad_tile(int L, int M, int elem_bytes);  // built-in tile of launch_zgrad
 
 // Fused CG front on the potentials (deferred xi update, direction update,
 // p = D pi, contraction, p.Kp, N2 real-to-complex pass); h: grid spacings;

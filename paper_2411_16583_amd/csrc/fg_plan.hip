@@ -65,6 +65,18 @@ int column_tile_cpt(int L, int M, int elem_bytes, int cpt) {
   return B;
 }
 
+// Built-in tile of the potential-form N0 pass: the largest power of two
+// dividing M whose workgroup (two columns per thread in single precision)
+// and LDS fit.
+int zgrad_tile(int L, int M, int elem_bytes) {
+  const int T = zline_threads(L);
+  const int cpt = (elem_bytes == 8) ? 2 : 1;
+  int B = 1;
+  while (M % (2 * B) == 0 && T * 2 * B / cpt <= 256 && (long)L * 2 * B * elem_bytes + 5L * L * elem_bytes / 2 <= 65536)
+    B *= 2;
+  return B;
+}
+
 int zline_threads(int L) {
   if (L == 256) return Line3<256>::T;
   if (L == 128) return Line3<128>::T;
@@ -86,7 +98,8 @@ bool tile_valid(bool zproj, int L, int M, int elem_bytes, int tile) {
   const int T = zproj ? zline_threads(L) : line_threads(L);
   // single-precision N1 pass with column pairs: tile / 2 column groups
   if (pairs && tile % 2 != 0) return false;
-  const int cpt = pairs ? 2 : 1;
+  // the single-precision N0 pass takes two columns per thread (even tiles)
+  const int cpt = (pairs || (zproj && elem_bytes == 8 && tile % 2 == 0)) ? 2 : 1;
   if (T * tile / cpt > 256) return false;
   // exchange buffer, plus the twiddles and kz tables of the projection pass
   // (the potential form of the projection stages one more kz table)
@@ -2005,7 +2018,7 @@ fg_status fg_plan_get_tiles(const fg_plan* P, int tiles[4]) {
     const TilePass tp = tile_pass(w);
     const int L = tile_len(P, w);
     const int T = tp.zproj ? fg::zline_threads(L) : fg::line_threads(L);
-    const int built_in = tp.zproj ? (fg::column_tile_t(T, L, P->M, tp.elem) | fg::kTileKyMajor)
+    const int built_in = tp.zproj ? (fg::zgrad_tile(L, P->M, tp.elem) | fg::kTileKyMajor)
                                   : fg::column_tile_t(T, L, P->M, tp.elem);
     tiles[w] = P->tiles[w] > 0 ? P->tiles[w] : built_in;
   }

@@ -261,12 +261,13 @@ k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip
 // Line transform of k_fft_axis_rows: three stages in double precision (two
 // 16-element lines per thread would not fit the registers), two stages in
 // single precision (measured faster at N1 = 256).
-template <typename R, int L> using RowLine = typename std::conditional<sizeof(R) == 8, ZLine<L>, Line2Ops<L>>::type;
+template <typename R, int L> using RowLine = ZLine<L>;
 
-template <typename R, int L>
+template <typename R, int L, int CPT>
 __global__ void __launch_bounds__(256)
 k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride, int B, SpecTables<R> tb,
                 Skip skip, const double* __restrict__ pap_partials, int nparts, KrylovScalars* ks) {
+  static_assert(CPT == 1 || (CPT == 2 && sizeof(R) == 4), "column pairs in single precision");
   using C = cplx<R>;
   using LS = RowLine<R, L>;
   extern __shared__ char smem_raw[];
@@ -285,44 +286,93 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
   __syncthreads();
   const R* scy = tb.cy;
   const R* ssy = tb.sy;
-  const int col = threadIdx.x % B;
-  const int t = threadIdx.x / B;
-  const int kx = blockIdx.x * B + col;
-  const bool dc = kx == 0;
-  const R cx = tb.cx[kx], sx = tb.sx[kx];
-  // workgroup-uniform bases of the three slots and a 32-bit element offset
-  // per thread (within one plane of one component)
+  // CPT adjacent columns per thread (single precision: two, one 16-byte
+  // access per element)
+  const int BC = B / CPT;
+  const int col0 = CPT * (int)(threadIdx.x % BC);
+  const int t = threadIdx.x / BC;
+  const int kx0 = blockIdx.x * B + col0;
+  bool dc[CPT];
+  R cx[CPT], sx[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    dc[c] = kx0 + c == 0;
+    cx[c] = tb.cx[kx0 + c];
+    sx[c] = tb.sx[kx0 + c];
+  }
+  // workgroup-uniform bases of the three slots and a 32-bit byte offset per
+  // thread (within one plane of one component)
   C* b0 = reinterpret_cast<C*>(data) + (long)blockIdx.z * zstride + (long)blockIdx.y * ystride + (long)blockIdx.x * B;
   C* b1 = b0 + cstride;
   C* b2 = b1 + cstride;
-  // byte offsets in 32 bits (one plane of one component), so that every
-  // access is a uniform base plus one 32-bit register
   const unsigned ues = (unsigned)(estride * (long)sizeof(C));
-  const unsigned ucol = (unsigned)(col * sizeof(C));
+  const unsigned ucol = (unsigned)(col0 * sizeof(C));
   auto offA = [&](int e) { return ucol + (unsigned)LS::idxA(t, e) * ues; };
   auto offB = [&](int e) { return ucol + (unsigned)LS::idxB(t, e) * ues; };
-  C v[LS::E], acc[LS::E];
+  auto load = [&](C* b, unsigned off, C (&x)[CPT]) {
+    if constexpr (CPT == 2) {
+      const float4 w = at_bytes(reinterpret_cast<float4*>(b), off);
+      x[0] = mk<C>(w.x, w.y);
+      x[CPT - 1] = mk<C>(w.z, w.w);
+    } else {
+      x[0] = at_bytes(b, off);
+    }
+  };
+  auto store = [&](C* b, unsigned off, const C (&x)[CPT]) {
+    if constexpr (CPT == 2)
+      at_bytes(reinterpret_cast<float4*>(b), off) = make_float4(x[0].x, x[0].y, x[CPT - 1].x, x[CPT - 1].y);
+    else
+      at_bytes(b, off) = x[0];
+  };
+  C v[CPT][LS::E], acc[CPT][LS::E];
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) v[e] = at_bytes(b0, offA(e));
+  for (int e = 0; e < LS::E; ++e) {
+    C x[CPT], y[CPT];
+    load(b0, offA(e), x);
+    load(b1, offA(e), y);
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) acc[e] = at_bytes(b1, offA(e));
-  LS::template fwd<false>(v, lds + col, B, t, stw);
+    for (int c = 0; c < CPT; ++c) {
+      v[c][e] = x[c];
+      acc[c][e] = y[c];
+    }
+  }
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) at_bytes(b0, offB(e)) = dc ? v[e] : cscale(v[e], scy[LS::idxB(t, e)] * cx);
+  for (int c = 0; c < CPT; ++c) LS::template fwd<false>(v[c], lds + col0 + c, B, t, stw);
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) v[e] = at_bytes(b2, offA(e));
-  LS::template fwd<false>(acc, lds + col, B, t, stw);
-  LS::template fwd<false>(v, lds + col, B, t, stw);
+  for (int e = 0; e < LS::E; ++e) {
+    const R cyk = scy[LS::idxB(t, e)];
+    C x[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) x[c] = dc[c] ? v[c][e] : cscale(v[c][e], cyk * cx[c]);
+    store(b0, offB(e), x);
+  }
+#pragma unroll
+  for (int e = 0; e < LS::E; ++e) {
+    C x[CPT];
+    load(b2, offA(e), x);
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) v[c][e] = x[c];
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    LS::template fwd<false>(acc[c], lds + col0 + c, B, t, stw);
+    LS::template fwd<false>(v[c], lds + col0 + c, B, t, stw);
+  }
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
     const int ky = LS::idxB(t, e);
-    if (dc) {
-      at_bytes(b2, offB(e)) = v[e];
-    } else {
-      const R f1 = ssy[ky] * cx, f2 = scy[ky] * sx;
-      acc[e] = mk<C>(acc[e].x * f1 + v[e].x * f2, acc[e].y * f1 + v[e].y * f2);
+    C x[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (dc[c]) {
+        at_bytes(b2, offB(e) + (unsigned)(c * sizeof(C))) = v[c][e];
+        x[c] = acc[c][e];
+      } else {
+        const R f1 = ssy[ky] * cx[c], f2 = scy[ky] * sx[c];
+        x[c] = mk<C>(acc[c][e].x * f1 + v[c][e].x * f2, acc[c][e].y * f1 + v[c][e].y * f2);
+      }
     }
-    at_bytes(b1, offB(e)) = acc[e];
+    store(b1, offB(e), x);
   }
 }
 

@@ -90,11 +90,17 @@ template <typename R>
 void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
                       int nitems, int tile, const double* pap_partials, int nparts, KrylovScalars* ks) {
   tile &= ~kTileColumnPairs;
-  const int T = sizeof(R) == 8 ? zline_threads(N1) : line_threads(N1);  // threads of RowLine<R, N1>
-  int B = tile > 0 ? tile : column_tile_t(T, N1, M, (int)sizeof(cplx<R>));
-  // the N1 tile is shared with launch_axis, whose lines take fewer threads:
-  // halve it until the workgroup and its LDS (exchange buffer + twiddles) fit
-  while (B > 1 && (T * B > 256 || (size_t)N1 * (B + 1) * sizeof(cplx<R>) > 65536)) B /= 2;
+  const int T = zline_threads(N1);  // threads per line of RowLine<R, N1>
+  // single precision: two adjacent columns per thread
+  constexpr int CPT = (sizeof(R) == 4) ? 2 : 1;
+  int B = tile > 0 ? tile : zgrad_tile(N1, M, (int)sizeof(cplx<R>));
+  int cpt = (B % CPT == 0) ? CPT : 1;
+  // the N1 tile is shared with launch_axis: halve it until the workgroup and
+  // its LDS (exchange buffer + twiddles) fit
+  while (B > 1 && (T * B / cpt > 256 || (size_t)N1 * (B + 1) * sizeof(cplx<R>) > 65536)) {
+    B /= 2;
+    cpt = (B % CPT == 0) ? CPT : 1;
+  }
   const size_t shm = (size_t)N1 * (B + 1) * sizeof(cplx<R>);
   const long plane = (long)N1 * M;
   // planes y = i0, z = row (3 per item); components of a row n0 planes apart
@@ -103,8 +109,12 @@ void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, c
   switch (N1) {
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \
-    hipLaunchKernelGGL((k_fft_axis_rows<R, L_>), grid, dim3(T * B), shm, s, data, (long)M, plane,       \
-                       3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks);        \
+    if (cpt == 2)                                                                                      \
+      hipLaunchKernelGGL((k_fft_axis_rows<R, L_, CPT>), grid, dim3(T * B / 2), shm, s, data, (long)M, plane, \
+                         3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks);      \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_fft_axis_rows<R, L_, 1>), grid, dim3(T * B), shm, s, data, (long)M, plane,  \
+                         3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks);      \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE

@@ -11,7 +11,10 @@
 // and transformed there.
 //
 // A workgroup owns LB grid lines (i0, i1) and all 9 components of them:
-// phase A is one thread per 2 or 4 voxels (coalesced along N2), phase B is the
+// phase A is one thread per 2 or 4 voxels (coalesced along N2; in single
+// precision, where a line is a whole number of waves, only full waves take
+// part and the stencil's lower corner comes from the neighbouring lane),
+// phase B is the
 // two-stage line FFT of the 9 LB complex lines with T threads each
 // (9 LB T = 144 threads).  The stencil needs pi at the corners of the lines
 // (i0 - 1, i1), (i0, i1 - 1), (i0 - 1, i1 - 1) too; it recomputes them from
@@ -94,9 +97,18 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   constexpr int W = front_width<R, M>();
   using PV = typename FrontPack<R, W>::type;
   constexpr int GPL = 2 * M / W;  // voxel groups per line
+  // single precision, lines of whole waves: the stencil's corner x - 1 comes
+  // from the lane below, and phase A runs on the full waves only (lane k =
+  // group k mod 64).  (In double precision this raised the kernel from 148
+  // to 184 VGPRs and made it slower.)
+  constexpr bool kLanes = sizeof(R) == 4 && GPL % 64 == 0;
+  constexpr int PA = kLanes ? (FS::THREADS / 64) * 64 : FS::THREADS;
+  static_assert(PA > 0, "phase A threads");
+  const bool edge = kLanes && GPL > 64 && (tid & 63) == 0;
   const long Nw = N / W;
   const PV* sv = reinterpret_cast<const PV*>(st);
-  for (int v = tid; v < LB * GPL; v += FS::THREADS) {
+#pragma unroll 1
+  for (int v = tid; tid < PA && v < LB * GPL; v += PA) {
     const int l = v / GPL;
     const int n = v % GPL;  // voxels W n .. W n + W - 1 of line l
     if (line0 + l >= nlines) continue;
@@ -106,10 +118,16 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       R u[2][2][W + 1];
-      load_corners<R, W>(rho + c * N, sl, u);
+      if constexpr (kLanes)
+        load_corners_lanes<R, W>(rho + c * N, sl, u, edge);
+      else
+        load_corners<R, W>(rho + c * N, sl, u);
       if (!first) {
         R uo[2][2][W + 1];
-        load_corners<R, W>(po + c * N, sl, uo);
+        if constexpr (kLanes)
+          load_corners_lanes<R, W>(po + c * N, sl, uo, edge);
+        else
+          load_corners<R, W>(po + c * N, sl, uo);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll

@@ -30,7 +30,7 @@ namespace fg {
 // G = n2 / W; partials per item = blocks per item.  Accesses are a per-item
 // base plus a 32-bit byte offset (the host checks that an item's 9 N values
 // fit in 4 GiB).
-template <typename T, int W>
+template <typename T, int W, bool LANES>
 __global__ void __launch_bounds__(256)
 k_cg_rupd_march(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const KrylovScalars* __restrict__ ks,
                 const int* __restrict__ idle, double* __restrict__ partials, int n0, int n1, int n2, int K, T q0,
@@ -69,7 +69,10 @@ k_cg_rupd_march(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const K
                             ((unsigned)i1m * (unsigned)n2 + (unsigned)x) * E};
     const unsigned dxm = (unsigned)(xm - x) * E;  // x - 1 (or n2 - 1) relative to x, mod 2^32
     const int i0s = seg * K, i0e = min(n0, i0s + K);
+    // LANES (a line is one wave: G = 64, lane k = group k): the corner x - 1
+    // is the last value of the lane below instead of a load.
     // new rho at the corners x - 1 .. x + W - 1 of lines i1 - b of plane i0
+    constexpr int q0c = LANES ? 1 : 0;  // first corner loaded from memory
     auto corners = [&](int i0, T (&u)[2][W + 1]) {
       const unsigned pb = (unsigned)i0 * plane_b;
       T d[2][W + 1];
@@ -77,12 +80,12 @@ k_cg_rupd_march(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const K
       for (int b = 0; b < 2; ++b) {
         const unsigned o = pb + lo[b];
         const V w = at_bytes(reinterpret_cast<const V*>(ro), o);
-        u[b][0] = at_bytes(ro, o + dxm);
+        if constexpr (!LANES) u[b][0] = at_bytes(ro, o + dxm);
 #pragma unroll
         for (int q = 0; q < W; ++q) u[b][q + 1] = reinterpret_cast<const T*>(&w)[q];
         if (mode == 0) {
           const V wu = at_bytes(reinterpret_cast<const V*>(U), o);
-          d[b][0] = at_bytes(U, o + dxm);
+          if constexpr (!LANES) d[b][0] = at_bytes(U, o + dxm);
 #pragma unroll
           for (int q = 0; q < W; ++q) d[b][q + 1] = reinterpret_cast<const T*>(&wu)[q];
         }
@@ -91,7 +94,11 @@ k_cg_rupd_march(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const K
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-          for (int q = 0; q <= W; ++q) u[b][q] -= alpha * d[b][q];
+          for (int q = q0c; q <= W; ++q) u[b][q] -= alpha * d[b][q];
+      }
+      if constexpr (LANES) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) u[b][0] = lane_below(u[b][W]);
       }
     };
     T prev[2][W + 1];
@@ -242,15 +249,28 @@ int launch_cg_rupd(const T* U, long ucs, T* rbuf, const KrylovScalars* ks, const
     throw std::invalid_argument("grid too large for 32-bit offsets in the residual update");
   const int K = kRupdPlanes;
   const long nseg = (n0 + K - 1) / K;
-  if (stencil_width(n2, (int)sizeof(T)) == 4) {
-    const long bx = ((long)n1 * (n2 / 4) + 255) / 256;
-    hipLaunchKernelGGL((k_cg_rupd_march<T, (sizeof(T) == 4 ? 4 : 2)>), dim3((unsigned)(3 * bx * nseg * nitems)),
-                       dim3(256), 0, s, U, ucs, rbuf, ks, idle, partials, n0, n1, n2, K, q0, q1, q2, mode);
-    return (int)(3 * bx * nseg);
+  const int W = stencil_width(n2, (int)sizeof(T));
+  const long bx = ((long)n1 * (n2 / W) + 255) / 256;
+  const dim3 grid((unsigned)(3 * bx * nseg * nitems));
+  // a line of n2 / W = 64 groups is exactly one wave of a workgroup
+  const bool lanes = n2 / W == 64;
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, U, ucs, rbuf, ks, idle, partials, n0, n1, n2, K, q0, q1, q2,
+                       mode);
+  };
+  if constexpr (sizeof(T) == 4) {
+    if (W == 4) {
+      if (lanes)
+        go(k_cg_rupd_march<T, 4, true>);
+      else
+        go(k_cg_rupd_march<T, 4, false>);
+      return (int)(3 * bx * nseg);
+    }
   }
-  const long bx = ((long)n1 * (n2 / 2) + 255) / 256;
-  hipLaunchKernelGGL((k_cg_rupd_march<T, 2>), dim3((unsigned)(3 * bx * nseg * nitems)), dim3(256), 0, s, U, ucs, rbuf,
-                     ks, idle, partials, n0, n1, n2, K, q0, q1, q2, mode);
+  if (lanes)
+    go(k_cg_rupd_march<T, 2, true>);
+  else
+    go(k_cg_rupd_march<T, 2, false>);
   return (int)(3 * bx * nseg);
 }
 

@@ -57,6 +57,45 @@ __device__ __forceinline__ void load_corners(const T* __restrict__ f, const Sten
     }
 }
 
+// The value v held by the lane one below (lane 0 takes lane 63's): a
+// wave-wide DPP rotation by one lane, no memory access.
+__device__ __forceinline__ float lane_below(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_below(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x13C, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x13C, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// As load_corners, with the corner x - 1 taken from the lane below rather
+// than from memory.  Lane k of the wave must hold voxel group k of 64
+// consecutive groups of one line (so the lane below holds x - W .. x - 1,
+// and lane 0 of a wave that covers a whole line holds the periodic
+// neighbour in lane 63); `edge` lanes (lane 0 when a line spans several
+// waves) load their corner.  Every lane of the wave must be active.
+template <typename T, int W>
+__device__ __forceinline__ void load_corners_lanes(const T* __restrict__ f, const StencilLines& s,
+                                                   T (&u)[2][2][W + 1], bool edge) {
+  using V = typename VecW<T, W>::type;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const V w = *reinterpret_cast<const V*>(f + s.row[a][b] + s.x);
+#pragma unroll
+      for (int q = 0; q < W; ++q) u[a][b][q + 1] = reinterpret_cast<const T*>(&w)[q];
+      u[a][b][0] = lane_below(u[a][b][W]);
+    }
+  if (edge) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) u[a][b][0] = f[s.row[a][b] + s.xm];
+  }
+}
+
 // Z[j][v] = (D_j u)[x + v] with q_j = 1 / (4 h_j).
 template <typename T, int W>
 __device__ __forceinline__ void corner_grad(const T (&u)[2][2][W + 1], T q0, T q1, T q2, T (&Z)[3][W]) {

@@ -252,6 +252,32 @@ def test_newton_small_odd_grids_match_oracle(shape, precision, tol):
     assert e <= tol
 
 
+@pytest.mark.parametrize("shape", [(4, 6, 256), (6, 4, 128), (4, 4, 512)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_newton_long_lines_match_oracle(shape, precision, tol):
+    """Newton-CG on grids whose lines along N2 are one or two waves of
+    stencil groups (N2 = 256 in single precision, 128 in double precision:
+    the stencil's lower corner is taken from the neighbouring lane; N2 = 512:
+    lines spanning two waves), random two-phase material, mixed macro load,
+    against the oracle's discrete solution."""
+    work = synth.homogeneous_workload(shape)
+    rng = np.random.default_rng(71207 + shape[2])
+    phase = rng.random(shape) < 0.3
+    work["E"] = np.where(phase, 100e9, 10e9)
+    work["nu"] = np.where(phase, 0.25, 0.3)
+    Fbar = np.eye(3)
+    Fbar[0, 0] += 0.004
+    Fbar[2, 1] += 0.003
+    work["loads"] = [Fbar]
+    tn = 1e-12 if precision == "fp64" else 1e-10
+    gpu = run_increments_gpu(work, precision, tol_newton=tn, tol_lin=1e-12)
+    F, _ = mechanics.solve_increments(work, tol_newton=1e-12, tol_lin=1e-12)
+    Fg, sg = gpu[-1]
+    e = rel(Fg, F, F - mechanics.uniform_field(Fbar, shape))
+    print(f"{shape} {precision}: newton {sg['newton_iters']} cg {sg['lin_history']} rel {e:.2e}", flush=True)
+    assert e <= tol
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_homogeneous_cell_exact_without_iterations(precision):
     """Uniform material, c and d (any Fbar): F = Fbar exactly and no Newton

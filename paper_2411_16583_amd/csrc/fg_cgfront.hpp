@@ -54,8 +54,14 @@ template <int M> struct FrontShape {
   static constexpr int T = Line<M>::T;
   static constexpr int LB = (16 / T) > 0 ? (16 / T) : 1;  // lines per workgroup
   static constexpr int THREADS = 9 * LB * T;
-  static constexpr int PADC = (M >= 16) ? 1 : 0;          // complex pad per line buffer
-  static constexpr int LSTRIDE = M + PADC;                // complex elements per line buffer
+  // Complex pad per line buffer.  A wave's LDS access is served 32 lanes
+  // (8-byte elements) or 16 lanes (16-byte elements) at a time, i.e. 32/T or
+  // 16/T lines of T consecutive elements; with a line stride of T (mod 32)
+  // they fall on distinct banks.  (A pad of one element puts line l + 1's
+  // element t on the banks of line l's element t + 1.)
+  static constexpr bool kBankPad = M % 32 == 0 && (T == 4 || T == 8 || T == 16);
+  static constexpr int PADC = kBankPad ? T : ((M >= 16) ? 1 : 0);
+  static constexpr int LSTRIDE = M + PADC;  // complex elements per line buffer
 };
 
 template <typename R, int M>

@@ -29,6 +29,27 @@ template <> struct Line3Shape<96> {
   static constexpr int R1 = 4, R2 = 4, R3 = 6, T = 8;
 };
 
+// CPT adjacent columns of one LDS row position in one access (two
+// single-precision complex values: one 16-byte access, the same bank pattern
+// as one double-precision column).
+template <int CPT, typename C> __device__ __forceinline__ void lds_put(C* p, const C (&x)[CPT]) {
+  if constexpr (CPT == 2) {
+    static_assert(sizeof(C) == 8, "column pairs in single precision");
+    *reinterpret_cast<float4*>(p) = make_float4(x[0].x, x[0].y, x[CPT - 1].x, x[CPT - 1].y);
+  } else {
+    *p = x[0];
+  }
+}
+template <int CPT, typename C> __device__ __forceinline__ void lds_get(const C* p, C (&x)[CPT]) {
+  if constexpr (CPT == 2) {
+    const float4 w = *reinterpret_cast<const float4*>(p);
+    x[0] = mk<C>(w.x, w.y);
+    x[CPT - 1] = mk<C>(w.z, w.w);
+  } else {
+    x[0] = *p;
+  }
+}
+
 template <int L> struct Line3 {
   static constexpr int R1 = Line3Shape<L>::R1, R2 = Line3Shape<L>::R2, R3 = Line3Shape<L>::R3;
   static constexpr int T = Line3Shape<L>::T;
@@ -134,6 +155,154 @@ template <int L> struct Line3 {
     }
     __syncthreads();
   }
+
+  // fwd and inv of CPT adjacent columns together (lds points at the first
+  // column, which is CPT-aligned; one CPT-wide LDS access per position).
+  template <bool INV, int CPT, typename C>
+  __device__ __forceinline__ static void fwd_cols(C (&v)[CPT][E], C* lds, int ls, int t, const C* tw) {
+    if constexpr (CPT == 1) {
+      fwd<INV>(v[0], lds, ls, t, tw);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U1; ++u) {
+        const int b = t + T * u;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          Dft<R1, 1, INV, C>::run(v[c] + u * R1);
+#pragma unroll
+          for (int k1 = 1; k1 < R1; ++k1) v[c][u * R1 + k1] = twiddle_tab<INV>(v[c][u * R1 + k1], tw, (b * k1) % L);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+          C x[CPT];
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) x[c] = v[c][u * R1 + k1];
+          lds_put<CPT>(lds + pos1(b, k1) * ls, x);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < U2; ++w) {
+        const int g = t + T * w;
+        const int k1 = g % R1, b2 = g / R1;
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+          C x[CPT];
+          lds_get<CPT>(lds + pos1(b2 + R3 * n2, k1) * ls, x);
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) v[c][w * R2 + n2] = x[c];
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          Dft<R2, 1, INV, C>::run(v[c] + w * R2);
+#pragma unroll
+          for (int k2 = 1; k2 < R2; ++k2)
+            v[c][w * R2 + k2] = twiddle_tab<INV>(v[c][w * R2 + k2], tw, (R1 * b2 * k2) % L);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < U2; ++w) {
+        const int g = t + T * w;
+        const int k1 = g % R1, b2 = g / R1;
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+          C x[CPT];
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) x[c] = v[c][w * R2 + k2];
+          lds_put<CPT>(lds + pos2(k1, b2, k2) * ls, x);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int z = 0; z < U3; ++z) {
+        const int g = t + T * z;
+        const int k1 = g % R1, k2 = g / R1;
+#pragma unroll
+        for (int b2 = 0; b2 < R3; ++b2) {
+          C x[CPT];
+          lds_get<CPT>(lds + pos2(k1, b2, k2) * ls, x);
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) v[c][z * R3 + b2] = x[c];
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) Dft<R3, 1, INV, C>::run(v[c] + z * R3);
+      }
+      __syncthreads();
+    }
+  }
+
+  template <int CPT, typename C>
+  __device__ __forceinline__ static void inv_cols(C (&v)[CPT][E], C* lds, int ls, int t, const C* tw) {
+    if constexpr (CPT == 1) {
+      inv(v[0], lds, ls, t, tw);
+    } else {
+#pragma unroll
+      for (int z = 0; z < U3; ++z) {
+        const int g = t + T * z;
+        const int k1 = g % R1, k2 = g / R1;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) Dft<R3, 1, true, C>::run(v[c] + z * R3);  // over k3 -> b2
+#pragma unroll
+        for (int b2 = 0; b2 < R3; ++b2) {
+          C x[CPT];
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) {
+            x[c] = v[c][z * R3 + b2];
+            if (b2 != 0 && k2 != 0) x[c] = twiddle_tab<true>(x[c], tw, (R1 * b2 * k2) % L);
+          }
+          lds_put<CPT>(lds + pos2(k1, b2, k2) * ls, x);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < U2; ++w) {
+        const int g = t + T * w;
+        const int k1 = g % R1, b2 = g / R1;
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+          C x[CPT];
+          lds_get<CPT>(lds + pos2(k1, b2, k2) * ls, x);
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) v[c][w * R2 + k2] = x[c];
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) Dft<R2, 1, true, C>::run(v[c] + w * R2);  // over k2 -> n2
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < U2; ++w) {
+        const int g = t + T * w;
+        const int k1 = g % R1, b2 = g / R1;
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+          const int b = b2 + R3 * n2;
+          C x[CPT];
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) {
+            x[c] = v[c][w * R2 + n2];
+            if (k1 != 0) x[c] = twiddle_tab<true>(x[c], tw, (b * k1) % L);
+          }
+          lds_put<CPT>(lds + pos1(b, k1) * ls, x);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < U1; ++u) {
+        const int b = t + T * u;
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+          C x[CPT];
+          lds_get<CPT>(lds + pos1(b, k1) * ls, x);
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) v[c][u * R1 + k1] = x[c];
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) Dft<R1, 1, true, C>::run(v[c] + u * R1);  // over k1 -> n1
+      }
+      __syncthreads();
+    }
+  }
 };
 
 // The two-stage transform behind the same interface.
@@ -149,6 +318,17 @@ template <int L> struct Line2Ops {
   template <typename C>
   __device__ __forceinline__ static void inv(C (&v)[E], C* lds, int ls, int t, const C* tw) {
     line_ifft_BA<L>(v, lds, ls, t, tw);
+  }
+  // columns one after the other (one element per LDS access)
+  template <bool INV, int CPT, typename C>
+  __device__ __forceinline__ static void fwd_cols(C (&v)[CPT][E], C* lds, int ls, int t, const C* tw) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) fwd<INV>(v[c], lds + c, ls, t, tw);
+  }
+  template <int CPT, typename C>
+  __device__ __forceinline__ static void inv_cols(C (&v)[CPT][E], C* lds, int ls, int t, const C* tw) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) inv(v[c], lds + c, ls, t, tw);
   }
 };
 
@@ -172,7 +352,7 @@ __global__ void __launch_bounds__(256)
 k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor) {
   using C = cplx<R>;
   using LS = ZLine<L>;
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C* stw = lds + L * B;
   R* scz = reinterpret_cast<R*>(stw + L);
@@ -258,9 +438,9 @@ k_fft_z_proj(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip
 // + e * estride + kx.  The line transform's twiddles are staged in LDS.
 // The loads of the next component are issued before the current one is
 // transformed (its registers are free by then).
-// Line transform of k_fft_axis_rows: three stages in double precision (two
-// 16-element lines per thread would not fit the registers), two stages in
-// single precision (measured faster at N1 = 256).
+// Line transform of k_fft_axis_rows: the three-stage line where there is one
+// (N1 = 96, 128, 256: two lines of 8 complex per thread); single precision
+// takes two adjacent columns per thread, exchanged through LDS together.
 template <typename R, int L> using RowLine = ZLine<L>;
 
 template <typename R, int L, int CPT>
@@ -270,7 +450,7 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
   static_assert(CPT == 1 || (CPT == 2 && sizeof(R) == 4), "column pairs in single precision");
   using C = cplx<R>;
   using LS = RowLine<R, L>;
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   __shared__ double red[16];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C* stw = lds + L * B;
@@ -336,8 +516,7 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
       acc[c][e] = y[c];
     }
   }
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) LS::template fwd<false>(v[c], lds + col0 + c, B, t, stw);
+  LS::template fwd_cols<false, CPT>(v, lds + col0, B, t, stw);
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
     const R cyk = scy[LS::idxB(t, e)];
@@ -353,11 +532,8 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
 #pragma unroll
     for (int c = 0; c < CPT; ++c) v[c][e] = x[c];
   }
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    LS::template fwd<false>(acc[c], lds + col0 + c, B, t, stw);
-    LS::template fwd<false>(v[c], lds + col0 + c, B, t, stw);
-  }
+  LS::template fwd_cols<false, CPT>(acc, lds + col0, B, t, stw);
+  LS::template fwd_cols<false, CPT>(v, lds + col0, B, t, stw);
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
     const int ky = LS::idxB(t, e);
@@ -403,7 +579,7 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   static_assert(CPT == 1 || (CPT == 2 && sizeof(R) == 4), "column pairs in single precision");
   using C = cplx<R>;
   using LS = ZLine<L>;
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C* stw = lds + L * B;
   R* scz = reinterpret_cast<R*>(stw + L);
@@ -450,6 +626,8 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
     for (int e = 0; e < LS::E; ++e) acc[0][e] = base[ucomp + (unsigned)col0 + (unsigned)LS::idxA(t, e) * uplane];
   }
   const R cy = tb.cy[ky], sy = tb.sy[ky];
+  LS::template fwd_cols<false, CPT>(v, lds + col0, B, t, stw);
+  LS::template fwd_cols<false, CPT>(acc, lds + col0, B, t, stw);
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int kx = kx0 + c;
@@ -457,8 +635,6 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
     const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
     // -i e^{i (qy + qx) / 2}; the kz factor is applied per element
     const C eyx = mul_mi(cmul(mk<C>(cy, tb.sny[ky]), mk<C>(cx, tb.snx[kx])));
-    LS::template fwd<false>(v[c], lds + col0 + c, B, t, stw);
-    LS::template fwd<false>(acc[c], lds + col0 + c, B, t, stw);
 #pragma unroll
     for (int e = 0; e < LS::E; ++e) {
       const int kz = LS::idxB(t, e);
@@ -469,8 +645,8 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
       const C w = mk<C>((v[c][e].x * sz + acc[c][e].x * cz) * f, (v[c][e].y * sz + acc[c][e].y * cz) * f);
       acc[c][e] = cmul(w, cmul(mk<C>(cz, snz[kz]), eyx));
     }
-    LS::inv(acc[c], lds + col0 + c, B, t, stw);
   }
+  LS::template inv_cols<CPT>(acc, lds + col0, B, t, stw);
   // the kx = 0 column is k_fft_z_dc's
   if constexpr (CPT == 2) {
 #pragma unroll

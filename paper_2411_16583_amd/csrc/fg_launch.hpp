@@ -26,7 +26,7 @@ int zgrad_tile(int L, int M, int elem_bytes);  // built-in tile of launch_zgrad
 template <typename R>
 int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st, const KrylovScalars* ks,
                     double* partials, long N, int n0, int n1, const double h[3], const SpecTables<R>& tb,
-                    hipStream_t s, int nitems = 1);
+                    hipStream_t s, int nitems = 1, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 template <typename R>
 void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const Skip& skip,

@@ -321,11 +321,17 @@ template <typename R> void host_tables(const fg_plan* P, std::vector<char>& blob
 }
 
 // Event pair around one launch of kernel class `pass` (no-op unless on).
+// Event pair around one launch of a kernel class (when that class is being
+// timed).  With `in_launch` the scope only hands out the pair (start, stop)
+// for a launch that records them itself (hipExtLaunchKernelGGL: the kernel's
+// own start and end, no marker packets between kernels); otherwise the
+// events are recorded on the stream around the scope.
 struct ProfScope {
   fg_plan* P;
   int pass;
-  hipEvent_t stop = nullptr;
-  ProfScope(fg_plan* P_, int pass_) : P(P_), pass(pass_) {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool in_launch;
+  ProfScope(fg_plan* P_, int pass_, bool in_launch_ = false) : P(P_), pass(pass_), in_launch(in_launch_) {
     if (!P->prof_on || !(P->prof_mask >> pass & 1u)) return;
     auto& v = P->prof_ev[pass];
     size_t& u = P->prof_used[pass];
@@ -335,12 +341,13 @@ struct ProfScope {
       FG_HIP(hipEventCreate(&b));
       v.emplace_back(a, b);
     }
-    FG_HIP(hipEventRecord(v[u].first, P->stream));
+    start = v[u].first;
     stop = v[u].second;
     ++u;
+    if (!in_launch) FG_HIP(hipEventRecord(start, P->stream));
   }
   ~ProfScope() {
-    if (stop) (void)hipEventRecord(stop, P->stream);
+    if (stop && !in_launch) (void)hipEventRecord(stop, P->stream);
   }
 };
 
@@ -556,9 +563,9 @@ void cg_iteration(fg_plan* P) {
   const Skip skip = Skip::done(ks);
   int nbf;
   {
-    ProfScope ps(P, FG_PASS_FRONT);
+    ProfScope ps(P, FG_PASS_FRONT, true);
     nbf = launch_cg_front<T>(P->M, S, (T*)P->p, (T*)P->x, (const T*)P->r, (const T*)P->st, ks, P->part, P->N, P->n0,
-                             P->n1, P->h, tb, P->stream, nit);
+                             P->n1, P->h, tb, P->stream, nit, ps.start, ps.stop);
   }
   {
     // alpha = r.r / p.Ap is formed by the row pass (one workgroup per item)

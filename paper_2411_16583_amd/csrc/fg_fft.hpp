@@ -530,7 +530,8 @@ template <int L, int OP> constexpr int z_dc_lds() { return 2 * L + ((OP == 1) ? 
 // least 2 T threads (the others take part in the barriers only).
 template <typename R, int L, int OP>
 __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0,
-                                          double a1, int ky0, int row, cplx<R>* xbuf, cplx<R>* spec) {
+                                          double a1, int ky0, int row, cplx<R>* xbuf, cplx<R>* spec,
+                                          const cplx<R>* __restrict__ dcb) {
   using C = cplx<R>;
   using LS = Line<L>;
   constexpr int NC = (OP == 1) ? 1 : 3;    // components read per row
@@ -552,8 +553,14 @@ __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTabl
     for (int l = 0; l < NC; ++l) {
       C v[LS::E];
 #pragma unroll
-      for (int e = 0; e < LS::E; ++e)
-        v[e] = lane_ok ? base[(cin + l) * comp + LS::idxA(t, e) * plane] : mk<C>(R(0), R(0));
+      for (int e = 0; e < LS::E; ++e) {
+        if (!lane_ok)
+          v[e] = mk<C>(R(0), R(0));
+        else if (dcb)  // the compact copy of the column: contiguous along N0
+          v[e] = dcb[((long)(cin + l) * N1 + myky) * L + LS::idxA(t, e)];
+        else
+          v[e] = base[(cin + l) * comp + LS::idxA(t, e) * plane];
+      }
       if constexpr (LS::R2 == 1) {
         Dft<LS::R1, 1, false, C>::run(v);
       } else {
@@ -690,10 +697,11 @@ __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTabl
 
 template <typename R, int L, int OP>
 __global__ void __launch_bounds__(64)
-k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, Skip skip) {
+k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, Skip skip, const R* dcb) {
   __shared__ cplx<R> lds[z_dc_lds<L, OP>()];
   if (skip(blockIdx.y)) return;
-  z_dc_body<R, L, OP>(data, N1, M, tb, scale, a0, a1, (int)blockIdx.x, (int)blockIdx.y, lds, lds + 2 * L);
+  z_dc_body<R, L, OP>(data, N1, M, tb, scale, a0, a1, (int)blockIdx.x, (int)blockIdx.y, lds, lds + 2 * L,
+                      reinterpret_cast<const cplx<R>*>(dcb));
 }
 
 }  // namespace fg

@@ -446,7 +446,7 @@ template <typename R, int L> using RowLine = ZLine<L>;
 template <typename R, int L, int CPT>
 __global__ void __launch_bounds__(256)
 k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride, int B, SpecTables<R> tb,
-                Skip skip, const double* __restrict__ pap_partials, int nparts, KrylovScalars* ks) {
+                Skip skip, const double* __restrict__ pap_partials, int nparts, KrylovScalars* ks, R* dcb) {
   static_assert(CPT == 1 || (CPT == 2 && sizeof(R) == 4), "column pairs in single precision");
   using C = cplx<R>;
   using LS = RowLine<R, L>;
@@ -504,6 +504,14 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
     else
       at_bytes(b, off) = x[0];
   };
+  // the kx = 0 column also goes to dcb (when given): slot s of row
+  // blockIdx.z at ((3 blockIdx.z + s) L + ky) N0 + i0, N0 = gridDim.y,
+  // i0 = blockIdx.y (a uniform base per row and a 32-bit byte offset)
+  const bool dcl = dcb != nullptr && dc[0];
+  C* dcw = dcb ? reinterpret_cast<C*>(dcb) + (long)blockIdx.z * 3 * L * gridDim.y : nullptr;
+  const unsigned dcs = gridDim.y * (unsigned)sizeof(C);  // ky stride in bytes
+  const unsigned dci = blockIdx.y * (unsigned)sizeof(C);
+  auto dc_off = [&](int s, int ky) { return (unsigned)(s * L + ky) * dcs + dci; };
   C v[CPT][LS::E], acc[CPT][LS::E];
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
@@ -524,6 +532,7 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
 #pragma unroll
     for (int c = 0; c < CPT; ++c) x[c] = dc[c] ? v[c][e] : cscale(v[c][e], cyk * cx[c]);
     store(b0, offB(e), x);
+    if (dcl) at_bytes(dcw, dc_off(0, LS::idxB(t, e))) = v[0][e];
   }
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {
@@ -543,6 +552,10 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
       if (dc[c]) {
         at_bytes(b2, offB(e) + (unsigned)(c * sizeof(C))) = v[c][e];
         x[c] = acc[c][e];
+        if (dcl) {
+          at_bytes(dcw, dc_off(1, ky)) = acc[c][e];
+          at_bytes(dcw, dc_off(2, ky)) = v[c][e];
+        }
       } else {
         const R f1 = ssy[ky] * cx[c], f2 = scy[ky] * sx[c];
         x[c] = mk<C>(acc[c][e].x * f1 + v[c][e].x * f2, acc[c][e].y * f1 + v[c][e].y * f2);

@@ -89,7 +89,7 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 
 template <typename R>
 void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
-                      int nitems, int tile, const double* pap_partials, int nparts, KrylovScalars* ks) {
+                      int nitems, int tile, const double* pap_partials, int nparts, KrylovScalars* ks, R* dcb) {
   tile &= ~kTileColumnPairs;
   const int T = zline_threads(N1);  // threads per line of RowLine<R, N1>
   // single precision: two adjacent columns per thread
@@ -112,10 +112,10 @@ void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, c
   case L_:                                                                                             \
     if (cpt == 2)                                                                                      \
       hipLaunchKernelGGL((k_fft_axis_rows<R, L_, CPT>), grid, dim3(T * B / 2), shm, s, data, (long)M, plane, \
-                         3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks);      \
+                         3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks, dcb); \
     else                                                                                               \
       hipLaunchKernelGGL((k_fft_axis_rows<R, L_, 1>), grid, dim3(T * B), shm, s, data, (long)M, plane,  \
-                         3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks);      \
+                         3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks, dcb); \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE
@@ -141,7 +141,8 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
   case L_:                                                                                             \
     hipLaunchKernelGGL((k_fft_z_proj<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, skip, \
                        kymajor);                                                                       \
-    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 0>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, skip); \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 0>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, skip,     \
+                       (const R*)nullptr);                                                            \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE
@@ -151,7 +152,7 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
 
 template <typename R>
 void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
-                  hipStream_t s, int nitems, int tile) {
+                  hipStream_t s, int nitems, int tile, const R* dcb) {
   const int T = zline_threads(N0);
   const int kymajor = (tile == 0 || (tile & kTileKyMajor)) ? 1 : 0;
   tile &= ~kTileKyMajor;
@@ -173,7 +174,7 @@ void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
     else                                                                                               \
       hipLaunchKernelGGL((k_fft_z_grad3<R, L_, 1>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, sk, \
                          kymajor);                                                                     \
-    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 2>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, sk); \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 2>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, sk, dcb); \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE
@@ -194,7 +195,8 @@ void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R s
   case L_:                                                                                            \
     hipLaunchKernelGGL((k_fft_z_scalar<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, a0, \
                        a1, skip);                                                                     \
-    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 1>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, a0, a1, skip); \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 1>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, a0, a1, skip,       \
+                       (const R*)nullptr);                                                            \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE
@@ -236,9 +238,10 @@ int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st
   template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const Skip&, \
                                hipStream_t, int);                                                       \
   template void launch_axis_rows<R>(int, R*, int, int, const SpecTables<R>&, const Skip&, hipStream_t, int, int,    \
-                                    const double*, int, KrylovScalars*);                                        \
+                                    const double*, int, KrylovScalars*, R*);                                    \
   template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
-  template void launch_zgrad<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
+  template void launch_zgrad<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int, \
+                                const R*);                                                               \
   template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const Skip&, \
                                   hipStream_t);
 

@@ -44,11 +44,13 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 // 3i, 3i + 1 written; kx = 0 column unmerged in all three slots).  tile as
 // for launch_axis (a column-pair flag is ignored).  With pap_partials (in
 // the CG), one workgroup per item also sets the item's step length from
-// the front's nparts partial sums of p.Ap (k_finalize mode 0).
+// the front's nparts partial sums of p.Ap (k_finalize mode 0).  With dcb,
+// the kx = 0 column of the three slots of every row is also written there,
+// contiguous along N0 (complex [9 nitems][N1][N0]), for launch_zgrad.
 template <typename R>
 void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
                       int nitems = 1, int tile = 0, const double* pap_partials = nullptr, int nparts = 0,
-                      KrylovScalars* ks = nullptr);
+                      KrylovScalars* ks = nullptr, R* dcb = nullptr);
 // N0 pass fused with the projection, for nitems 9-component fields (3 rows
 // each).
 template <typename R>
@@ -56,10 +58,11 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
                   hipStream_t s, int nitems = 1, int tile = 0);
 // N0 pass fused with the projection in the potential form, on the output of
 // launch_axis_rows (the potential U_i written to slot 3i of each item), and
-// its kx = 0 companion.
+// its kx = 0 companion (reading the kx = 0 column from dcb when given: the
+// buffer launch_axis_rows filled in the same pass).
 template <typename R>
 void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
-                  hipStream_t s, int nitems = 1, int tile = 0);
+                  hipStream_t s, int nitems = 1, int tile = 0, const R* dcb = nullptr);
 // Flag on a projection-pass tile: workgroups ordered ky fastest.
 constexpr int kTileKyMajor = 1 << 16;
 // Flag on an N1-pass tile in single precision: two adjacent columns per

@@ -177,6 +177,7 @@ struct fg_plan {
   void* r = nullptr;             // 9N T
   void* p = nullptr;             // 9N T
   void* st = nullptr;            // 12N T tangent state
+  void* dcb = nullptr;           // kx = 0 column of the row slots, contiguous along N0 (9 n0 n1 complex per item)
   double* sc = nullptr;          // scalar solver area, 16N doubles
   size_t part_n = 0;
 
@@ -254,6 +255,7 @@ size_t layout(fg_plan* P, char* base) {
   P->r = carve<char>(base, off, 9 * NT * tb);
   P->p = carve<char>(base, off, 9 * NT * tb);
   P->st = carve<char>(base, off, 12 * NT * tb);
+  P->dcb = carve<char>(base, off, (size_t)9 * n0 * n1 * P->nitems * sizeof(cplx<double>));
   // scalar solvers (phase field, Fick) only on single plans; batches keep
   // just the zero fields standing in for c and d
   P->sc = carve<double>(base, off, P->nitems == 1 ? 16 * N : NT);
@@ -570,11 +572,13 @@ void cg_iteration(fg_plan* P) {
   {
     // alpha = r.r / p.Ap is formed by the row pass (one workgroup per item)
     ProfScope ps(P, FG_PASS_AXIS);
-    launch_axis_rows<T>(P->n1, S, P->n0, P->M, tb, skip, P->stream, nit, tile_axis<T>(P), P->part, nbf / nit, ks);
+    launch_axis_rows<T>(P->n1, S, P->n0, P->M, tb, skip, P->stream, nit, tile_axis<T>(P), P->part, nbf / nit, ks,
+                        (T*)P->dcb);
   }
   {
     ProfScope ps(P, FG_PASS_ZPROJ);
-    launch_zgrad<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip, P->stream, nit, tile_zproj<T>(P));
+    launch_zgrad<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip, P->stream, nit, tile_zproj<T>(P),
+                    (const T*)P->dcb);
   }
   inv_potential<T>(P, S, skip);
   int nbg;
@@ -603,12 +607,13 @@ void potential64(fg_plan* P, double* field, const Skip& skip) {
   }
   {
     ProfScope ps(P, FG_PASS_AXIS);
-    launch_axis_rows<double>(P->n1, field, P->n0, P->M, tb, skip, P->stream, P->nitems, tile_axis<double>(P));
+    launch_axis_rows<double>(P->n1, field, P->n0, P->M, tb, skip, P->stream, P->nitems, tile_axis<double>(P), nullptr,
+                             0, nullptr, (double*)P->dcb);
   }
   {
     ProfScope ps(P, FG_PASS_ZPROJ);
     launch_zgrad<double>(P->n0, field, P->n1, P->M, tb, 1.0 / (double)P->N, skip, P->stream, P->nitems,
-                         tile_zproj<double>(P));
+                         tile_zproj<double>(P), (const double*)P->dcb);
   }
   inv_potential<double>(P, field, skip);
 }
@@ -1297,9 +1302,10 @@ fg_status fg_project_grad(fg_plan* P, const double* x, double* y) {
       ProfScope ps(P, FG_PASS_R2C);
       launch_r2c<double>(P->M, x, P->S64, 9L * P->n0 * P->n1, P->t64.spec(), Skip{}, P->stream);
     }
-    launch_axis_rows<double>(P->n1, P->S64, P->n0, P->M, P->t64.spec(), Skip{}, P->stream, 1, tile_axis<double>(P));
+    launch_axis_rows<double>(P->n1, P->S64, P->n0, P->M, P->t64.spec(), Skip{}, P->stream, 1, tile_axis<double>(P),
+                             nullptr, 0, nullptr, (double*)P->dcb);
     launch_zgrad<double>(P->n0, P->S64, P->n1, P->M, P->t64.spec(), 1.0 / (double)P->N, Skip{}, P->stream, 1,
-                         tile_zproj<double>(P));
+                         tile_zproj<double>(P), (const double*)P->dcb);
     inv_potential<double>(P, P->S64, Skip{});
     launch_grad_store<double, double>((const double*)P->S64, 3 * P->N, 9 * P->N, y, 9 * P->N, nullptr, P->n0, P->n1,
                                       P->n2, 1, P->h, P->stream);

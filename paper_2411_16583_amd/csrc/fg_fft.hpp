@@ -521,25 +521,31 @@ k_fft_z_scalar(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, double 
 // OP = 1: scalar symbol (grid.y = 1);
 // OP = 2: projection to the 3-component potential (see k_fft_z_grad3), one
 //         row per workgroup (grid.y = 3 rows per item), U_i into slot 3 i.
-// LDS of z_dc_body in complex values: exchange buffer of the column pair
-// and the spectra of the components read.
-template <int L, int OP> constexpr int z_dc_lds() { return 2 * L + ((OP == 1) ? 1 : 3) * 2 * L; }
+// Components read per row by k_fft_z_dc, one wave per component (the
+// components' loads and transforms run side by side).
+template <int OP> constexpr int z_dc_groups() { return (OP == 1) ? 1 : 3; }
+// LDS of z_dc_body in complex values: an exchange buffer of the column pair
+// per wave and the spectra of the components read.
+template <int L, int OP> constexpr int z_dc_lds() { return z_dc_groups<OP>() * 2 * L * 2; }
 
 // Body of k_fft_z_dc for the column pair (ky0, -ky0) of row `row` (OP 0, 2)
-// with xbuf (2 L) and spec (NC 2 L complex) in LDS; any block size of at
-// least 2 T threads (the others take part in the barriers only).
+// with xbuf (NC 2 L) and spec (NC 2 L complex) in LDS; 64 NC threads, wave g
+// reading component g (lanes with t >= T take part in the barriers only).
 template <typename R, int L, int OP>
 __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTables<R>& tb, R scale, double a0,
                                           double a1, int ky0, int row, cplx<R>* xbuf, cplx<R>* spec,
                                           const cplx<R>* __restrict__ dcb) {
   using C = cplx<R>;
   using LS = Line<L>;
-  constexpr int NC = (OP == 1) ? 1 : 3;    // components read per row
+  constexpr int NC = z_dc_groups<OP>();    // components read per row
   constexpr int NOUT = (OP == 0) ? 3 : 1;  // components written per row
+  static_assert(2 * LS::T <= 64, "a column pair of lines per wave");
+  const int grp = threadIdx.x / 64;
   const int col = threadIdx.x % 2;
-  const int t = threadIdx.x / 2;
+  const int t = (threadIdx.x % 64) / 2;
   // idle lanes (t >= T) still take part in every barrier below
   const bool lane_ok = t < LS::T;
+  xbuf += grp * 2 * L;
   const int ky1 = (N1 - ky0) % N1;
   const int myky = col ? ky1 : ky0;
   const long plane = (long)N1 * M;
@@ -550,7 +556,8 @@ __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTabl
     // first component read and written by this workgroup's row
     const int cin = (OP == 1) ? 0 : 3 * row;
     const int cout = cin;
-    for (int l = 0; l < NC; ++l) {
+    {
+      const int l = grp;
       C v[LS::E];
 #pragma unroll
       for (int e = 0; e < LS::E; ++e) {
@@ -650,7 +657,10 @@ __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTabl
         }
       }
     }
-    for (int j = 0; j < NOUT; ++j) {
+    {
+      // OP 0: wave j writes output j; OP 1, 2: every wave forms the one
+      // output (in its own exchange buffer), wave 0 stores it
+      const int j = (NOUT == 1) ? 0 : grp;
       C v[LS::E];
 #pragma unroll
       for (int e = 0; e < LS::E; ++e) {
@@ -688,7 +698,7 @@ __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTabl
         }
         __syncthreads();
       }
-      if (store)
+      if (store && (NOUT > 1 || grp == 0))
 #pragma unroll
         for (int e = 0; e < LS::E; ++e) base[(cout + j) * comp + LS::idxA(t, e) * plane] = v[e];
     }
@@ -696,12 +706,12 @@ __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTabl
 }
 
 template <typename R, int L, int OP>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64 * z_dc_groups<OP>())
 k_fft_z_dc(R* data, int N1, int M, SpecTables<R> tb, R scale, double a0, double a1, Skip skip, const R* dcb) {
   __shared__ cplx<R> lds[z_dc_lds<L, OP>()];
   if (skip(blockIdx.y)) return;
-  z_dc_body<R, L, OP>(data, N1, M, tb, scale, a0, a1, (int)blockIdx.x, (int)blockIdx.y, lds, lds + 2 * L,
-                      reinterpret_cast<const cplx<R>*>(dcb));
+  z_dc_body<R, L, OP>(data, N1, M, tb, scale, a0, a1, (int)blockIdx.x, (int)blockIdx.y, lds,
+                      lds + z_dc_groups<OP>() * 2 * L, reinterpret_cast<const cplx<R>*>(dcb));
 }
 
 }  // namespace fg

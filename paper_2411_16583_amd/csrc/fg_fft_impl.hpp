@@ -141,8 +141,8 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
   case L_:                                                                                             \
     hipLaunchKernelGGL((k_fft_z_proj<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, skip, \
                        kymajor);                                                                       \
-    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 0>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, skip,     \
-                       (const R*)nullptr);                                                            \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 0>), gdc, dim3(64 * z_dc_groups<0>()), 0, s, data, N1, M, tb, scale, \
+                       0.0, 0.0, skip, (const R*)nullptr);                                            \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE
@@ -174,7 +174,8 @@ void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
     else                                                                                               \
       hipLaunchKernelGGL((k_fft_z_grad3<R, L_, 1>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, sk, \
                          kymajor);                                                                     \
-    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 2>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, 0.0, 0.0, sk, dcb); \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 2>), gdc, dim3(64 * z_dc_groups<2>()), 0, s, data, N1, M, tb, scale, \
+                       0.0, 0.0, sk, dcb);                                                            \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE
@@ -195,8 +196,8 @@ void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R s
   case L_:                                                                                            \
     hipLaunchKernelGGL((k_fft_z_scalar<R, L_>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, a0, \
                        a1, skip);                                                                     \
-    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 1>), gdc, dim3(64), 0, s, data, N1, M, tb, scale, a0, a1, skip,       \
-                       (const R*)nullptr);                                                            \
+    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 1>), gdc, dim3(64 * z_dc_groups<1>()), 0, s, data, N1, M, tb, scale, \
+                       a0, a1, skip, (const R*)nullptr);                                              \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE

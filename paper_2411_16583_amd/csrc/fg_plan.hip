@@ -322,7 +322,6 @@ template <typename R> void host_tables(const fg_plan* P, std::vector<char>& blob
   half(P->n2, P->M + 1, P->h[2], dev.cx, dev.sx, dev.snx);
 }
 
-// Event pair around one launch of kernel class `pass` (no-op unless on).
 // Event pair around one launch of a kernel class (when that class is being
 // timed).  With `in_launch` the scope only hands out the pair (start, stop)
 // for a launch that records them itself (hipExtLaunchKernelGGL: the kernel's

@@ -14,6 +14,7 @@
 //                                     residual norm |G*P| from U(P)).
 #pragma once
 #include "fg_fft.hpp"
+#include "fg_launch.hpp"
 #include "fg_potential.hpp"
 
 namespace fg {
@@ -243,7 +244,8 @@ constexpr int kRupdPlanes = 16;
 // returns the number of partials per item.
 template <typename T>
 int launch_cg_rupd(const T* U, long ucs, T* rbuf, const KrylovScalars* ks, const int* idle, double* partials, int n0,
-                   int n1, int n2, int nitems, const double h[3], int mode, hipStream_t s) {
+                   int n1, int n2, int nitems, const double h[3], int mode, hipStream_t s, hipEvent_t ev0 = nullptr,
+                   hipEvent_t ev1 = nullptr) {
   const T q0 = (T)(0.25 / h[0]), q1 = (T)(0.25 / h[1]), q2 = (T)(0.25 / h[2]);
   if ((double)9 * n0 * n1 * n2 * sizeof(T) >= 4294967296.0)
     throw std::invalid_argument("grid too large for 32-bit offsets in the residual update");
@@ -255,8 +257,8 @@ int launch_cg_rupd(const T* U, long ucs, T* rbuf, const KrylovScalars* ks, const
   // a line of n2 / W = 64 groups is exactly one wave of a workgroup
   const bool lanes = n2 / W == 64;
   auto go = [&](auto kernel) {
-    hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, U, ucs, rbuf, ks, idle, partials, n0, n1, n2, K, q0, q1, q2,
-                       mode);
+    launch_ev(kernel, grid, dim3(256), 0, s, ev0, ev1, U, ucs, rbuf, ks, idle, partials, n0, n1, n2, K, q0, q1, q2,
+              mode);
   };
   if constexpr (sizeof(T) == 4) {
     if (W == 4) {

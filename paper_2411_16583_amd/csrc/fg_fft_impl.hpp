@@ -33,14 +33,14 @@ void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb
 
 template <typename R>
 int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const C2REpi& epi,
-               hipStream_t s) {
+               hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   switch (M) {
 #define FG_CASE(L_)                                                                        \
   case L_: {                                                                               \
     constexpr int LPB = XBLOCK / Line<L_>::T;                                              \
     const long blocks = epi.skip.line_blocks(nlines, LPB);                                 \
-    hipLaunchKernelGGL((k_fft_x_c2r<R, L_>), dim3((unsigned)blocks), dim3(XBLOCK), 0, s, in, out, \
-                       nlines, tb, epi);                                                   \
+    launch_ev((k_fft_x_c2r<R, L_>), dim3((unsigned)blocks), dim3(XBLOCK), 0, s, ev0, ev1, in, out, \
+              nlines, tb, epi);                                                            \
     return (int)blocks;                                                                    \
   }
     FG_FOR_M(FG_CASE)
@@ -51,7 +51,7 @@ int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb,
 
 template <typename R>
 void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
-                 const cplx<R>* tw, const Skip& skip, hipStream_t s, int tile) {
+                 const cplx<R>* tw, const Skip& skip, hipStream_t s, int tile, hipEvent_t ev0, hipEvent_t ev1) {
   // single precision, on request: two columns per thread (16-byte accesses)
   int cpt = (sizeof(R) == 4 && (tile & kTileColumnPairs)) ? 2 : 1;
   tile &= ~kTileColumnPairs;
@@ -67,18 +67,18 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
   case L_:                                                                                             \
     if (cpt == 2) {                                                                                    \
       if (inv)                                                                                         \
-        hipLaunchKernelGGL((k_fft_axis<R, L_, true, CP>), grid, block, shm, s, data, estride, ystride, \
-                           zstride, B, tw, skip);                                                      \
+        launch_ev((k_fft_axis<R, L_, true, CP>), grid, block, shm, s, ev0, ev1, data, estride, ystride, \
+                  zstride, B, tw, skip);                                                               \
       else                                                                                             \
-        hipLaunchKernelGGL((k_fft_axis<R, L_, false, CP>), grid, block, shm, s, data, estride, ystride, \
-                           zstride, B, tw, skip);                                                      \
+        launch_ev((k_fft_axis<R, L_, false, CP>), grid, block, shm, s, ev0, ev1, data, estride, ystride, \
+                  zstride, B, tw, skip);                                                               \
     } else {                                                                                           \
       if (inv)                                                                                         \
-        hipLaunchKernelGGL((k_fft_axis<R, L_, true, 1>), grid, block, shm, s, data, estride, ystride,  \
-                           zstride, B, tw, skip);                                                      \
+        launch_ev((k_fft_axis<R, L_, true, 1>), grid, block, shm, s, ev0, ev1, data, estride, ystride,  \
+                  zstride, B, tw, skip);                                                               \
       else                                                                                             \
-        hipLaunchKernelGGL((k_fft_axis<R, L_, false, 1>), grid, block, shm, s, data, estride, ystride, \
-                           zstride, B, tw, skip);                                                      \
+        launch_ev((k_fft_axis<R, L_, false, 1>), grid, block, shm, s, ev0, ev1, data, estride, ystride, \
+                  zstride, B, tw, skip);                                                               \
     }                                                                                                  \
     return;
     FG_FOR_AXIS(FG_CASE)
@@ -89,7 +89,8 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 
 template <typename R>
 void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
-                      int nitems, int tile, const double* pap_partials, int nparts, KrylovScalars* ks, R* dcb) {
+                      int nitems, int tile, const double* pap_partials, int nparts, KrylovScalars* ks, R* dcb,
+                      hipEvent_t ev0, hipEvent_t ev1) {
   tile &= ~kTileColumnPairs;
   const int T = zline_threads(N1);  // threads per line of RowLine<R, N1>
   // single precision: two adjacent columns per thread
@@ -111,10 +112,10 @@ void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, c
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \
     if (cpt == 2)                                                                                      \
-      hipLaunchKernelGGL((k_fft_axis_rows<R, L_, CPT>), grid, dim3(T * B / 2), shm, s, data, (long)M, plane, \
+      launch_ev((k_fft_axis_rows<R, L_, CPT>), grid, dim3(T * B / 2), shm, s, ev0, ev1, data, (long)M, plane, \
                          3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks, dcb); \
     else                                                                                               \
-      hipLaunchKernelGGL((k_fft_axis_rows<R, L_, 1>), grid, dim3(T * B), shm, s, data, (long)M, plane,  \
+      launch_ev((k_fft_axis_rows<R, L_, 1>), grid, dim3(T * B), shm, s, ev0, ev1, data, (long)M, plane,  \
                          3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks, dcb); \
     return;
     FG_FOR_AXIS(FG_CASE)
@@ -152,7 +153,7 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
 
 template <typename R>
 void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
-                  hipStream_t s, int nitems, int tile, const R* dcb) {
+                  hipStream_t s, int nitems, int tile, const R* dcb, hipEvent_t ev0, hipEvent_t ev1) {
   const int T = zline_threads(N0);
   const int kymajor = (tile == 0 || (tile & kTileKyMajor)) ? 1 : 0;
   tile &= ~kTileKyMajor;
@@ -169,13 +170,13 @@ void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \
     if (cpt == 2)                                                                                      \
-      hipLaunchKernelGGL((k_fft_z_grad3<R, L_, CPT>), grid, dim3(T * B / 2), shm, s, data, N1, M, B, tb, scale, \
+      launch_ev((k_fft_z_grad3<R, L_, CPT>), grid, dim3(T * B / 2), shm, s, ev0, nullptr, data, N1, M, B, tb, scale, \
                          sk, kymajor);                                                                 \
     else                                                                                               \
-      hipLaunchKernelGGL((k_fft_z_grad3<R, L_, 1>), grid, dim3(T * B), shm, s, data, N1, M, B, tb, scale, sk, \
+      launch_ev((k_fft_z_grad3<R, L_, 1>), grid, dim3(T * B), shm, s, ev0, nullptr, data, N1, M, B, tb, scale, sk, \
                          kymajor);                                                                     \
-    hipLaunchKernelGGL((k_fft_z_dc<R, L_, 2>), gdc, dim3(64 * z_dc_groups<2>()), 0, s, data, N1, M, tb, scale, \
-                       0.0, 0.0, sk, dcb);                                                            \
+    launch_ev((k_fft_z_dc<R, L_, 2>), gdc, dim3(64 * z_dc_groups<2>()), 0, s, nullptr, ev1, data, N1, M, tb,   \
+              scale, 0.0, 0.0, sk, dcb);                                                              \
     return;
     FG_FOR_AXIS(FG_CASE)
 #undef FG_CASE
@@ -235,14 +236,15 @@ int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st
                                   int, const double*, const SpecTables<R>&, hipStream_t, int, hipEvent_t,   \
                                   hipEvent_t);                                                          \
   template void launch_r2c<R>(int, const R*, R*, long, const SpecTables<R>&, const Skip&, hipStream_t); \
-  template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t); \
+  template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t, hipEvent_t, \
+                             hipEvent_t);                                                           \
   template void launch_axis<R>(int, bool, R*, long, long, long, int, int, int, const cplx<R>*, const Skip&, \
-                               hipStream_t, int);                                                       \
+                               hipStream_t, int, hipEvent_t, hipEvent_t);                               \
   template void launch_axis_rows<R>(int, R*, int, int, const SpecTables<R>&, const Skip&, hipStream_t, int, int,    \
-                                    const double*, int, KrylovScalars*, R*);                                    \
+                                    const double*, int, KrylovScalars*, R*, hipEvent_t, hipEvent_t);            \
   template void launch_zproj<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int); \
   template void launch_zgrad<R>(int, R*, int, int, const SpecTables<R>&, R, const Skip&, hipStream_t, int, int, \
-                                const R*);                                                               \
+                                const R*, hipEvent_t, hipEvent_t);                                       \
   template void launch_zscalar<R>(int, R*, int, int, const SpecTables<R>&, R, double, double, const Skip&, \
                                   hipStream_t);
 

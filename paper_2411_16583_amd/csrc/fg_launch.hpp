@@ -1,11 +1,24 @@
 // Host-side launchers of the FFT passes (size dispatch).  Defined once per
 // working precision in fg_fft_f64.hip / fg_fft_f32.hip.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "fg_fft.hpp"
 
 namespace fg {
+
+// Launch that takes a timing event pair itself when one is given (the
+// kernel's own start and end, no marker packets on the stream): ev0 is
+// recorded at the start of this kernel, ev1 at its end; either may be null.
+template <typename F, typename... A>
+inline void launch_ev(F kernel, dim3 grid, dim3 block, unsigned shm, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                      A... args) {
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, s, ev0, ev1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+}
 
 bool fft_length_supported(int L);       // complex line lengths
 bool fft_axis_length_supported(int L);  // N0, N1
@@ -34,11 +47,12 @@ void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb
 // returns the number of blocks (= partials written when epi.partials != nullptr)
 template <typename R>
 int launch_c2r(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const C2REpi& epi,
-               hipStream_t s);
+               hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // tile: columns per workgroup (0: column_tile).
 template <typename R>
 void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstride, int M, int gy, int gz,
-                 const cplx<R>* tw, const Skip& skip, hipStream_t s, int tile = 0);
+                 const cplx<R>* tw, const Skip& skip, hipStream_t s, int tile = 0, hipEvent_t ev0 = nullptr,
+                 hipEvent_t ev1 = nullptr);
 // Forward N1 pass of the potential-form projection for nitems 9-component
 // fields: per row, the two terms sharing the N0 factor are merged (slots
 // 3i, 3i + 1 written; kx = 0 column unmerged in all three slots).  tile as
@@ -50,7 +64,8 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
 template <typename R>
 void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, const Skip& skip, hipStream_t s,
                       int nitems = 1, int tile = 0, const double* pap_partials = nullptr, int nparts = 0,
-                      KrylovScalars* ks = nullptr, R* dcb = nullptr);
+                      KrylovScalars* ks = nullptr, R* dcb = nullptr, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 // N0 pass fused with the projection, for nitems 9-component fields (3 rows
 // each).
 template <typename R>
@@ -62,7 +77,8 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
 // buffer launch_axis_rows filled in the same pass).
 template <typename R>
 void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
-                  hipStream_t s, int nitems = 1, int tile = 0, const R* dcb = nullptr);
+                  hipStream_t s, int nitems = 1, int tile = 0, const R* dcb = nullptr, hipEvent_t ev0 = nullptr,
+                  hipEvent_t ev1 = nullptr);
 // Flag on a projection-pass tile: workgroups ordered ky fastest.
 constexpr int kTileKyMajor = 1 << 16;
 // Flag on an N1-pass tile in single precision: two adjacent columns per

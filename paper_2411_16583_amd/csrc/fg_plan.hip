@@ -532,18 +532,18 @@ void inv_potential(fg_plan* P, R* data, const Skip& skip) {
   const SpecTables<R> tb = tabs<R>(P).spec();
   const long lines = (long)P->n0 * P->n1;
   {
-    ProfScope ps(P, FG_PASS_AXIS3);
+    ProfScope ps(P, FG_PASS_AXIS3, true);
     // planes y = i0, z = 3 item + c (components 3 apart)
     launch_axis<R>(P->n1, true, data, P->M, (long)P->n1 * P->M, 3L * P->n0 * P->n1 * P->M, P->M, P->n0,
-                   3 * P->nitems, tb.tw1, skip.unit(3L * P->n0), P->stream, tile_axis<R>(P));
+                   3 * P->nitems, tb.tw1, skip.unit(3L * P->n0), P->stream, tile_axis<R>(P), ps.start, ps.stop);
   }
-  ProfScope ps(P, FG_PASS_C2R3);
+  ProfScope ps(P, FG_PASS_C2R3, true);
   // sub-items (item, c) of N0 N1 lines, 3 N0 N1 lines apart, 3 per item
   Skip sk = skip.unit(lines);
   sk.item_stride = 3 * lines;
   sk.sub = 3;
   C2REpi epi{1.0, nullptr, true, nullptr, sk};
-  launch_c2r<R>(P->M, data, data, 3 * lines * P->nitems, tb, epi, P->stream);
+  launch_c2r<R>(P->M, data, data, 3 * lines * P->nitems, tb, epi, P->stream, ps.start, ps.stop);
 }
 
 // One CG iteration for every item of the plan (items whose solve is done
@@ -570,25 +570,26 @@ void cg_iteration(fg_plan* P) {
   }
   {
     // alpha = r.r / p.Ap is formed by the row pass (one workgroup per item)
-    ProfScope ps(P, FG_PASS_AXIS);
+    ProfScope ps(P, FG_PASS_AXIS, true);
     launch_axis_rows<T>(P->n1, S, P->n0, P->M, tb, skip, P->stream, nit, tile_axis<T>(P), P->part, nbf / nit, ks,
-                        (T*)P->dcb);
+                        (T*)P->dcb, ps.start, ps.stop);
   }
   {
-    ProfScope ps(P, FG_PASS_ZPROJ);
+    ProfScope ps(P, FG_PASS_ZPROJ, true);
     launch_zgrad<T>(P->n0, S, P->n1, P->M, tb, (T)(1.0 / (double)P->N), skip, P->stream, nit, tile_zproj<T>(P),
-                    (const T*)P->dcb);
+                    (const T*)P->dcb, ps.start, ps.stop);
   }
   inv_potential<T>(P, S, skip);
   int nbg;
   {
-    ProfScope ps(P, FG_PASS_GRAD);
+    ProfScope ps(P, FG_PASS_GRAD, true);
     nbg = launch_cg_rupd<T>((const T*)S, 3 * P->N, (T*)P->r, ks, nullptr, P->part2, P->n0, P->n1, P->n2, nit, P->h, 0,
-                            P->stream);
+                            P->stream, ps.start, ps.stop);
   }
   {
-    ProfScope ps(P, FG_PASS_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3(nit), dim3(1024), 0, P->stream, P->part2, nbg, ks, (double*)nullptr, 1, 0);
+    ProfScope ps(P, FG_PASS_FINALIZE, true);
+    launch_ev(k_finalize, dim3(nit), dim3(1024), 0, P->stream, ps.start, ps.stop, (const double*)P->part2, nbg, ks,
+              (double*)nullptr, 1, 0);
   }
   check_launch();
 }

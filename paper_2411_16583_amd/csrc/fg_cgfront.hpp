@@ -191,11 +191,14 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   C v[LS::E];
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) v[e] = my[LS::idxA(t, e)];
-  __syncthreads();  // every line fully read before the exchange writes into it
-  line_fft_AB<M, false>(v, my, 1, t, tb.twM);
+  // from here on a line's buffer is touched by its own T threads only, which
+  // sit in one wave (T divides 64): wave-level ordering suffices
+  static_assert(64 % LS::T == 0, "lines within one wave");
+  lds_sync<true>();  // every line fully read before the exchange writes into it
+  line_fft_AB<M, false, C, true>(v, my, 1, t, tb.twM);
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) my[LS::idxB(t, e)] = v[e];
-  __syncthreads();
+  lds_sync<true>();
   C* dst = reinterpret_cast<C*>(spec) + ((long)comp * nlines + line0 + l) * M;
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) {

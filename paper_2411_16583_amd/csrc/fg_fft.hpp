@@ -144,7 +144,19 @@ __device__ __forceinline__ C twiddle_tab(C a, const C* __restrict__ tw, int j) {
 // Forward (or, with INV, inverse) DFT of a line, layout A -> layout B.
 // lds: the line's exchange buffer, element i at lds[i * ls].  Ends with a
 // barrier so that the caller may reuse the buffer immediately.
-template <int L, bool INV, typename C>
+// Order LDS accesses: across the workgroup, or (WAVE) within the wave only,
+// for lines that no other wave touches.
+template <bool WAVE> __device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int L, bool INV, typename C, bool WAVE = false>
 __device__ __forceinline__ void line_fft_AB(C (&v)[Line<L>::E], C* lds, int ls, int t,
                                             const C* __restrict__ tw) {
   using LS = Line<L>;
@@ -161,7 +173,7 @@ __device__ __forceinline__ void line_fft_AB(C (&v)[Line<L>::E], C* lds, int ls, 
 #pragma unroll
       for (int k1 = 0; k1 < LS::R1; ++k1) lds[(k1 * LS::R2 + b) * ls] = v[u * LS::R1 + k1];
     }
-    __syncthreads();
+    lds_sync<WAVE>();
 #pragma unroll
     for (int w = 0; w < LS::V; ++w) {
       const int k1 = t + LS::T * w;
@@ -169,7 +181,7 @@ __device__ __forceinline__ void line_fft_AB(C (&v)[Line<L>::E], C* lds, int ls, 
       for (int n2 = 0; n2 < LS::R2; ++n2) v[w * LS::R2 + n2] = lds[(k1 * LS::R2 + n2) * ls];
       Dft<LS::R2, 1, INV, C>::run(v + w * LS::R2);
     }
-    __syncthreads();
+    lds_sync<WAVE>();
   }
 }
 

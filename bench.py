@@ -3,19 +3,25 @@ at 256^3 (double precision and the mixed form) and the HBM-roofline fraction
 of the dominant kernel, on one MI355X.
 
 Workload: the polydisperse microstructure (256^3 unit cell, 60 seeded RSA
-spheres with radii U(10, 24) voxels, stiffness contrast 20), macroscopic
-stretch ramped by 0.0025 per load increment, damage on, chemistry off.  One
-"step" is one load increment of the staggered scheme: Newton-CG equilibrium
-(constitutive update, FP64 residual, CG on the operator of eq. (30)), the
-history / driving-force update, the phase-field PCG and the residual check.
-Warmup increments come first; the timed increments follow them.
+spheres with radii U(10, 24) voxels, stiffness contrast 20) at the state of
+its first load increment (macroscopic stretch 1.0025 along e1).  One "step"
+is one CG iteration of the linear system of the first Newton correction
+(eq. (30) with the tangent at F = Fbar): the matvec (fused contraction and
+N2 transform, N1 pass, N0 pass with the projection, inverse passes of the
+potential) and the CG updates and FP64 reductions.  Warmup iterations run
+first, untimed; then exactly --steps iterations are timed between two
+device synchronisations.  The system is assembled before the warmup.
 
-value = voxels x CG iterations / wall time of the timed increments (FP64).
-The mixed form's figures are reported alongside.  The roofline object
-refers to the kernel class with the largest time in the FP64 timed region;
-its average launch duration comes from HIP events on the plan stream.
+value = voxels x timed CG iterations / wall time of those iterations (FP64).
+The mixed form's figures are reported alongside, together with one complete
+Newton solve of the increment in each form (end-to-end time to Newton 1e-8,
+CG 1e-10, and the mixed form's field error against the FP64 solution).
+The roofline object refers to the kernel class with the largest time in the
+warmup (the fused front kernel); its average launch duration comes from HIP
+events taken by the kernel launches themselves during the timed iterations.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--n 256] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 40] [--warmup 5] [--n 256] [--no-cpu]
+    python bench.py --ramp [--steps 2] [--warmup 1]   (staggered load increments with damage)
     python bench.py --batch [--batch-items 48] [--graph-ticks 16]   (batched form)
     python bench.py --coupled [--steps 3] [--warmup 1]   (coupled path, particle 128^3)
 """
@@ -50,12 +56,20 @@ WORDS_PER_VOXEL = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps: CG iterations (default 40); load increments with --ramp, time steps with "
+                         "--coupled (default 2 / 3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 5; 1 with --ramp, "
+                                                                 "--coupled)")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--ramp", action="store_true",
+                    help="staggered load increments of the polydisperse ramp (Newton-CG, history, phase field) "
+                         "instead of CG iterations at the first increment")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the end-to-end Newton solve of the increment after the timed iterations")
     ap.add_argument("--batch", action="store_true",
                     help="the batched form instead: 48 ragged RVEs x 6 load cases (effective stiffness), batched "
                          "FP64 and mixed against the 288 single-item FP64 solves")
@@ -70,14 +84,22 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 9 N doubles device-to-device 3 times (a plain copy kernel of known size, "
                          "for scaling HBM counters)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    long_steps = args.ramp or args.coupled
+    if args.steps is None:
+        args.steps = (3 if args.coupled else 2) if long_steps else 40
+    if args.warmup is None:
+        args.warmup = 1 if long_steps else 5
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be >= 1 and --warmup >= 0")
+    return args
 
 
-def run_form(work, form, steps, warmup):
+def new_plan(work, form):
+    """Plan, material and state (F = I, c = d = H = 0) of a workload on cuda:0."""
     import torch
 
     from paper_2411_16583_amd import Plan
-    from paper_2411_16583_amd.driver import staggered_step
 
     dev = torch.device("cuda:0")
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
@@ -93,7 +115,73 @@ def run_form(work, form, steps, warmup):
     d = torch.zeros(shape, dtype=torch.float64, device=dev)
     H = torch.zeros(shape, dtype=torch.float64, device=dev)
     plan.set_state(F, c, d, H)
+    return plan, F
+
+
+def run_cg_form(work, form, steps, warmup, solve=True):
+    """The benchmark step: CG iterations of the first Newton correction of
+    the first load increment.  Warmup iterations (every kernel class timed
+    with HIP events: the per-class breakdown) come first; then exactly
+    `steps` iterations are timed (events only on the dominant class, taken by
+    its launches).  Afterwards, untimed by the step clock, one complete Newton
+    solve of the increment from F = I (end-to-end time and iteration counts);
+    its F is returned for the accuracy comparison between the forms."""
+    import torch
+
+    from paper_2411_16583_amd import make_opts
+
+    plan, F = new_plan(work, form)
+    Fbar = work["loads"][0]
+    plan.apply_macro(Fbar)
+    err0 = plan.newton_linear_begin(Fbar)
+    plan.profile_begin()
+    if warmup > 0:
+        plan.cg_iterate(warmup)
+    torch.cuda.synchronize()
+    prof_all = plan.profile_end()
+    timed = [k for k in WORDS_PER_VOXEL if prof_all[k][1] > 0]
+    dominant = max(timed, key=lambda k: prof_all[k][0]) if timed else "front"
+    plan.profile_begin(passes=[dominant])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = plan.cg_iterate(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = plan.profile_end()
+    print(f"[{form}] {steps} CG iterations (after {warmup} warmup) in {elapsed * 1e3:.2f} ms, "
+          f"err_res before the correction {err0:.3e}, ||r||/||b|| {it['relres']:.3e}", flush=True)
+    out = dict(elapsed=elapsed, cg_iters=steps, prof=prof, prof_all=prof_all, relres=it["relres"], err0=err0)
+    if solve:
+        F.zero_()
+        F[0] = 1.0
+        F[4] = 1.0
+        F[8] = 1.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = plan.newton_solve(Fbar, make_opts(tol_newton=1e-8, tol_lin=1e-10, max_newton=50, max_lin=20000))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        Pm = plan.homogenized_stress()
+        print(f"[{form}] Newton solve of the increment: {el:.3f} s, newton {st['newton_iters']}, "
+              f"cg {st['lin_history']}, err_res {st['err_res']:.2e}", flush=True)
+        out.update(solve=dict(seconds=el, newton_iters=st["newton_iters"], cg_iters=st["lin_iters_total"],
+                              cg_history=st["lin_history"], err_res=st["err_res"], P_avg=Pm), F=F)
+    plan.close()
+    return out
+
+
+def run_ramp_form(work, form, steps, warmup):
+    """Staggered load increments (Alg. 4 without chemistry) of the ramp:
+    warmup increments, then `steps` timed increments.  An increment whose
+    staggered loop does not converge raises (it is not timed as a step)."""
+    import torch
+
+    from paper_2411_16583_amd.driver import staggered_step
+
     loads = work["loads"]
+    if warmup + steps > len(loads):
+        raise SystemExit(f"--warmup + --steps = {warmup + steps} exceeds the {len(loads)} load increments")
+    plan, F = new_plan(work, form)
     # warm-up increments: HIP events around every kernel class (the per-class
     # breakdown); timed increments: events around the dominant class only
     # (the roofline kernel), since the event records of all classes cost a
@@ -457,19 +545,59 @@ def main():
         print(f"copy calibration: 3 copies of {9 * N * 8} bytes", flush=True)
         del a, b
     forms = args.forms.split(",")
+    if args.ramp:
+        run_ramp(args, work, forms, N)
+    else:
+        run_cg(args, work, forms, N)
+
+
+def field_error(Fa, Fb, Fbar):
+    """||Fa - Fb|| / ||Fb - Fbar|| (relative to the fluctuation) and the
+    largest absolute difference, computed on the device."""
+    import torch
+
+    ub = torch.as_tensor(np.asarray(Fbar, dtype=np.float64).reshape(9, 1, 1, 1), device=Fb.device)
+    num = torch.linalg.vector_norm(Fa - Fb).item()
+    den = torch.linalg.vector_norm(Fb - ub).item()
+    return num / max(den, 1e-300), torch.max(torch.abs(Fa - Fb)).item()
+
+
+def run_cg(args, work, forms, N):
+    """Default mode: CG iterations of the first Newton correction (see the
+    module docstring), FP64 as the headline value and mixed beside it."""
+    import torch
+
     res = {}
     errors = {}
+    F64 = None
     for form in forms:
         try:
-            res[form] = run_form(work, form, args.steps, args.warmup)
+            res[form] = run_cg_form(work, form, args.steps, args.warmup, solve=not args.no_solve)
         except Exception as e:  # report a failing form instead of dropping the line
             if form == forms[0]:
                 raise
             errors[form] = repr(e)
             print(f"[{form}] failed: {e!r}", flush=True)
+            continue
+        F = res[form].pop("F", None)
+        if form == "fp64":
+            F64 = F
+        elif F is not None and F64 is not None:
+            res[form]["F_err"] = field_error(F, F64, work["loads"][0])
+        del F
+        torch.cuda.empty_cache()
     main_form = "fp64" if "fp64" in res else forms[0]
     r0 = res[main_form]
     value = N * r0["cg_iters"] / r0["elapsed"]
+
+    def solve_rec(r):
+        if "solve" not in r:
+            return None
+        sv = r["solve"]
+        return dict(seconds=round(sv["seconds"], 4), newton_iters=sv["newton_iters"], cg_iters=sv["cg_iters"],
+                    cg_history=sv["cg_history"], err_res=sv["err_res"],
+                    voxel_cg_iters_per_s=N * sv["cg_iters"] / sv["seconds"], P11=float(sv["P_avg"][0, 0]))
+
     line = {
         "metric": "voxel*CG-iters/s at 256^3 (FP64 vs mixed) + % of HBM roofline",
         "value": value,
@@ -483,11 +611,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_form == "fp64" else "f32/f64",
         "data": "synthetic",
-        "config": {"workload": f"polydisperse RVE {args.n}^3, 60 RSA spheres r~U(10,24) vox, contrast 20, "
-                               f"macro stretch +0.0025 per increment, damage on, chemistry off",
-                   "voxels": N, "cg_iters": r0["cg_iters"], "newton_iters": r0["newton_iters"]},
+        "config": {"workload": f"polydisperse RVE {args.n}^3 (60 RSA spheres r~U(10,24) vox, contrast 20), "
+                               f"first load increment F = I + 0.0025 e1(x)e1; step = one CG iteration of the "
+                               f"first Newton correction",
+                   "voxels": N, "step": "CG iteration", "relres_after_steps": r0["relres"]},
         "roofline": roofline(r0, N, 8 if main_form == "fp64" else 4),
     }
+    if solve_rec(r0):
+        line["newton_solve"] = solve_rec(r0)
     for form in forms:
         if form == main_form:
             continue
@@ -496,13 +627,61 @@ def main():
             continue
         r = res[form]
         v = N * r["cg_iters"] / r["elapsed"]
+        rec = dict(value=v, ms_per_step=1e3 * r["elapsed"] / args.steps, speedup_per_cg_iter=v / value,
+                   relres_after_steps=r["relres"], roofline=roofline(r, N, 4))
+        sv = solve_rec(r)
+        if sv:
+            rec["newton_solve"] = sv
+            if "solve" in r0:
+                rec["speedup_newton_solve_at_equal_accuracy"] = r0["solve"]["seconds"] / r["solve"]["seconds"]
+                P0 = r0["solve"]["P_avg"]
+                rec["rel_diff_Pavg_vs_fp64"] = float(np.linalg.norm(r["solve"]["P_avg"] - P0) / np.linalg.norm(P0))
+            if "F_err" in r:
+                rec["rel_diff_F_vs_fp64"] = r["F_err"][0]
+                rec["max_abs_diff_F_vs_fp64"] = r["F_err"][1]
+        line[form] = rec
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(work, args.cpu_iters)
+    print(json.dumps(line), flush=True)
+
+
+def run_ramp(args, work, forms, N):
+    """--ramp: staggered load increments (Newton-CG, history, phase field)."""
+    res = {}
+    for form in forms:
+        res[form] = run_ramp_form(work, form, args.steps, args.warmup)
+    main_form = "fp64" if "fp64" in res else forms[0]
+    r0 = res[main_form]
+    value = N * r0["cg_iters"] / r0["elapsed"]
+    line = {
+        "metric": "voxel*CG-iters/s at 256^3 over staggered load increments (damage on)",
+        "value": value,
+        "unit": "voxel*CG-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r0["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_form == "fp64" else "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"polydisperse RVE {args.n}^3, load increments {args.warmup + 1}.."
+                               f"{args.warmup + args.steps} of the stretch ramp, damage on, chemistry off; "
+                               f"step = one staggered load increment",
+                   "voxels": N, "cg_iters": r0["cg_iters"], "newton_iters": r0["newton_iters"]},
+        "roofline": roofline(r0, N, 8 if main_form == "fp64" else 4),
+    }
+    for form in forms:
+        if form == main_form:
+            continue
+        r = res[form]
+        v = N * r["cg_iters"] / r["elapsed"]
         line[form] = dict(value=v, ms_per_step=1e3 * r["elapsed"] / args.steps, cg_iters=r["cg_iters"],
                           newton_iters=r["newton_iters"], speedup_per_cg_iter=v / value,
                           speedup_per_step=r0["elapsed"] / r["elapsed"],
                           rel_diff_P11_vs_fp64=abs(r["P11"] - r0["P11"]) / abs(r0["P11"]),
                           roofline=roofline(r, N, 4))
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(work, args.cpu_iters)
     print(json.dumps(line), flush=True)
 
 

@@ -125,6 +125,27 @@ fg_status fg_set_state(fg_plan* plan, double* F, double* c, double* d, double* H
 fg_status fg_newton_solve(fg_plan* plan, const double F_macro[9], const fg_solver_opts* opts,
                           fg_stats* stats);
 
+/* One Newton correction of Alg. 1 split in two calls, for callers that run
+ * the CG iterations of eq. (30) themselves (a stopping rule of their own, or
+ * timing the CG loop alone).
+ * fg_newton_linear_begin evaluates P and the tangent at the current F (the
+ * macroscopic increment is NOT applied), writes err_res of eq. (31)
+ * (normalised by ||G*P(F_macro)|| as in fg_newton_solve) to *err_res (host,
+ * may be NULL) and starts CG on G*(K : dF) = -G*P from dF = 0.  F_macro:
+ * host, 9 doubles.  Synchronises.  Errors: FG_E_STATE, FG_E_DOMAIN,
+ * FG_E_HIP.
+ * fg_cg_iterate continues that CG by exactly n iterations (n >= 0; no
+ * tolerance test, the iterations are those fg_newton_solve runs).  With
+ * apply != 0 it then adds the CG iterate dF to F (double precision) and the
+ * system is closed.  Any other call on the plan that uses its workspace also
+ * closes it; fg_cg_iterate on a closed system returns FG_E_STATE.  stats (may
+ * be NULL): lin_iters_last = CG iterations of this system so far,
+ * lin_relres = ||r|| / ||b||.  Synchronises.  Errors: FG_E_ARG (n < 0),
+ * FG_E_STATE, FG_E_BREAKDOWN (p.Ap <= 0; the system stays open but cannot
+ * advance), FG_E_HIP. */
+fg_status fg_newton_linear_begin(fg_plan* plan, const double F_macro[9], double* err_res);
+fg_status fg_cg_iterate(fg_plan* plan, int n, int apply, fg_stats* stats);
+
 /* Add the macroscopic increment F_macro - <F> to F (the first line of
  * Alg. 1, F^0 = F_t + dFbar; Sec. 3.2 Global problem: the chemistry of a step
  * sees the new macroscopic F).  F_macro: host, 9 doubles.  Synchronises.

@@ -18,17 +18,30 @@ import numpy as np
 
 from .chemistry import fick_step
 from .fracture import pff_solve, update_history
-from .mechanics import err_denominator, newton_solve, norm, residual_rhs, uniform_field
+from .mechanics import NoConvergence, err_denominator, newton_solve, norm, residual_rhs, uniform_field
+
+
+class StaggeredNoConvergence(NoConvergence):
+    """The staggered loop used max_stag iterations without reaching tol_nw;
+    ``result`` holds (F, c, d, H, stats) of the last iterate."""
+
+    def __init__(self, result):
+        st = result[-1]
+        super().__init__(f"staggered loop: err_res {st['err_res']:.3e} after {st['stag_iters']} iterations")
+        self.result = result
 
 
 def staggered_step(F, c, d, H, Fbar_new, Fbar_old, mat, dt=None, cdot_B=None,
                    chemistry=True, tol_newton=1e-8, tol_lin=1e-10, tol_chem=1e-8,
-                   tol_pff=1e-10, max_stag=20):
-    """One time step of Alg. 4; returns (F, c, d, H, stats)."""
+                   tol_pff=1e-10, max_stag=20, raise_on_noconv=True):
+    """One time step of Alg. 4; returns (F, c, d, H, stats), stats["converged"]
+    telling whether err_res <= tol_newton was reached.  Without convergence in
+    max_stag iterations StaggeredNoConvergence is raised (or, with
+    raise_on_noconv=False, the result is returned with converged False)."""
     shape = mat["shape"]
     spacing = mat["spacing"]
     F = F + uniform_field(np.asarray(Fbar_new) - np.asarray(Fbar_old), shape)
-    st = dict(newton=[], pff_iters=[], stag_iters=0, chem=None)
+    st = dict(newton=[], pff_iters=[], stag_iters=0, chem=None, converged=False)
     if chemistry:
         c, chem = fick_step(c, F, d, cdot_B, dt, mat, tol_chem=tol_chem, tol_lin=tol_lin)
         st["chem"] = chem
@@ -45,5 +58,8 @@ def staggered_step(F, c, d, H, Fbar_new, Fbar_old, mat, dt=None, cdot_B=None,
         st["stag_iters"] = k + 1
         st["err_res"] = err
         if err <= tol_newton:
+            st["converged"] = True
             break
+    if not st["converged"] and raise_on_noconv:
+        raise StaggeredNoConvergence((F, c, d, H, st))
     return F, c, d, H, st

@@ -188,6 +188,10 @@ struct fg_plan {
   // state (caller-owned)
   double *F = nullptr, *c = nullptr, *d = nullptr, *H = nullptr;
   double* zeroN = nullptr;  // N zeros (c, d when not given) inside the scalar area
+  // a linear system of one Newton correction begun by fg_newton_linear_begin
+  // and open for fg_cg_iterate (cleared by every call that reuses the CG
+  // workspace)
+  bool lin_open = false;
 
   // optional per-kernel-class timing with HIP events (fg_profile_*)
   bool prof_on = false;
@@ -683,18 +687,15 @@ void cg_solve(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
     stats->lin_iters_last = h.iter;
     stats->lin_relres = h.rr0 > 0 ? std::sqrt(h.rr / h.rr0) : 0.0;
   }
-  // An inexact inner solve in the mixed form (single-precision rounding
-  // breaking p.Ap > 0, or the iteration cap) still hands its correction to
-  // the double-precision Newton loop, which measures the true residual.
-  const bool inexact_ok = (P->prec == FG_MIXED) && h.iter > 0;
-  if (h.flag == 1 && !inexact_ok) throw Status(FG_E_BREAKDOWN, "CG breakdown: p.Ap <= 0");
-  if (h.flag == 2 && !inexact_ok) throw Status(FG_E_NOCONV, "CG reached max_lin iterations");
+  // Both precisions report a breakdown (p.Ap <= 0) and the iteration cap:
+  // a correction from an indefinite or unconverged solve is not handed on.
+  if (h.flag == 1) throw Status(FG_E_BREAKDOWN, "CG breakdown: p.Ap <= 0");
+  if (h.flag == 2) throw Status(FG_E_NOCONV, "CG reached max_lin iterations");
 }
 
-// Newton loop of Alg. 1 at the current F (increment already applied).
-void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stats* stats) {
-  const long n9 = 9 * P->N;
-  // normaliser of eq. (31): ||G*P(Fbar)||, with floors (A8)
+// Normaliser of eq. (31) for the macroscopic F_macro: ||G*P(F_macro)||
+// with the floors of reading A8 (max with 1e-14 ||P(F_macro)|| and 1e-300).
+double residual_denominator(fg_plan* P, const double Fmacro[9]) {
   FG_HIP(hipMemcpyAsync(P->Fu, Fmacro, 9 * sizeof(double), hipMemcpyHostToDevice, P->stream));
   const unsigned nbN = blocks_for(P->N);
   constitutive(P, P->Fu, P->S64, nullptr, P->part2);
@@ -702,7 +703,23 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
   residual_norm(P, 1);                  // ||G*P(Fbar)||^2
   sync_read(P);
   check_domain(P);
-  const double den = std::max(std::max(std::sqrt(P->hd[1]), 1e-14 * std::sqrt(P->hd[0])), 1e-300);
+  return std::max(std::max(std::sqrt(P->hd[1]), 1e-14 * std::sqrt(P->hd[0])), 1e-300);
+}
+
+// P and the tangent state at the current F, and ||G*P|| / den; S64 is left
+// holding the potential U(P) (D U = G*P) that the CG start reuses.
+double newton_residual(fg_plan* P, double den) {
+  constitutive(P, nullptr, P->S64, P->st, nullptr);
+  residual_norm(P, 2);
+  sync_read(P);
+  check_domain(P);
+  return std::sqrt(P->hd[2]) / den;
+}
+
+// Newton loop of Alg. 1 at the current F (increment already applied).
+void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stats* stats) {
+  const long n9 = 9 * P->N;
+  const double den = residual_denominator(P, Fmacro);
   int it = 0;
   if (stats) {
     stats->newton_iters = 0;
@@ -710,11 +727,7 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
     stats->n_history = 0;
   }
   while (true) {
-    constitutive(P, nullptr, P->S64, P->st, nullptr);
-    residual_norm(P, 2);
-    sync_read(P);
-    check_domain(P);
-    const double err = std::sqrt(P->hd[2]) / den;
+    const double err = newton_residual(P, den);
     if (stats) {
       if (stats->n_history < 64) stats->err_history[stats->n_history] = err;
       stats->n_history += 1;
@@ -995,7 +1008,7 @@ void fick(fg_plan* P, double dt, const double* cdot, const fg_solver_opts* o, fg
     hipLaunchKernelGGL(k_fick_residual, dim3(nbN), dim3(256), 0, P->stream, P->c, v.ct, v.mu, v.A6, cdot, dt, g,
                        v.r, v.x, P->part2, N);
     check_launch();
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbN, P->ks + 1,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbN, P->ksc,
                        (double*)nullptr, 5, 1);
     check_launch();
     sync_read(P);
@@ -1097,6 +1110,7 @@ fg_status plan_new(const int grid[3], const double spacing[3], fg_precision prec
 
 void need_ready(fg_plan* P, bool need_state) {
   if (P->batch_group) throw Status(FG_E_ARG, "a batch group plan takes only the tile calls");
+  P->lin_open = false;  // every solver call reuses the CG workspace
   if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
   if (!P->have_material) throw Status(FG_E_STATE, "material not set");
   if (need_state && !P->F) throw Status(FG_E_STATE, "state not set");
@@ -1198,6 +1212,69 @@ fg_status fg_newton_solve(fg_plan* P, const double F_macro[9], const fg_solver_o
   });
 }
 
+fg_status fg_newton_linear_begin(fg_plan* P, const double F_macro[9], double* err_res) {
+  if (!P || !F_macro) return FG_E_ARG;
+  return run(P, [&]() {
+    need_ready(P, true);
+    const double err = newton_residual(P, residual_denominator(P, F_macro));
+    // b = -G*P: rho_0 = -U(P), the potential newton_residual left in S64
+    if (P->prec == FG_FP64)
+      cg_start1<double>(P, P->S64, -1.0, true);
+    else
+      cg_start1<float>(P, P->S64, -1.0, true);
+    sync_read(P);
+    if (err_res) *err_res = err;
+    P->lin_open = true;
+  });
+}
+
+fg_status fg_cg_iterate(fg_plan* P, int n, int apply, fg_stats* stats) {
+  if (!P || n < 0 || P->batch_group) return FG_E_ARG;
+  return run(P, [&]() {
+    if (!P->lin_open) throw Status(FG_E_STATE, "no linear system open (fg_newton_linear_begin)");
+    // P->hks[0] holds the scalars of the last read-back (every call here
+    // ends with one): continue from them for exactly n more iterations
+    KrylovScalars& h = P->hks[0];
+    if (n > 0 && h.flag != 1 && h.rr0 > 0.0) {
+      h.tol2 = 0.0;
+      h.maxit = h.iter + n;
+      h.done = 0;
+      h.flag = 0;
+      FG_HIP(hipMemcpyAsync(P->ks, &h, sizeof(KrylovScalars), hipMemcpyHostToDevice, P->stream));
+      for (int left = n; left > 0;) {
+        const int chunk = std::min(left, 8);
+        for (int k = 0; k < chunk; ++k) {
+          if (P->prec == FG_FP64)
+            cg_iteration<double>(P);
+          else
+            cg_iteration<float>(P);
+        }
+        left -= chunk;
+        sync_read(P);
+        if (P->hks[0].flag == 1) break;
+      }
+    }
+    const KrylovScalars& k = P->hks[0];
+    if (stats) {
+      stats->lin_iters_last = k.iter;
+      stats->lin_relres = k.rr0 > 0 ? std::sqrt(k.rr / k.rr0) : 0.0;
+    }
+    if (k.flag == 1) throw Status(FG_E_BREAKDOWN, "CG breakdown: p.Ap <= 0");
+    if (apply) {
+      P->lin_open = false;
+      if (P->prec == FG_FP64)
+        cg_result<double>(P, P->S64, nullptr);
+      else
+        cg_result<float>(P, P->S64, nullptr);
+      const long n9 = 9 * P->N;
+      hipLaunchKernelGGL((k_axpy_into_f64<double>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->F,
+                         (const double*)P->S64, n9);
+      check_launch();
+      FG_HIP(hipStreamSynchronize(P->stream));
+    }
+  });
+}
+
 fg_status fg_adjoint_gradient(fg_plan* P, const double dL_dPavg[9], double* dL_dlogE, double* dL_dOmega,
                               const fg_solver_opts* opts, fg_stats* stats) {
   if (!P || !dL_dPavg || !opts) return FG_E_ARG;
@@ -1288,6 +1365,7 @@ fg_status fg_project(fg_plan* P, const double* x, double* y) {
   if (!P || !x || !y || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
+    P->lin_open = false;
     C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
     project9<double>(P, x, P->S64, y, epi);
     check_launch();
@@ -1298,6 +1376,7 @@ fg_status fg_project_grad(fg_plan* P, const double* x, double* y) {
   if (!P || !x || !y || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
+    P->lin_open = false;
     {
       ProfScope ps(P, FG_PASS_R2C);
       launch_r2c<double>(P->M, x, P->S64, 9L * P->n0 * P->n1, P->t64.spec(), Skip{}, P->stream);
@@ -1317,6 +1396,7 @@ fg_status fg_fft_r2c(fg_plan* P, double* data, int ncomp) {
   if (!P || !data || ncomp <= 0 || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
+    P->lin_open = false;
     const SpecTables<double> tb = P->t64.spec();
     fwd_xy<double>(P, data, data, ncomp, Skip{});
     launch_axis<double>(P->n0, false, data, (long)P->n1 * P->M, P->M, (long)P->n0 * P->n1 * P->M, P->M, P->n1,
@@ -1329,6 +1409,7 @@ fg_status fg_fft_c2r(fg_plan* P, double* data, int ncomp) {
   if (!P || !data || ncomp <= 0 || P->batch_group) return FG_E_ARG;
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
+    P->lin_open = false;
     const SpecTables<double> tb = P->t64.spec();
     launch_axis<double>(P->n0, true, data, (long)P->n1 * P->M, P->M, (long)P->n0 * P->n1 * P->M, P->M, P->n1,
                         ncomp, tb.tw0, Skip{}, P->stream);
@@ -2045,6 +2126,7 @@ fg_status fg_plan_time_pass(fg_plan* P, int which, int tile, int reps, double* m
   if (which >= 2 && P->prec != FG_MIXED) return FG_E_ARG;  // single-precision passes exist in mixed plans only
   return run(P, [&]() {
     if (!P->ws) throw Status(FG_E_STATE, "workspace not set");
+    P->lin_open = false;
     if (which < 2)
       time_pass_impl<double>(P, tp.zproj, tile, reps, ms);
     else

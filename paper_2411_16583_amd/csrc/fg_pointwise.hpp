@@ -273,13 +273,14 @@ k_finalize(const double* __restrict__ partials, int nparts, KrylovScalars* ks, d
   } else if (mode == 1) {
     const double rr = s;
     ks->iter += 1;
+    // beta is kept even when the solve stops here, so that a solve stopped
+    // at a fixed iteration count can be continued
+    ks->beta = rr / ks->rr;
     if (ks->tol2 > 0.0 && rr <= ks->tol2 * ks->rr0) {
       ks->done = 1;
     } else if (ks->iter >= ks->maxit) {
       ks->done = 1;
       ks->flag = (ks->tol2 > 0.0) ? 2 : 0;
-    } else {
-      ks->beta = rr / ks->rr;
     }
     ks->rr = rr;
   } else if (mode == 2) {

@@ -8,14 +8,28 @@ call runs in the HIP library; this module only sequences them.
 """
 from __future__ import annotations
 
-from .fgfft import make_opts
+from .fgfft import FG_E_NOCONV, FgError, make_opts
+
+
+class StaggeredNoConvergence(FgError):
+    """The staggered loop of Alg. 4 used its ``max_stag`` iterations without
+    reaching err_res <= tol_newton.  ``stats`` holds the step's statistics;
+    the plan's state holds the last iterate."""
+
+    def __init__(self, stats):
+        super().__init__(FG_E_NOCONV, f"staggered loop: err_res {stats['err_res']:.3e} after "
+                                      f"{stats['stag_iters']} iterations")
+        self.stats = stats
 
 
 def staggered_step(plan, F_macro, dt=None, cdot_B=None, chemistry=True, tol_newton=1e-8, tol_lin=1e-10,
-                   tol_chem=1e-8, tol_pff=1e-10, max_stag=20, max_lin=20000):
-    """One time step; returns a stats dict.  The plan's state (F, c, d, H)
-    is updated in place."""
-    st = dict(chem=None, newton=[], pff=[], stag_iters=0, err_res=None)
+                   tol_chem=1e-8, tol_pff=1e-10, max_stag=20, max_lin=20000, raise_on_noconv=True):
+    """One time step; returns a stats dict (``converged`` tells whether the
+    staggered loop met its tolerance).  The plan's state (F, c, d, H) is
+    updated in place.  When the loop does not converge within ``max_stag``
+    iterations, StaggeredNoConvergence is raised (or, with
+    raise_on_noconv=False, the stats are returned with converged=False)."""
+    st = dict(chem=None, newton=[], pff=[], stag_iters=0, err_res=None, converged=False)
     plan.apply_macro(F_macro)  # F^0 = F_t + dFbar (Alg. 1, first line)
     if chemistry:
         # chemistry once per step, with the new macroscopic F and the damage of
@@ -28,5 +42,8 @@ def staggered_step(plan, F_macro, dt=None, cdot_B=None, chemistry=True, tol_newt
         st["stag_iters"] = k + 1
         st["err_res"] = err
         if err <= tol_newton:
+            st["converged"] = True
             break
+    if not st["converged"] and raise_on_noconv:
+        raise StaggeredNoConvergence(st)
     return st

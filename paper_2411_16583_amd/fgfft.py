@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": FG_FP64, "mixed": FG_MIXED}
 # Every function declared in include/fgfft.h.
 EXPORTED = [
     "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
-    "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_adjoint_gradient", "fg_residual", "fg_homogenized_stress", "fg_stress",
+    "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_newton_linear_begin", "fg_cg_iterate",
+    "fg_adjoint_gradient", "fg_residual", "fg_homogenized_stress", "fg_stress",
     "fg_apply_operator", "fg_project", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
     "fg_batch_create", "fg_batch_workspace_bytes", "fg_batch_groups", "fg_batch_set_workspace",
     "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
@@ -99,6 +100,8 @@ def load_library(path=LIB_PATH):
         "fg_set_state": ([vp, dptr, dptr, dptr, dptr], c_int),
         "fg_apply_macro": ([vp, ctypes.POINTER(c_double)], c_int),
         "fg_newton_solve": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
+        "fg_newton_linear_begin": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
+        "fg_cg_iterate": ([vp, c_int, c_int, ctypes.POINTER(Stats)], c_int),
         "fg_adjoint_gradient": ([vp, ctypes.POINTER(c_double), dptr, dptr, ctypes.POINTER(SolverOpts),
                                  ctypes.POINTER(Stats)], c_int),
         "fg_residual": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
@@ -230,6 +233,22 @@ class Plan:
         d = stats.to_dict()
         d["status"] = st
         return d
+
+    def newton_linear_begin(self, F_macro):
+        """P, tangent and the CG right-hand side of one Newton correction at
+        the current F; returns err_res (eq. (31))."""
+        a, p = _mat9(F_macro)
+        out = ctypes.c_double()
+        self._check(self.lib.fg_newton_linear_begin(self.handle, p, ctypes.byref(out)), "fg_newton_linear_begin")
+        return out.value
+
+    def cg_iterate(self, n, apply=False):
+        """Exactly n more CG iterations of the open Newton system; apply=True
+        then adds the CG iterate to F and closes the system."""
+        stats = Stats()
+        self._check(self.lib.fg_cg_iterate(self.handle, int(n), 1 if apply else 0, ctypes.byref(stats)),
+                    "fg_cg_iterate")
+        return dict(iters=stats.lin_iters_last, relres=stats.lin_relres)
 
     def adjoint_gradient(self, dL_dPavg, g_logE=None, g_Omega=None, opts=None):
         """Per-voxel d L / d log E and d L / d Omega of L = sum w_ij <P_ij> into

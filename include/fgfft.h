@@ -22,8 +22,9 @@
  * Memory: every field, material array and the workspace is owned by the
  * caller (for example PyTorch tensors) and must stay valid until it is
  * replaced or the plan is destroyed.  The library allocates no device
- * memory; it owns only the opaque plan and a little pinned host memory for
- * scalar read-backs.
+ * memory; it owns only the opaque plan, a little pinned host memory for
+ * scalar read-backs, and the fixed device array of fg_project_noalloc that
+ * is part of its code object.
  * Streams: all device work is issued on the stream given at plan creation
  * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL is the
  * default stream).  Calls that return solver statistics synchronise that
@@ -199,6 +200,23 @@ fg_status fg_project(fg_plan* plan, const double* x, double* y);
  * rotated scheme (its symbol is i e^{-i Phi} r).  Double precision; x, y:
  * device, 9 N doubles (y may equal x).  Does not synchronise. */
 fg_status fg_project_grad(fg_plan* plan, const double* x, double* y);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * projection of fg_project, y = F^-1[ G^ : F[x] ] (eq. (28)), without a plan
+ * or workspace.  grid: 3 ints, spacing: 3 doubles (host), as for
+ * fg_plan_create; x, y: device, 9 N doubles, caller-owned (y may equal x);
+ * stream: hipStream_t or NULL.  Its transform tables and its spectral work
+ * buffer (9 N doubles) live in a fixed 64 MiB + 64 KiB array that the
+ * library holds on every device it runs on until the process ends, so the
+ * call allocates nothing; grids with 9 N doubles beyond 64 MiB (N above
+ * 932067 voxels, e.g. 96^3 fits, 128^3 does not) return FG_E_SIZE before any
+ * device work.  Every call on a device shares that device's array (each call
+ * rewrites all of it before reading it): calls that overlap on one device,
+ * on different streams or host threads, race.  Double precision; the
+ * result equals fg_project's to rounding.  Does not synchronise.
+ * Errors: FG_E_ARG, FG_E_SIZE, FG_E_HIP. */
+fg_status fg_project_noalloc(const int grid[3], const double spacing[3], const double* x, double* y, void* stream);
 
 /* 3-D real transform of ncomp scalar fields, double precision, in place:
  * fg_fft_r2c turns ncomp real fields (ncomp N doubles) into the packed half

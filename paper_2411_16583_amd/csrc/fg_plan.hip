@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -2132,6 +2133,138 @@ fg_status fg_plan_time_pass(fg_plan* P, int which, int tile, int reps, double* m
     else
       time_pass_impl<float>(P, tp.zproj, tile, reps, ms);
   });
+}
+
+}  // extern "C"
+
+// --------------------------------------------- allocation-free projection --
+// fg_project_noalloc: the compatibility projection of fg_project without a
+// plan or workspace.  Its transform tables and spectral work buffer live in
+// `scratch`, a fixed array in the library's code object on every device (held
+// until the process ends).  In host code `scratch` names only a host-side
+// stand-in: its device address on the current device comes from
+// hipGetSymbolAddress, taken once per device and kept in g_scratch_dev[],
+// and only that address is ever handed to kernels.
+constexpr size_t kScratchTableBytes = 64 * 1024;                // transform and symbol tables
+constexpr size_t kScratchWorkBytes = 64ull * 1024 * 1024;       // 9 N doubles of spectrum
+static __device__ __align__(256) char scratch[kScratchTableBytes + kScratchWorkBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (nullptr on failure).
+void* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+// The tables of host_tables<double>, computed on the device (sincospi in
+// double instead of long double rounded once: the entries agree to an ulp,
+// with the same exact values at the quarter and half angles).
+__global__ void __launch_bounds__(256) k_tables_f64(TablesDev<double> t, int n0, int n1, int n2, double h0, double h1,
+                                                    double h2) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int M = n2 / 2;
+  auto root = [&](int L, cplx<double>* w) {
+    if (j >= L) return;
+    double sv, cv;
+    sincospi(2.0 * (double)j / (double)L, &sv, &cv);
+    cplx<double> r{cv, -sv};
+    if (4 * j == L) r = cplx<double>{0.0, -1.0};
+    if (2 * j == L) r = cplx<double>{-1.0, 0.0};
+    if (4 * j == 3 * L) r = cplx<double>{0.0, 1.0};
+    if (j == 0) r = cplx<double>{1.0, 0.0};
+    w[j] = r;
+  };
+  root(n0, t.tw0);
+  root(n1, t.tw1);
+  root(M, t.twM);
+  if (j < M) {
+    double sv, cv;
+    sincospi(2.0 * (double)j / (double)n2, &sv, &cv);
+    cplx<double> r{cv, -sv};
+    if (j == 0) r = cplx<double>{1.0, 0.0};
+    if (4 * j == n2) r = cplx<double>{0.0, -1.0};
+    t.post[j] = r;
+  }
+  auto half = [&](int n, int count, double h, double* c, double* sc, double* sn) {
+    if (j >= count) return;
+    double sv, cv;
+    sincospi((double)j / (double)n, &sv, &cv);
+    if (j == 0) sv = 0.0;
+    if (2 * j == n) {
+      cv = 0.0;
+      sv = 1.0;
+    }
+    c[j] = cv;
+    sc[j] = (2.0 / h) * sv;
+    sn[j] = sv;
+  };
+  half(n0, n0, h0, t.cz, t.sz, t.snz);
+  half(n1, n1, h1, t.cy, t.sy, t.sny);
+  half(n2, M + 1, h2, t.cx, t.sx, t.snx);
+}
+
+}  // namespace
+
+extern "C" {
+
+fg_status fg_project_noalloc(const int grid[3], const double spacing[3], const double* x, double* y, void* stream) {
+  if (!grid || !spacing || !x || !y) return FG_E_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!(spacing[k] > 0.0) || !std::isfinite(spacing[k])) return FG_E_ARG;
+  if (!fg::fft_axis_length_supported(grid[0]) || !fg::fft_axis_length_supported(grid[1])) return FG_E_SIZE;
+  if (grid[2] % 2 != 0 || grid[2] < 4 || !fg::fft_length_supported(grid[2] / 2)) return FG_E_SIZE;
+  const long N = (long)grid[0] * grid[1] * grid[2];
+  if ((size_t)N * 9 * sizeof(double) > kScratchWorkBytes) return FG_E_SIZE;
+  char* base = (char*)scratch_on_current_device();
+  if (!base) return FG_E_HIP;
+  try {
+    fg_plan P;  // a view of the grid only: no workspace, no pinned memory
+    P.n0 = grid[0];
+    P.n1 = grid[1];
+    P.n2 = grid[2];
+    P.M = grid[2] / 2;
+    P.N = N;
+    for (int k = 0; k < 3; ++k) P.h[k] = spacing[k];
+    P.prec = FG_FP64;
+    P.stream = (hipStream_t)stream;
+    size_t off = 0;
+    TablesDev<double>& t = P.t64;
+    t.tw0 = carve<cplx<double>>(base, off, P.n0);
+    t.tw1 = carve<cplx<double>>(base, off, P.n1);
+    t.twM = carve<cplx<double>>(base, off, P.M);
+    t.post = carve<cplx<double>>(base, off, P.M);
+    t.cz = carve<double>(base, off, P.n0);
+    t.sz = carve<double>(base, off, P.n0);
+    t.cy = carve<double>(base, off, P.n1);
+    t.sy = carve<double>(base, off, P.n1);
+    t.cx = carve<double>(base, off, P.M + 1);
+    t.sx = carve<double>(base, off, P.M + 1);
+    t.snz = carve<double>(base, off, P.n0);
+    t.sny = carve<double>(base, off, P.n1);
+    t.snx = carve<double>(base, off, P.M + 1);
+    if (off > kScratchTableBytes) return FG_E_SIZE;
+    P.S64 = (double*)(base + kScratchTableBytes);
+    const int nt = std::max(std::max(P.n0, P.n1), P.M + 1);
+    hipLaunchKernelGGL(k_tables_f64, dim3((nt + 255) / 256), dim3(256), 0, P.stream, t, P.n0, P.n1, P.n2, P.h[0],
+                       P.h[1], P.h[2]);
+    C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
+    project9<double>(&P, x, P.S64, y, epi);
+    return hipGetLastError() == hipSuccess ? FG_OK : FG_E_HIP;
+  } catch (...) {
+    return FG_E_HIP;
+  }
 }
 
 }  // extern "C"

@@ -25,7 +25,7 @@ EXPORTED = [
     "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
     "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_newton_linear_begin", "fg_cg_iterate",
     "fg_adjoint_gradient", "fg_residual", "fg_homogenized_stress", "fg_stress",
-    "fg_apply_operator", "fg_project", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
+    "fg_apply_operator", "fg_project", "fg_project_noalloc", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
     "fg_batch_create", "fg_batch_workspace_bytes", "fg_batch_groups", "fg_batch_set_workspace",
     "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
     "fg_batch_plan", "fg_batch_group_info", "fg_batch_set_schedule", "fg_plan_tile_candidates", "fg_plan_set_tiles", "fg_plan_get_tiles",
@@ -110,6 +110,7 @@ def load_library(path=LIB_PATH):
         "fg_apply_operator": ([vp, dptr, dptr], c_int),
         "fg_project": ([vp, dptr, dptr], c_int),
         "fg_project_grad": ([vp, dptr, dptr], c_int),
+        "fg_project_noalloc": ([ctypes.POINTER(c_int), ctypes.POINTER(c_double), dptr, dptr, vp], c_int),
         "fg_fft_r2c": ([vp, dptr, c_int], c_int),
         "fg_fft_c2r": ([vp, dptr, c_int], c_int),
         "pff_solve": ([vp, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
@@ -163,6 +164,22 @@ def _ptr(t):
 def _mat9(a):
     a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(9))
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def project_noalloc(grid, spacing, x, y, stream=None):
+    """fg_project_noalloc: y = G * x on the given grid without a plan (the
+    library's fixed device array holds the tables and the spectrum)."""
+    import torch
+
+    lib = load_library()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    g = (ctypes.c_int * 3)(*[int(n) for n in grid])
+    h = (ctypes.c_double * 3)(*[float(v) for v in spacing])
+    st = lib.fg_project_noalloc(g, h, _ptr(x), _ptr(y), ctypes.c_void_p(stream.cuda_stream))
+    if st != FG_OK:
+        raise FgError(st, f"fg_project_noalloc{tuple(grid)}: {lib.fg_status_string(st).decode()}")
+    return y
 
 
 def make_opts(tol_newton=1e-8, tol_lin=1e-10, max_newton=50, max_lin=20000, fixed_lin=0):

@@ -94,3 +94,33 @@ def test_effective_cauchy_limits():
     G = E / (2 * (1 + nu))
     assert abs(s[0, 0] / eps - (lam + 2 * G)) < 1e-5 * (lam + 2 * G)
     assert abs(s[1, 1] / eps - lam) < 1e-5 * (lam + 2 * G)
+
+
+def test_effective_cauchy_is_push_forward_of_undegraded_stress():
+    """sigma = J^-1 (P / g) F^T (the Cauchy stress of the undegraded law,
+    reading A6 of eq. (8)), with P from the pinned constitutive stress, at
+    random finite F (J far from 1), concentration, swelling and damage; the
+    result is symmetric and objective: sigma(Q F) = Q sigma(F) Q^T."""
+    from oracle import constitutive as cm
+
+    rng = np.random.default_rng(3111)
+    n = 40
+    F = np.eye(3)[:, :, None] + 0.25 * rng.standard_normal((3, 3, n))
+    J = np.linalg.det(np.moveaxis(F, 2, 0))
+    F[:, :, J < 0.2] = np.eye(3)[:, :, None] * 1.3  # keep det F well positive
+    c = rng.uniform(0.0, 0.9, n)
+    Om = rng.uniform(0.0, 1.3, n)
+    E = rng.uniform(5e9, 2e11, n)
+    nu = rng.uniform(0.1, 0.45, n)
+    d = rng.uniform(0.0, 0.9, n)
+    sig = fracture.effective_cauchy(F, c, E, nu, Om)
+    P = cm.stress(F, c, d, E, nu, Om)
+    J = np.linalg.det(np.moveaxis(F, 2, 0))
+    ref = np.einsum("ik...,jk...->ij...", P / (1 - d) ** 2, F) / J
+    scale = np.max(np.abs(ref), axis=(0, 1))
+    assert np.max(np.abs(sig - ref) / scale) <= 1e-12
+    assert np.max(np.abs(sig - np.swapaxes(sig, 0, 1)) / scale) <= 1e-12
+    Q = _rot(3112)
+    sigQ = fracture.effective_cauchy(np.einsum("ik,kj...->ij...", Q, F), c, E, nu, Om)
+    rotated = np.einsum("ik,kl...,jl->ij...", Q, sig, Q)
+    assert np.max(np.abs(sigQ - rotated) / scale) <= 1e-12

@@ -32,6 +32,13 @@ Readings of the paper taken here:
 * C_t = F^T F of the stored deformation, d_t the stored damage (chemistry is
   solved once per step with the fields of the previous step, Sec. 3.2
   Global problem).
+
+Fully implicit variant (beyond the paper's stated approximation): with
+``jacobian="full"`` the Newton linearisation also keeps the elastic part,
+d mu/dc = w + d(mu_e / c_max)/dc, so the step converges quadratically; the
+equation f(c) = 0 and hence its solution are unchanged.  The staggered
+driver can then call the step inside its loop with the current F and d
+(staggered.staggered_step(chemistry="coupled")).
 """
 from __future__ import annotations
 
@@ -57,6 +64,22 @@ def chemical_potential(c, F, d, mat):
     trC = np.einsum("ij...,ij...->...", F, F)
     mu_e = -g * Om / (3.0 * a) * (G * (trC * s2inv - 3.0) + 3.0 * lam * lnJe)
     return mu_c + mu_e / mat["c_max"]
+
+
+def elastic_potential_slope(c, F, d, mat):
+    """d(mu_e / c_max)/dc at fixed F and d (J/mol per unit c), from the
+    mu_e above with a = 1 + Omega c:
+        d mu_e/dc = g Omega^2 / (3 a^2) [ (5/3) G a^(-2/3) tr C - 3 G
+                                           + 3 lambda (ln J_e + 1) ]."""
+    lam, G = lame(mat["E"], mat["nu"])
+    Om = mat["Omega"]
+    g = (1.0 - d) ** 2
+    a, s2inv = swelling_factors(c, Om)
+    J, _ = det_and_inv_transpose(F)
+    lnJe = np.log(J) - np.log(a)
+    trC = np.einsum("ij...,ij...->...", F, F)
+    dmue = g * Om * Om / (3.0 * a * a) * ((5.0 / 3.0) * G * s2inv * trC - 3.0 * G + 3.0 * lam * (lnJe + 1.0))
+    return dmue / mat["c_max"]
 
 
 def mobility(d, D, RT):
@@ -109,8 +132,10 @@ def potential_slope(c, RT):
 
 
 def fick_step(c_t, F_t, d_t, cdot_B, dt, mat, tol_chem=1e-8, tol_lin=1e-10,
-              max_newton=50, maxit_lin=10000, fixed_lin=None):
-    """Alg. 3: one backward-Euler step.  Returns (c_{t+dt}, stats)."""
+              max_newton=50, maxit_lin=10000, fixed_lin=None, jacobian="mu_c"):
+    """Alg. 3: one backward-Euler step.  Returns (c_{t+dt}, stats).
+    jacobian="mu_c": the paper's linearisation (eq. (45)); "full": also
+    the elastic part of d mu/dc (see the module docstring)."""
     spacing = mat["spacing"]
     Q = flux_coefficient(c_t, F_t, d_t, mat)
     lam = laplacian_symbol(c_t.shape, spacing)
@@ -121,6 +146,10 @@ def fick_step(c_t, F_t, d_t, cdot_B, dt, mat, tol_chem=1e-8, tol_lin=1e-10,
     for it in range(max_newton):
         f = residual(c, c_t, F_t, d_t, cdot_B, dt, mat, Q)
         w = potential_slope(c, mat["RT"])
+        if jacobian == "full":
+            w = w + elastic_potential_slope(c, F_t, d_t, mat)
+            if np.any(w <= 0.0):
+                raise DomainError("d mu / dc <= 0: the full Jacobian is not SPD")
         winv_mean = float(np.mean(1.0 / w))
 
         def B(x):

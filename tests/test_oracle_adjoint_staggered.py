@@ -74,3 +74,41 @@ def test_particle_twin_mass_and_bounds():
         assert abs(c.sum() - c_prev.sum() - w["dt"] * w["cdot_B"].sum()) < 1e-9 * c.sum()
         assert np.all(d >= 0.0) and np.all(d < 1.0)
     assert np.max(H) > 0.0 and np.max(d) > 0.0
+
+
+def test_coupled_chemistry_reduces_to_once_per_step_without_coupling():
+    """With no swelling (Omega = 0) and no damage the mechanics does not
+    depend on c and F stays F_t: solving the chemistry inside the loop gives
+    exactly the concentration of the once-per-step scheme."""
+    w = synth.particle_workload(n=8, n_steps=1, dt=20.0, sigma_max=1e30)
+    w["Omega"] = np.zeros(w["shape"])
+    shape = w["shape"]
+    F0 = mechanics.uniform_field(np.eye(3), shape)
+    args = (F0, w["c0"].copy(), w["d0"].copy(), np.zeros(shape), np.eye(3), np.eye(3), w)
+    _, ca, _, _, sa = staggered.staggered_step(*args, dt=w["dt"], cdot_B=w["cdot_B"])
+    _, cb, _, _, sb = staggered.staggered_step(*args, dt=w["dt"], cdot_B=w["cdot_B"], chemistry="coupled",
+                                               jacobian="full")
+    assert sb["stag_iters"] == 2 and sb["dc_rel"] == 0.0
+    assert np.max(np.abs(ca - cb)) <= 1e-14
+
+
+def test_coupled_chemistry_solves_fick_with_final_fields():
+    """The coupled step's concentration solves the Fick equation (eq. (43))
+    with the step's final F and d (to the Newton and loop tolerances), which
+    the once-per-step scheme's does not (it uses F of the start of the
+    step)."""
+    from oracle import chemistry as ch
+
+    w = synth.particle_workload(n=8, n_steps=1, dt=20.0, sigma_max=1e30)
+    shape = w["shape"]
+    F0 = mechanics.uniform_field(np.eye(3), shape)
+    c_t = w["c0"].copy()
+    args = (F0, c_t.copy(), w["d0"].copy(), np.zeros(shape), np.eye(3), np.eye(3), w)
+    res = {}
+    for mode in (True, "coupled"):
+        F, c, d, H, st = staggered.staggered_step(*args, dt=w["dt"], cdot_B=w["cdot_B"], chemistry=mode,
+                                                  jacobian="full", tol_chem=1e-11)
+        f = ch.residual(c, c_t, F, d, w["cdot_B"], w["dt"], w)
+        res[mode] = np.linalg.norm(f) / np.linalg.norm(c - c_t)
+    assert res["coupled"] <= 1e-9
+    assert res[True] >= 1e3 * res["coupled"]

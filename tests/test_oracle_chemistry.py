@@ -116,3 +116,72 @@ def test_div_grad_is_minus_seven_point_laplacian():
     for ax in range(3):
         lap += (np.roll(v, 1, ax) + np.roll(v, -1, ax) - 2 * v) / sp[ax] ** 2
     assert np.max(np.abs(lhs - lap)) < 1e-12 * np.abs(lap).max()
+
+
+def test_elastic_potential_slope_is_derivative_of_mu_e():
+    """d(mu_e / c_max)/dc of the fully implicit Jacobian against a central
+    difference of mu - mu_c in c, at random finite F, damage and swelling
+    coefficients up to the plate's 1.3."""
+    rng = np.random.default_rng(44)
+    n = 30
+    F = np.eye(3)[:, :, None] + 0.08 * rng.standard_normal((3, 3, n))
+    c = rng.uniform(0.05, 0.9, n)
+    d = rng.uniform(0.0, 0.8, n)
+    w = dict(RT=2478.0, E=rng.uniform(5e9, 3e10, n), nu=rng.uniform(0.2, 0.4, n), Omega=rng.uniform(0.0, 1.3, n),
+             c_max=3e4)
+    h = 1e-6
+    mue = lambda cc: ch.chemical_potential(cc, F, d, w) - w["RT"] * np.log(cc / (1 - cc))
+    fd = (mue(c + h) - mue(c - h)) / (2 * h)
+    slope = ch.elastic_potential_slope(c, F, d, w)
+    assert np.max(np.abs(slope - fd) / (np.abs(fd) + 1e-3 * np.max(np.abs(fd)))) < 1e-6
+
+
+def test_full_jacobian_newton_increment_is_dense_fd_newton_step():
+    """The first increment of the fully implicit Newton step (the dmu-form
+    PCG with d mu/dc including the elastic part) equals the Newton step of
+    the residual of eq. (43) with its Jacobian assembled densely by central
+    differences of that residual (4^3 grid, strong swelling coupling)."""
+    w = chem_work(shape=(4, 4, 4), Omega=1.3)
+    shape = w["shape"]
+    rng = np.random.default_rng(45)
+    w["D"] = 1e-14 * (0.5 + rng.random(shape))
+    c_t = 0.1 + 0.5 * rng.random(shape)
+    F = uniform_field(np.eye(3), shape) + 0.02 * rng.standard_normal((3, 3) + shape)
+    d = 0.3 * rng.random(shape)
+    cdot = 1e-3 * rng.random(shape)
+    dt = 20.0
+    c1, st = ch.fick_step(c_t, F, d, cdot, dt, w, tol_chem=1e30, tol_lin=1e-14, jacobian="full")
+    assert st["newton_iters"] == 1
+    n = c_t.size
+    f0 = ch.residual(c_t, c_t, F, d, cdot, dt, w)
+    J = np.empty((n, n))
+    eps = 1e-7
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = eps
+        e = e.reshape(shape)
+        J[:, k] = ((ch.residual(c_t + e, c_t, F, d, cdot, dt, w) - ch.residual(c_t - e, c_t, F, d, cdot, dt, w))
+                   / (2 * eps)).ravel()
+    dc = np.linalg.solve(J, -f0.ravel()).reshape(shape)
+    assert np.max(np.abs((c1 - c_t) - dc)) < 1e-6 * np.max(np.abs(dc))
+
+
+def test_full_jacobian_same_solution_quadratic_convergence():
+    """Both linearisations solve the same equation f(c) = 0: the fully
+    implicit step lands on the same concentration, in fewer Newton
+    iterations, with quadratic contraction of the increments (swelling
+    coefficient 0.1 at a deformation near the free swelling of c = 0.35;
+    measured 5 Newton iterations against 26)."""
+    w = chem_work(shape=(8, 8, 8), Omega=0.1)
+    shape = w["shape"]
+    rng = np.random.default_rng(46)
+    c_t = 0.2 + 0.3 * rng.random(shape)
+    F = uniform_field(np.eye(3), shape) * (1 + 0.1 * 0.35) ** (1 / 3) + 0.01 * rng.standard_normal((3, 3) + shape)
+    d = 0.2 * rng.random(shape)
+    cdot = np.where(rng.random(shape) < 0.2, 4e-3, 0.0)
+    ca, sa = ch.fick_step(c_t, F, d, cdot, 20.0, w, tol_chem=1e-12, tol_lin=1e-13)
+    cb, sb = ch.fick_step(c_t, F, d, cdot, 20.0, w, tol_chem=1e-12, tol_lin=1e-13, jacobian="full")
+    assert np.max(np.abs(ca - cb)) < 1e-11
+    assert sb["newton_iters"] < sa["newton_iters"]
+    h = sb["dc_history"]
+    assert all(h[k + 1] <= 10.0 * h[k] ** 2 / h[0] for k in range(len(h) - 1) if h[k] > 1e-9)

@@ -126,6 +126,16 @@ fg_status fg_set_state(fg_plan* plan, double* F, double* c, double* d, double* H
 fg_status fg_newton_solve(fg_plan* plan, const double F_macro[9], const fg_solver_opts* opts,
                           fg_stats* stats);
 
+/* Alg. 1 for the shifted equilibrium G*[P(F) - B] = 0 (eqs. (30), (31) with
+ * P replaced by P - B), from the current F: no macroscopic increment is
+ * applied and every correction has zero mean, so <F> is kept.  err_res is
+ * ||G*(P(F) - B)|| normalised by its value at the entry state.  B: device,
+ * 9 N doubles, caller-owned.  With B = P(F0; theta) of a converged state F0
+ * and a perturbed material theta', this is the difference solve of a finite
+ * difference: the base residual cancels exactly, and the solve is accurate
+ * relative to the (small) difference problem.  Errors as fg_newton_solve. */
+fg_status fg_newton_solve_shifted(fg_plan* plan, const double* B, const fg_solver_opts* opts, fg_stats* stats);
+
 /* One Newton correction of Alg. 1 split in two calls, for callers that run
  * the CG iterations of eq. (30) themselves (a stopping rule of their own, or
  * timing the CG loop alone).
@@ -246,6 +256,16 @@ fg_status pff_solve(fg_plan* plan, const fg_solver_opts* opts, fg_stats* stats);
  * FG_E_BREAKDOWN, FG_E_HIP. */
 fg_status fick_step(fg_plan* plan, double dt, const double* cdot_B, const fg_solver_opts* opts,
                     fg_stats* stats);
+
+/* Fully implicit form of fick_step: the same backward-Euler equation
+ * f(c) = 0 (eq. (43)), with the Newton linearisation of eq. (45) extended by
+ * the elastic part of the chemical potential, d mu/dc = RT (1/c + 1/(1-c))
+ * + d(mu_e / c_max)/dc at the stored F and d, so Newton converges
+ * quadratically to the same c (the paper linearises mu_c only).  The
+ * linear step stays SPD PCG in dmu while d mu/dc > 0; a voxel where it is not
+ * returns FG_E_DOMAIN.  Arguments, outputs and errors as fick_step. */
+fg_status fick_step_full(fg_plan* plan, double dt, const double* cdot_B, const fg_solver_opts* opts,
+                         fg_stats* stats);
 
 /* ---------------------------------------------------------------------
  * Batched form of Alg. 1: n_rve RVEs (each with its own grid, spacing and

@@ -707,20 +707,30 @@ double residual_denominator(fg_plan* P, const double Fmacro[9]) {
   return std::max(std::max(std::sqrt(P->hd[1]), 1e-14 * std::sqrt(P->hd[0])), 1e-300);
 }
 
-// P and the tangent state at the current F, and ||G*P|| / den; S64 is left
-// holding the potential U(P) (D U = G*P) that the CG start reuses.
-double newton_residual(fg_plan* P, double den) {
+// P and the tangent state at the current F, and ||G*(P - B)|| (B = 0 when
+// null); S64 is left holding the potential U(P - B) (D U = G*(P - B)) that the
+// CG start reuses.
+double newton_residual_norm(fg_plan* P, const double* B = nullptr) {
   constitutive(P, nullptr, P->S64, P->st, nullptr);
+  if (B) {
+    const long n9 = 9 * P->N;
+    hipLaunchKernelGGL(k_sub_f64, dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, P->S64, B, n9);
+    check_launch();
+  }
   residual_norm(P, 2);
   sync_read(P);
   check_domain(P);
-  return std::sqrt(P->hd[2]) / den;
+  return std::sqrt(P->hd[2]);
 }
+double newton_residual(fg_plan* P, double den) { return newton_residual_norm(P) / den; }
 
 // Newton loop of Alg. 1 at the current F (increment already applied).
-void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stats* stats) {
+// With B, the equation is G*(P(F) - B) = 0 and err_res is normalised by its
+// value at the entry state (Fmacro unused).
+void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stats* stats,
+            const double* B = nullptr) {
   const long n9 = 9 * P->N;
-  const double den = residual_denominator(P, Fmacro);
+  double den = B ? 0.0 : residual_denominator(P, Fmacro);
   int it = 0;
   if (stats) {
     stats->newton_iters = 0;
@@ -728,7 +738,9 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
     stats->n_history = 0;
   }
   while (true) {
-    const double err = newton_residual(P, den);
+    const double rn = newton_residual_norm(P, B);
+    if (B && it == 0) den = (rn > 0.0) ? rn : 1.0;
+    const double err = rn / den;
     if (stats) {
       if (stats->n_history < 64) stats->err_history[stats->n_history] = err;
       stats->n_history += 1;
@@ -980,7 +992,8 @@ void pff(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
   FG_HIP(hipMemcpyAsync(P->d, v.x, P->N * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
 }
 
-void fick(fg_plan* P, double dt, const double* cdot, const fg_solver_opts* o, fg_stats* stats) {
+void fick(fg_plan* P, double dt, const double* cdot, const fg_solver_opts* o, fg_stats* stats,
+          int full_jacobian = 0) {
   if (!P->c || !P->D) throw Status(FG_E_STATE, "fick_step needs c and D");
   ScalarVecs v = scalar_vecs(P);
   const long N = P->N;
@@ -1003,7 +1016,7 @@ void fick(fg_plan* P, double dt, const double* cdot, const fg_solver_opts* o, fg
   }
   for (int it = 0; it < o->max_newton; ++it) {
     hipLaunchKernelGGL(k_fick_mu, dim3(nbN), dim3(256), 0, P->stream, P->c, P->F, d, P->E, P->nu, P->Om, P->RT,
-                       P->cmax, v.mu, v.w, P->part, P->flags, N);
+                       P->cmax, v.mu, v.w, P->part, P->flags, N, full_jacobian);
     check_launch();
     reduce_to(P, P->part, (int)nbN, 2);  // sum 1/w
     hipLaunchKernelGGL(k_fick_residual, dim3(nbN), dim3(256), 0, P->stream, P->c, v.ct, v.mu, v.A6, cdot, dt, g,
@@ -1209,6 +1222,17 @@ fg_status fg_newton_solve(fg_plan* P, const double F_macro[9], const fg_solver_o
     if (stats) std::memset(stats, 0, sizeof(fg_stats));
     apply_macro(P, F_macro);
     newton(P, F_macro, opts, stats);
+    FG_HIP(hipStreamSynchronize(P->stream));
+  });
+}
+
+fg_status fg_newton_solve_shifted(fg_plan* P, const double* B, const fg_solver_opts* opts, fg_stats* stats) {
+  if (!P || !B || !opts) return FG_E_ARG;
+  if (opts->max_lin <= 0 && opts->fixed_lin <= 0) return FG_E_ARG;
+  return run(P, [&]() {
+    need_ready(P, true);
+    if (stats) std::memset(stats, 0, sizeof(fg_stats));
+    newton(P, nullptr, opts, stats, B);
     FG_HIP(hipStreamSynchronize(P->stream));
   });
 }
@@ -1436,6 +1460,16 @@ fg_status fick_step(fg_plan* P, double dt, const double* cdot_B, const fg_solver
     need_ready(P, true);
     if (stats) std::memset(stats, 0, sizeof(fg_stats));
     fick(P, dt, cdot_B, opts, stats);
+    FG_HIP(hipStreamSynchronize(P->stream));
+  });
+}
+
+fg_status fick_step_full(fg_plan* P, double dt, const double* cdot_B, const fg_solver_opts* opts, fg_stats* stats) {
+  if (!P || !opts || !(dt > 0)) return FG_E_ARG;
+  return run(P, [&]() {
+    need_ready(P, true);
+    if (stats) std::memset(stats, 0, sizeof(fg_stats));
+    fick(P, dt, cdot_B, opts, stats, 1);
     FG_HIP(hipStreamSynchronize(P->stream));
   });
 }

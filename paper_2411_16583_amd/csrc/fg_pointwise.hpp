@@ -318,6 +318,12 @@ __global__ void __launch_bounds__(256) k_axpy_into_f64(double* __restrict__ F, c
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) F[i] += (double)x[i];
 }
 
+// a -= b (double precision), n values.
+__global__ void __launch_bounds__(256) k_sub_f64(double* __restrict__ a, const double* __restrict__ b, long n) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] -= b[i];
+}
+
 // F_k += dF_k for a uniform 3x3 increment per batch item (dF: 9 per item).
 __global__ void __launch_bounds__(256) k_add_uniform9(double* __restrict__ F, const double* __restrict__ dF, long N,
                                                       long Ntot) {

@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256)
 k_fick_mu(const double* __restrict__ c, const double* __restrict__ F, const double* __restrict__ d,
           const double* __restrict__ E, const double* __restrict__ nu, const double* __restrict__ Om, double RT,
           double cmax, double* __restrict__ mu, double* __restrict__ w, double* __restrict__ part_winv, int* flags,
-          long N) {
+          long N, int full_jacobian) {
   __shared__ double red[16];
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double wi = 0.0;
@@ -231,7 +231,16 @@ k_fick_mu(const double* __restrict__ c, const double* __restrict__ F, const doub
     const double lnJe = log(J) - la;
     const double mue = -g * oo / (3.0 * a) * (G * (trC * s2inv - 3.0) + 3.0 * lam * lnJe);
     mu[i] = RT * log(cc / (1.0 - cc)) + mue / cmax;
-    const double ww = RT * (1.0 / cc + 1.0 / (1.0 - cc));
+    double ww = RT * (1.0 / cc + 1.0 / (1.0 - cc));
+    if (full_jacobian) {
+      // d(mu_e / cmax)/dc at fixed F and d:
+      // g Omega^2 / (3 a^2) [ (5/3) G a^(-2/3) tr C - 3 G + 3 lambda (ln J_e + 1) ] / cmax
+      ww += g * oo * oo / (3.0 * a * a) * ((5.0 / 3.0) * G * s2inv * trC - 3.0 * G + 3.0 * lam * (lnJe + 1.0)) / cmax;
+      if (!(ww > 0.0)) {
+        flags[0] = FG_FLAG_DOMAIN;  // the linear step would not be SPD
+        ww = RT * (1.0 / cc + 1.0 / (1.0 - cc));
+      }
+    }
     w[i] = ww;
     wi = 1.0 / ww;
   }

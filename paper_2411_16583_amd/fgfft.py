@@ -23,9 +23,9 @@ PRECISIONS = {"fp64": FG_FP64, "mixed": FG_MIXED}
 # Every function declared in include/fgfft.h.
 EXPORTED = [
     "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
-    "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_newton_linear_begin", "fg_cg_iterate",
+    "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_newton_solve_shifted", "fg_newton_linear_begin", "fg_cg_iterate",
     "fg_adjoint_gradient", "fg_residual", "fg_homogenized_stress", "fg_stress",
-    "fg_apply_operator", "fg_project", "fg_project_noalloc", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step",
+    "fg_apply_operator", "fg_project", "fg_project_noalloc", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step", "fick_step_full",
     "fg_batch_create", "fg_batch_workspace_bytes", "fg_batch_groups", "fg_batch_set_workspace",
     "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
     "fg_batch_plan", "fg_batch_group_info", "fg_batch_set_schedule", "fg_plan_tile_candidates", "fg_plan_set_tiles", "fg_plan_get_tiles",
@@ -100,6 +100,7 @@ def load_library(path=LIB_PATH):
         "fg_set_state": ([vp, dptr, dptr, dptr, dptr], c_int),
         "fg_apply_macro": ([vp, ctypes.POINTER(c_double)], c_int),
         "fg_newton_solve": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
+        "fg_newton_solve_shifted": ([vp, dptr, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
         "fg_newton_linear_begin": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
         "fg_cg_iterate": ([vp, c_int, c_int, ctypes.POINTER(Stats)], c_int),
         "fg_adjoint_gradient": ([vp, ctypes.POINTER(c_double), dptr, dptr, ctypes.POINTER(SolverOpts),
@@ -115,6 +116,7 @@ def load_library(path=LIB_PATH):
         "fg_fft_c2r": ([vp, dptr, c_int], c_int),
         "pff_solve": ([vp, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
         "fick_step": ([vp, c_double, dptr, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
+        "fick_step_full": ([vp, c_double, dptr, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
         "fg_profile_begin": ([vp], c_int),
         "fg_profile_passes": ([vp, ctypes.c_uint], c_int),
         "fg_profile_end": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(ctypes.c_long)], c_int),
@@ -251,6 +253,14 @@ class Plan:
         d["status"] = st
         return d
 
+    def newton_solve_shifted(self, B, opts=None):
+        """Newton on G*(P(F) - B) = 0 from the current F (difference solves)."""
+        opts = opts or make_opts()
+        stats = Stats()
+        self._check(self.lib.fg_newton_solve_shifted(self.handle, _ptr(B), ctypes.byref(opts), ctypes.byref(stats)),
+                    "fg_newton_solve_shifted")
+        return stats.to_dict()
+
     def newton_linear_begin(self, F_macro):
         """P, tangent and the CG right-hand side of one Newton correction at
         the current F; returns err_res (eq. (31))."""
@@ -356,11 +366,14 @@ class Plan:
         self._check(self.lib.fg_profile_end(self.handle, ms, cnt), "fg_profile_end")
         return {name: (ms[k], cnt[k]) for k, name in enumerate(PASS_NAMES)}
 
-    def fick_step(self, dt, cdot_B=None, opts=None, raise_on_error=True):
+    def fick_step(self, dt, cdot_B=None, opts=None, raise_on_error=True, jacobian="mu_c"):
+        """Alg. 3 (jacobian="mu_c", the paper's linearisation) or its fully
+        implicit form (jacobian="full", fick_step_full)."""
         opts = opts or make_opts()
         stats = Stats()
         self._keep["cdot_B"] = cdot_B
-        st = self.lib.fick_step(self.handle, float(dt), _ptr(cdot_B), ctypes.byref(opts), ctypes.byref(stats))
+        fn = self.lib.fick_step_full if jacobian == "full" else self.lib.fick_step
+        st = fn(self.handle, float(dt), _ptr(cdot_B), ctypes.byref(opts), ctypes.byref(stats))
         if raise_on_error:
             self._check(st, "fick_step")
         d = stats.to_dict()

@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--coupled", action="store_true",
                     help="the coupled path instead: staggered steps (Fick, Newton-CG, phase field) of the 128^3 "
                          "particle workload, FP64 and mixed")
+    ap.add_argument("--chemistry", choices=["once", "coupled"], default="once",
+                    help="--coupled: chemistry once per step (the paper) or inside the staggered loop")
+    ap.add_argument("--jacobian", choices=["mu_c", "full"], default="mu_c",
+                    help="--coupled: Fick Newton linearisation of the paper (mu_c) or fully implicit")
     ap.add_argument("--batch-items", type=int, default=48)
     ap.add_argument("--graph-ticks", type=int, default=16)
     ap.add_argument("--newton-every", type=int, default=4,
@@ -453,18 +457,20 @@ def run_coupled(args):
         c, d, H = t(work["c0"]), t(work["d0"]), torch.zeros(shape, dtype=torch.float64, device=dev)
         plan.set_state(F, c, d, H)
         cdot = t(work["cdot_B"])
-        kw = dict(dt=work["dt"], cdot_B=cdot, chemistry=True)
+        kw = dict(dt=work["dt"], cdot_B=cdot, chemistry=True if args.chemistry == "once" else "coupled",
+                  jacobian=args.jacobian)
         for k in range(args.warmup):
             staggered_step(plan, work["loads"][k], **kw)
         torch.cuda.synchronize()
         plan.profile_begin()
-        cg = pcg = chem = stag = 0
+        cg = pcg = chem = stag = chem_newton = 0
         t0 = time.perf_counter()
         for k in range(args.warmup, args.warmup + args.steps):
             st = staggered_step(plan, work["loads"][k], **kw)
             cg += sum(s_["lin_iters_total"] for s_ in st["newton"])
             pcg += sum(s_["lin_iters_last"] for s_ in st["pff"])
-            chem += st["chem"]["lin_iters_total"]
+            chem += sum(ch_["lin_iters_total"] for ch_ in (st["chem_coupled"] or [st["chem"]]))
+            chem_newton += sum(ch_["newton_iters"] for ch_ in (st["chem_coupled"] or [st["chem"]]))
             stag += st["stag_iters"]
             print(f"[coupled {form}] step {k + 1}: staggered {st['stag_iters']}, newton CG "
                   f"{[s_['lin_iters_total'] for s_ in st['newton']]}, pff {[s_['lin_iters_last'] for s_ in st['pff']]}, "
@@ -473,7 +479,7 @@ def run_coupled(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = plan.profile_end()
-        res[form] = dict(elapsed=el, cg=cg, pcg=pcg, chem=chem, stag=stag, prof=prof)
+        res[form] = dict(elapsed=el, cg=cg, pcg=pcg, chem=chem, chem_newton=chem_newton, stag=stag, prof=prof)
         fields[form] = (c.cpu().numpy(), d.cpu().numpy(), F.cpu().numpy())
         plan.close()
         del F, c, d, H, mats, cdot
@@ -502,8 +508,9 @@ def run_coupled(args):
         "data": "synthetic",
         "config": {"workload": f"particle {n}^3 (ellipsoid 40/32/28 voxels at 128^3, buffer 1e-3 E), flux "
                                f"4e-10 m/s on the inner shell, dt = {work['dt']} s, Omega = 0.03, sigma_max = 20 MPa",
-                   "voxels": N},
+                   "voxels": N, "chemistry": args.chemistry, "fick_jacobian": args.jacobian},
         "fp64": dict(cg_iters=f64["cg"], pff_pcg_iters=f64["pcg"], fick_pcg_iters=f64["chem"],
+                     fick_newton_iters=f64["chem_newton"],
                      staggered_iters=f64["stag"], per_class=per_class(f64["prof"], N, 8),
                      voxel_cg_iters_per_s=N * f64["cg"] / f64["elapsed"]),
         "mixed": dict(ms_per_step=1e3 * mx["elapsed"] / args.steps, cg_iters=mx["cg"], pff_pcg_iters=mx["pcg"],

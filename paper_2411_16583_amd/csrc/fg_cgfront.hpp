@@ -50,6 +50,18 @@ template <typename R, int W, typename PV> __device__ __forceinline__ void pk_str
   __builtin_nontemporal_store(a, reinterpret_cast<nvw*>(p));
 }
 
+// nontemporal load of a W-vector (streams read once: the tangent state and
+// the solution potential), so that they do not push the stencil's neighbour
+// lines of rho and pi out of the caches
+template <typename R, int W, typename PV> __device__ __forceinline__ PV pk_load_nt(const PV* p) {
+  typedef R nvw __attribute__((ext_vector_type(W)));
+  const nvw a = __builtin_nontemporal_load(reinterpret_cast<const nvw*>(p));
+  PV v;
+#pragma unroll
+  for (int w = 0; w < W; ++w) pk_set<R>(v, w, a[w]);
+  return v;
+}
+
 template <int M> struct FrontShape {
   static constexpr int T = Line<M>::T;
   static constexpr int LB = (16 / T) > 0 ? (16 / T) : 1;  // lines per workgroup
@@ -143,7 +155,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
             for (int q = 0; q <= W; ++q) u[a][b][q] += beta * uo[a][b][q];
         // deferred solution update at the thread's own voxels
         PV* xv = reinterpret_cast<PV*>(xbuf + c * N) + g;
-        PV xo = *xv;
+        PV xo = pk_load_nt<R, W>(xv);
 #pragma unroll
         for (int w = 0; w < W; ++w) pk_set<R>(xo, w, pk_get<R>(xo, w) + alpha * uo[0][0][w + 1]);
         pk_stream<R, W>(xv, xo);
@@ -161,8 +173,9 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
     }
     PV A[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) A[k] = sv[k * Nw + g];
-    const PV al = sv[9 * Nw + g], be = sv[10 * Nw + g], ga = sv[11 * Nw + g];
+    for (int k = 0; k < 9; ++k) A[k] = pk_load_nt<R, W>(sv + k * Nw + g);
+    const PV al = pk_load_nt<R, W>(sv + 9 * Nw + g), be = pk_load_nt<R, W>(sv + 10 * Nw + g),
+             ga = pk_load_nt<R, W>(sv + 11 * Nw + g);
 #pragma unroll
     for (int w = 0; w < W; w += 2) {
       R A0[9], A1[9], Y0[9], Y1[9];

@@ -114,3 +114,69 @@ def mean_stress(F, c, d, mat):
     """Homogenised (voxel-mean) first Piola-Kirchhoff stress <P>."""
     P = stress(F, c, d, mat["E"], mat["nu"], mat["Omega"])
     return P.reshape(3, 3, -1).mean(axis=-1)
+
+
+def homogenized_tangent(F, c, d, mat, W, tol_lin=1e-12, maxit=20000):
+    """The homogenised tangent applied to a macroscopic direction W (3x3):
+    d<P>/dFbar : W at the converged state F.  A uniform change W of Fbar
+    changes the fluctuation by the compatible, zero-mean dF solving the
+    linearised equilibrium of eq. (30),
+        G*(K : dF) = -G*(K : W),
+    and then d<P> = <K : (W + dF)>.  Returns (3x3 array, CG iterations)."""
+    spacing = mat["spacing"]
+    shape = F.shape[2:]
+    K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+    Wf = uniform_field(W, shape)
+    b = -project(project(apply_tangent(K, Wf), spacing), spacing)
+    dF, it, _ = cg(lambda X: operator(K, X, spacing), b, tol_lin, maxit)
+    T = apply_tangent(K, Wf + dF)
+    return T.reshape(3, 3, -1).mean(axis=-1), it
+
+
+def project_mixed(A, mask, spacing):
+    """Projection of the mixed macroscopic control: the compatibility
+    projection of eq. (28) on the fluctuation, plus, at zero frequency, the
+    mean of the stress-controlled components (mask: 3x3 booleans, True where
+    <P>_ij is prescribed and Fbar_ij is free).  Idempotent and symmetric,
+    like the projection itself."""
+    shape = A.shape[2:]
+    m = np.asarray(mask, dtype=np.float64).reshape(3, 3, 1, 1, 1)
+    mean = A.reshape(3, 3, -1).mean(axis=-1).reshape(3, 3, 1, 1, 1)
+    return project(A, spacing) + np.broadcast_to(m * mean, (3, 3) + tuple(shape))
+
+
+def newton_solve_mixed(F, Fbar, mask, Pbar, c, d, mat, spacing, tol_newton=1e-8, tol_lin=1e-10, max_newton=50,
+                       max_lin=20000):
+    """Alg. 1 under mixed macroscopic control (Sec. 3.1: Fbar prescribed in
+    some components, <P> in the others; reading of the cited mixed-control
+    approach as the zero-frequency extension of the projection): the mean of
+    F is Fbar where mask is False (the caller's F already has it) and free
+    where mask is True; there <P> = Pbar is required.  Residual
+        R = G_m*(P) - mask Pbar,   G_m = project_mixed,
+    normalised by its value at the entry state; Newton with CG on
+    X -> G_m*(K : X) (self-adjoint on the range of G_m).  Returns (F, stats)."""
+    m = np.asarray(mask, dtype=np.float64).reshape(3, 3, 1, 1, 1)
+    target = m * np.asarray(Pbar, dtype=np.float64).reshape(3, 3, 1, 1, 1)
+    shape = F.shape[2:]
+    lin_iters, errs = [], []
+    den = None
+    it = 0
+    while True:
+        P = stress(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+        R = project_mixed(P, mask, spacing) - np.broadcast_to(target, (3, 3) + tuple(shape))
+        nr = norm(R)
+        if den is None:
+            den = max(nr, 1e-14 * norm(P), 1e-300)
+        err = nr / den
+        errs.append(err)
+        if err <= tol_newton:
+            break
+        if it >= max_newton:
+            raise NoConvergence("mixed-control Newton did not converge")
+        b = -project_mixed(R, mask, spacing)
+        K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+        dF, n, _ = cg(lambda X: project_mixed(apply_tangent(K, X), mask, spacing), b, tol_lin, max_lin)
+        lin_iters.append(n)
+        F = F + dF
+        it += 1
+    return F, dict(newton_iters=it, lin_iters=lin_iters, err_history=errs, den=den)

@@ -157,3 +157,106 @@ def test_effective_stiffness_bounds_and_symmetry():
         e = rng.standard_normal(6)
         q = e @ Ceff @ e
         assert e @ reuss @ e * (1 - 1e-6) <= q <= e @ voigt @ e * (1 + 1e-6)
+
+
+def _converged(work, Fbar, tol=1e-13):
+    shape = work["shape"]
+    F = mechanics.uniform_field(Fbar, shape)
+    F, _ = mechanics.newton_solve(F, Fbar, work["c0"], work["d0"], work, work["spacing"], tol_newton=tol,
+                                  tol_lin=1e-13)
+    return F
+
+
+def test_homogenized_tangent_matches_finite_differences_and_is_symmetric():
+    """d<P>/dFbar : W by one linearised solve equals the central difference
+    of <P> between two converged Newton solves at Fbar +- h W, and
+    W1 : C_eff : W2 = W2 : C_eff : W1 (major symmetry at equilibrium)."""
+    work = small_two_phase(shape=(6, 4, 8), seed=22)
+    Fbar = np.eye(3) + np.array([[0.01, 0.002, 0.0], [0.0, -0.004, 0.001], [0.003, 0.0, 0.006]])
+    F = _converged(work, Fbar)
+    rng = np.random.default_rng(23)
+    W1, W2 = rng.standard_normal((3, 3)), rng.standard_normal((3, 3))
+    T1, _ = mechanics.homogenized_tangent(F, work["c0"], work["d0"], work, W1)
+    T2, _ = mechanics.homogenized_tangent(F, work["c0"], work["d0"], work, W2)
+    h = 1e-6
+    Pp = mechanics.mean_stress(_converged(work, Fbar + h * W1), work["c0"], work["d0"], work)
+    Pm = mechanics.mean_stress(_converged(work, Fbar - h * W1), work["c0"], work["d0"], work)
+    fd = (Pp - Pm) / (2 * h)
+    assert np.max(np.abs(T1 - fd)) <= 1e-6 * np.max(np.abs(fd))
+    assert abs(np.sum(W1 * T2) - np.sum(W2 * T1)) <= 1e-10 * abs(np.sum(W1 * T2))
+
+
+def test_homogenized_tangent_of_homogeneous_cell_is_local_tangent():
+    shape = (4, 6, 4)
+    work = synth.homogeneous_workload(shape, 1.0, E=30e9, nu=0.27, Omega=0.02)
+    work["c0"] = np.full(shape, 0.4)
+    work["d0"] = np.full(shape, 0.1)
+    Fbar = np.eye(3) + np.array([[0.02, 0.0, 0.01], [0.0, -0.01, 0.0], [0.005, 0.0, 0.01]])
+    F = mechanics.uniform_field(Fbar, shape)
+    W = np.arange(9.0).reshape(3, 3) / 10.0
+    T, it = mechanics.homogenized_tangent(F, work["c0"], work["d0"], work, W)
+    K = cm.tangent(F[:, :, :1, :1, :1], work["c0"][:1, :1, :1], work["d0"][:1, :1, :1], work["E"][:1, :1, :1],
+                   work["nu"][:1, :1, :1], work["Omega"][:1, :1, :1])
+    ref = (K.reshape(9, 9) @ W.reshape(9)).reshape(3, 3)
+    assert it == 0
+    assert np.max(np.abs(T - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_mixed_projection_is_symmetric_idempotent():
+    shape, sp = (4, 6, 4), (0.3, 0.2, 0.25)
+    rng = np.random.default_rng(24)
+    mask = np.zeros((3, 3), bool)
+    mask[1, 1] = mask[2, 2] = mask[0, 2] = True
+    A, B = rng.standard_normal((3, 3) + shape), rng.standard_normal((3, 3) + shape)
+    GA = mechanics.project_mixed(A, mask, sp)
+    assert np.max(np.abs(mechanics.project_mixed(GA, mask, sp) - GA)) <= 1e-13 * np.max(np.abs(GA))
+    assert abs(np.sum(GA * B) - np.sum(A * mechanics.project_mixed(B, mask, sp))) <= 1e-12 * np.sum(np.abs(GA * B))
+    # the strain-controlled components keep zero mean
+    m = GA.reshape(3, 3, -1).mean(-1)
+    assert np.max(np.abs(m[~mask])) <= 1e-14 * np.max(np.abs(GA))
+
+
+def test_mixed_control_homogeneous_uniaxial_stress_exact():
+    """Uniform material, Fbar_11 = 1.01 prescribed, <P>_22 = <P>_33 = 0
+    (other components strain-controlled at the identity): the solution is
+    the uniform F = diag(1.01, s, s) with P_22(s) = 0 of the Neo-Hookean
+    law, from a scalar Newton written here from P = G F + (lam ln J - G) F^-T."""
+    shape = (4, 4, 6)
+    E, nu = 20e9, 0.3
+    work = synth.homogeneous_workload(shape, 1.0, E=E, nu=nu)
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    G = E / (2 * (1 + nu))
+    s = 1.0
+    for _ in range(60):
+        f = G * s + (lam * np.log(1.01 * s * s) - G) / s
+        df = G + (2 * lam / s) / s - (lam * np.log(1.01 * s * s) - G) / s ** 2
+        s -= f / df
+    mask = np.zeros((3, 3), bool)
+    mask[1, 1] = mask[2, 2] = True
+    Fbar = np.diag([1.01, 1.0, 1.0])
+    F, st = mechanics.newton_solve_mixed(mechanics.uniform_field(Fbar, shape), Fbar, mask, np.zeros((3, 3)),
+                                         work["c0"], work["d0"], work, work["spacing"], tol_newton=1e-13)
+    exact = mechanics.uniform_field(np.diag([1.01, s, s]), shape)
+    assert np.max(np.abs(F - exact)) <= 1e-13
+    Pm = mechanics.mean_stress(F, work["c0"], work["d0"], work)
+    assert abs(Pm[1, 1]) <= 1e-3 and abs(Pm[2, 2]) <= 1e-3  # Pa, against P_11 ~ 2e8
+
+
+def test_mixed_control_recovers_the_strain_controlled_state():
+    """Solve with Fbar* prescribed, record <P>*; then prescribe <P>_22, <P>_33
+    = <P>*_22, <P>*_33 with Fbar_22 = Fbar_33 = 1 as the start: the mixed
+    solve lands on Fbar* and on the same field."""
+    work = small_two_phase(shape=(6, 4, 8), seed=25)
+    Fs = np.eye(3) + np.diag([0.008, -0.003, 0.002])
+    Fs[0, 1] = 0.001
+    F1 = _converged(work, Fs)
+    P1 = mechanics.mean_stress(F1, work["c0"], work["d0"], work)
+    mask = np.zeros((3, 3), bool)
+    mask[1, 1] = mask[2, 2] = True
+    F0 = Fs.copy()
+    F0[1, 1] = F0[2, 2] = 1.0
+    F2, st = mechanics.newton_solve_mixed(mechanics.uniform_field(F0, work["shape"]), F0, mask, P1, work["c0"],
+                                          work["d0"], work, work["spacing"], tol_newton=1e-13, tol_lin=1e-13)
+    fl = F1 - mechanics.uniform_field(Fs, work["shape"])
+    assert np.max(np.abs(F2.reshape(3, 3, -1).mean(-1) - Fs)) <= 1e-12
+    assert np.max(np.abs(F2 - F1)) <= 1e-10 * np.max(np.abs(fl))

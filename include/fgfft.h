@@ -181,6 +181,21 @@ fg_status fg_apply_macro(fg_plan* plan, const double F_macro[9]);
 fg_status fg_adjoint_gradient(fg_plan* plan, const double dL_dPavg[9], double* dL_dlogE, double* dL_dOmega,
                               const fg_solver_opts* opts, fg_stats* stats);
 
+/* Homogenised tangent of the current, converged state applied to a
+ * macroscopic direction W (host, 9 doubles): T_out = d<P>/dFbar : W (host,
+ * 9 doubles).  A uniform change W of Fbar changes the fluctuation by the
+ * compatible, zero-mean dF solving the linearised equilibrium of eq. (30),
+ * G*(K : dF) = -G*(K : W) (one CG solve with the operator of the Newton
+ * step, to ||r|| <= opts->tol_lin ||b||), and T_out = <K : (W + dF)>.  By the
+ * major symmetry of K this is the adjoint system of fg_adjoint_gradient with
+ * dL_dPavg = W, and mixed plans refine it in double precision the same way.
+ * Used for mixed macroscopic stress/strain control (the Jacobian of the
+ * prescribed stress components with respect to the free strain components)
+ * and for effective stiffnesses.  stats as fg_adjoint_gradient.  Errors:
+ * FG_E_STATE, FG_E_NOCONV, FG_E_BREAKDOWN, FG_E_DOMAIN, FG_E_HIP. */
+fg_status fg_homogenized_tangent(fg_plan* plan, const double W[9], double T_out[9], const fg_solver_opts* opts,
+                                 fg_stats* stats);
+
 /* Equilibrium residual of the current state (eq. (31)) with respect to the
  * macroscopic F_macro (host, 9 doubles): *err_res (host).  Synchronises. */
 fg_status fg_residual(fg_plan* plan, const double F_macro[9], double* err_res);

@@ -786,8 +786,25 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
 // Adjoint of L = sum W_ij <P_ij> at the current (converged) state: solve
 // G(K:lam) = -G(K:W) for the compatible, zero-mean lam with the same CG (lam
 // = D xi), then the per-voxel gradients with respect to log E and Omega.
+// <K : (W + lam)> of the adjoint solution lam into Tout (host, 9): the
+// homogenised tangent applied to W (d<P>/dFbar : W), by the major symmetry
+// of K the same linear solve as the adjoint.
+void tangent_mean(fg_plan* P, const double* lam, double* Tout) {
+  const long N = P->N;
+  const double* c = P->c ? P->c : P->zeroN;
+  const double* d = P->d ? P->d : P->zeroN;
+  hipLaunchKernelGGL(k_tangent_apply_f64, dim3(blocks_for(N)), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu,
+                     P->Om, (const double*)P->Fu, lam, P->S64, P->flags, N);
+  check_launch();
+  mean9(P, P->S64);
+  sync_read(P);
+  check_domain(P);
+  for (int k = 0; k < 9; ++k) Tout[k] = P->hd[8 + k] / (double)N;
+}
+
 template <typename T>
-void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_solver_opts* o, fg_stats* stats) {
+void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_solver_opts* o, fg_stats* stats,
+             double* Tout = nullptr) {
   const long N = P->N;
   T* S = (T*)P->S;
   T* pbuf = (T*)P->p;
@@ -812,9 +829,12 @@ void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_sol
   cg_result<double>(P, lam, nullptr);
   const double* c = P->c ? P->c : P->zeroN;
   const double* d = P->d ? P->d : P->zeroN;
-  hipLaunchKernelGGL((k_adjoint_grad<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu,
-                     P->Om, (const T*)lam, (const double*)P->Fu, gE, gO, P->flags, N);
-  check_launch();
+  if (gE || gO) {
+    hipLaunchKernelGGL((k_adjoint_grad<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu,
+                       P->Om, (const T*)lam, (const double*)P->Fu, gE, gO, P->flags, N);
+    check_launch();
+  }
+  if (Tout) tangent_mean(P, lam, Tout);
   sync_read(P);
   check_domain(P);
 }
@@ -827,7 +847,7 @@ void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_sol
 // when ||R_k|| <= tol_lin ||R_0||, the criterion of the double-precision CG.
 // lam lives in the (otherwise unused) scalar-solver area.
 void adjoint_mixed(fg_plan* P, const double W[9], double* gE, double* gO, const fg_solver_opts* o,
-                   fg_stats* stats) {
+                   fg_stats* stats, double* Tout = nullptr) {
   const long N = P->N, n9 = 9 * N;
   double* lam = P->sc;
   const double* c = P->c ? P->c : P->zeroN;
@@ -878,9 +898,12 @@ void adjoint_mixed(fg_plan* P, const double W[9], double* gE, double* gO, const 
     stats->lin_iters_last = stats->lin_iters_total;
     stats->lin_relres = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
   }
-  hipLaunchKernelGGL((k_adjoint_grad<double>), dim3(nbN), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu, P->Om,
-                     (const double*)lam, (const double*)P->Fu, gE, gO, P->flags, N);
-  check_launch();
+  if (gE || gO) {
+    hipLaunchKernelGGL((k_adjoint_grad<double>), dim3(nbN), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu, P->Om,
+                       (const double*)lam, (const double*)P->Fu, gE, gO, P->flags, N);
+    check_launch();
+  }
+  if (Tout) tangent_mean(P, lam, Tout);
   sync_read(P);
   check_domain(P);
 }
@@ -1311,6 +1334,20 @@ fg_status fg_adjoint_gradient(fg_plan* P, const double dL_dPavg[9], double* dL_d
       adjoint<double>(P, dL_dPavg, dL_dlogE, dL_dOmega, opts, stats);
     else
       adjoint_mixed(P, dL_dPavg, dL_dlogE, dL_dOmega, opts, stats);
+    FG_HIP(hipStreamSynchronize(P->stream));
+  });
+}
+
+fg_status fg_homogenized_tangent(fg_plan* P, const double W[9], double T_out[9], const fg_solver_opts* opts,
+                                 fg_stats* stats) {
+  if (!P || !W || !T_out || !opts) return FG_E_ARG;
+  return run(P, [&]() {
+    need_ready(P, true);
+    if (stats) std::memset(stats, 0, sizeof(fg_stats));
+    if (P->prec == FG_FP64)
+      adjoint<double>(P, W, nullptr, nullptr, opts, stats, T_out);
+    else
+      adjoint_mixed(P, W, nullptr, nullptr, opts, stats, T_out);
     FG_HIP(hipStreamSynchronize(P->stream));
   });
 }

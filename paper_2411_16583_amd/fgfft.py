@@ -24,7 +24,7 @@ PRECISIONS = {"fp64": FG_FP64, "mixed": FG_MIXED}
 EXPORTED = [
     "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
     "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_newton_solve_shifted", "fg_newton_linear_begin", "fg_cg_iterate",
-    "fg_adjoint_gradient", "fg_residual", "fg_homogenized_stress", "fg_stress",
+    "fg_adjoint_gradient", "fg_homogenized_tangent", "fg_residual", "fg_homogenized_stress", "fg_stress",
     "fg_apply_operator", "fg_project", "fg_project_noalloc", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step", "fick_step_full",
     "fg_batch_create", "fg_batch_workspace_bytes", "fg_batch_groups", "fg_batch_set_workspace",
     "fg_batch_set_material", "fg_batch_newton_solve", "fg_batch_state", "fg_batch_last_error", "fg_batch_destroy",
@@ -105,6 +105,8 @@ def load_library(path=LIB_PATH):
         "fg_cg_iterate": ([vp, c_int, c_int, ctypes.POINTER(Stats)], c_int),
         "fg_adjoint_gradient": ([vp, ctypes.POINTER(c_double), dptr, dptr, ctypes.POINTER(SolverOpts),
                                  ctypes.POINTER(Stats)], c_int),
+        "fg_homogenized_tangent": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                    ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats)], c_int),
         "fg_residual": ([vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
         "fg_homogenized_stress": ([vp, ctypes.POINTER(c_double)], c_int),
         "fg_stress": ([vp, dptr], c_int),
@@ -286,6 +288,16 @@ class Plan:
         self._check(self.lib.fg_adjoint_gradient(self.handle, p, _ptr(g_logE), _ptr(g_Omega), ctypes.byref(opts),
                                                  ctypes.byref(stats)), "fg_adjoint_gradient")
         return stats.to_dict()
+
+    def homogenized_tangent(self, W, opts=None):
+        """d<P>/dFbar : W at the current converged state (3x3 array)."""
+        opts = opts or make_opts()
+        a, p = _mat9(W)
+        out = (ctypes.c_double * 9)()
+        stats = Stats()
+        self._check(self.lib.fg_homogenized_tangent(self.handle, p, out, ctypes.byref(opts), ctypes.byref(stats)),
+                    "fg_homogenized_tangent")
+        return np.array(out[:]).reshape(3, 3)
 
     def apply_macro(self, F_macro):
         a, p = _mat9(F_macro)

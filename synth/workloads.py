@@ -42,6 +42,7 @@ __all__ = [
     "inclusion_workload",
     "particle_workload",
     "polydisperse_workload",
+    "polydisperse_window",
     "batch_workloads",
     "grf_workload",
     "homogeneous_workload",
@@ -170,6 +171,30 @@ def polydisperse_workload(n=256, n_spheres=60, n_inc=20, total_strain=0.05,
         loads=uniaxial_schedule(total_strain, n_inc),
         tol_newton=1e-8, tol_lin=1e-10,
     )
+
+
+def polydisperse_window(n=48, pair=(12, 55), strength_ratio=0.04, n_inc=20, total_strain=0.05):
+    """An n^3 window of the 256^3 polydisperse microstructure (same voxels,
+    same materials, same load ramp), centred on the surface gap between the
+    two given spheres (by default the gap most aligned with the stretch
+    axis among the narrowest, where damage starts), taken as a periodic cell
+    of its own: the full-resolution twin of the damage ramp."""
+    full = polydisperse_workload(n=256, strength_ratio=strength_ratio, n_inc=n_inc, total_strain=total_strain)
+    C, R = full["centres"], full["radii"]
+    i, j = pair
+    L = np.array([256.0] * 3)
+    d = C[j] - C[i]
+    d = d - L * np.round(d / L)
+    dist = float(np.sqrt(np.sum(d * d)))
+    gap = dist - R[i] - R[j]
+    mid = (C[i] + d * (R[i] + 0.5 * gap) / dist) % 256.0
+    lo = np.floor(mid - n / 2).astype(int)
+    sub = np.ix_(*[np.arange(lo[a], lo[a] + n) % 256 for a in range(3)])
+    w = Workload(full)
+    for k in ("E", "nu", "Omega", "D", "sigma_max", "c0", "d0", "phase"):
+        w[k] = np.ascontiguousarray(full[k][sub])
+    w.update(name="polydisperse_window", shape=(n, n, n), gap=gap, window_origin=lo.tolist())
+    return w
 
 
 def batch_workloads(n_items=48, sizes=(32, 48, 64, 96), eps=1e-3):

@@ -13,7 +13,10 @@ d^k, before each mechanics solve, and the loop also requires the
 concentration to have settled, ||c^{k+1} - c^k|| <= tol_chem ||c_t||.
 
 Readings of the paper taken here: Alg. 4 tests "tol_mech" but declares
-tol_nw; we use tol_nw with at most 20 staggered iterations.  The history
+tol_nw; we use tol_nw.  Alg. 4 sets no cap on the staggered iterations; we
+stop after 100 and report it (during damage growth the loop converges
+linearly, at a rate near 0.75 per iteration when a ligament is half broken,
+so 20 are too few).  The history
 is updated as H <- max(H, D_f) at every PFF call, so staggered iterates
 count as intermediate states.
 """
@@ -38,7 +41,7 @@ class StaggeredNoConvergence(NoConvergence):
 
 def staggered_step(F, c, d, H, Fbar_new, Fbar_old, mat, dt=None, cdot_B=None,
                    chemistry=True, tol_newton=1e-8, tol_lin=1e-10, tol_chem=1e-8,
-                   tol_pff=1e-10, max_stag=20, raise_on_noconv=True, jacobian="mu_c"):
+                   tol_pff=1e-10, max_stag=100, raise_on_noconv=True, jacobian="mu_c"):
     """One time step of Alg. 4; returns (F, c, d, H, stats), stats["converged"]
     telling whether err_res <= tol_newton was reached.  Without convergence in
     max_stag iterations StaggeredNoConvergence is raised (or, with

@@ -29,7 +29,7 @@ class StaggeredNoConvergence(FgError):
 
 
 def staggered_step(plan, F_macro, dt=None, cdot_B=None, chemistry=True, tol_newton=1e-8, tol_lin=1e-10,
-                   tol_chem=1e-8, tol_pff=1e-10, max_stag=20, max_lin=20000, raise_on_noconv=True,
+                   tol_chem=1e-8, tol_pff=1e-10, max_stag=100, max_lin=20000, raise_on_noconv=True,
                    jacobian="mu_c"):
     """One time step; returns a stats dict (``converged`` tells whether the
     staggered loop met its tolerance).  The plan's state (F, c, d, H) is

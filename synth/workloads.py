@@ -150,12 +150,15 @@ def particle_workload(n=128, n_steps=200, dt=5.0, q_in=4.0e-10, sigma_max=20e6):
 
 
 def polydisperse_workload(n=256, n_spheres=60, n_inc=20, total_strain=0.05,
-                          strength_ratio=0.04):
+                          strength_ratio=0.25):
     """Periodic RSA spheres (radii U(10, 24) voxels at 256^3, scaled with
     n / 256), spheres 200 GPa, matrix 10 GPa, nu = 0.3.  The threshold
-    stress is proportional to stiffness, sigma_max = 0.04 E (400 MPa in the
-    matrix, 8 GPa in the spheres), so damage starts in the second half of
-    the stretch ramp instead of in the stiff spheres at the first step."""
+    stress is proportional to stiffness, sigma_max = strength_ratio E
+    (default 0.25: 2.5 GPa in the matrix, 50 GPa in the spheres), so that
+    damage starts in the second half of the stretch ramp, in the matrix
+    ligament of the narrowest gap aligned with the stretch (about ten times
+    the mean strain there).  With 0.04 E that ligament damages from the
+    second increment and a crack runs through the matrix at 1 % stretch."""
     shape, spacing = _base((n, n, n), 1.0)
     s = n / 256.0
     rng = rng_for(3)
@@ -173,7 +176,7 @@ def polydisperse_workload(n=256, n_spheres=60, n_inc=20, total_strain=0.05,
     )
 
 
-def polydisperse_window(n=48, pair=(12, 55), strength_ratio=0.04, n_inc=20, total_strain=0.05):
+def polydisperse_window(n=48, pair=(12, 55), strength_ratio=0.25, n_inc=20, total_strain=0.05):
     """An n^3 window of the 256^3 polydisperse microstructure (same voxels,
     same materials, same load ramp), centred on the surface gap between the
     two given spheres (by default the gap most aligned with the stretch

@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--ramp", action="store_true",
                     help="staggered load increments of the polydisperse ramp (Newton-CG, history, phase field) "
                          "instead of CG iterations at the first increment")
+    ap.add_argument("--first-increment", type=int, default=1,
+                    help="--ramp: run the increments before this one untimed first (to reach a damaged state)")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the end-to-end Newton solve of the increment after the timed iterations")
     ap.add_argument("--batch", action="store_true",
@@ -174,18 +176,24 @@ def run_cg_form(work, form, steps, warmup, solve=True):
     return out
 
 
-def run_ramp_form(work, form, steps, warmup):
+def run_ramp_form(work, form, steps, warmup, first=1):
     """Staggered load increments (Alg. 4 without chemistry) of the ramp:
-    warmup increments, then `steps` timed increments.  An increment whose
-    staggered loop does not converge raises (it is not timed as a step)."""
+    increments 1 .. first - 1 untimed (silently), then warmup increments
+    with every kernel class timed, then `steps` timed increments.  An
+    increment whose staggered loop does not converge raises (it is not
+    timed as a step)."""
     import torch
 
     from paper_2411_16583_amd.driver import staggered_step
 
     loads = work["loads"]
-    if warmup + steps > len(loads):
-        raise SystemExit(f"--warmup + --steps = {warmup + steps} exceeds the {len(loads)} load increments")
+    if first - 1 + warmup + steps > len(loads):
+        raise SystemExit(f"increments up to {first - 1 + warmup + steps} requested; the ramp has {len(loads)}")
     plan, F = new_plan(work, form)
+    for k in range(first - 1):
+        st = staggered_step(plan, loads[k], chemistry=False)
+        print(f"[{form}] increment {k + 1} (untimed): staggered {st['stag_iters']}", flush=True)
+    loads = loads[first - 1:]
     # warm-up increments: HIP events around every kernel class (the per-class
     # breakdown); timed increments: events around the dominant class only
     # (the roofline kernel), since the event records of all classes cost a
@@ -193,7 +201,7 @@ def run_ramp_form(work, form, steps, warmup):
     plan.profile_begin()
     for k in range(warmup):
         st = staggered_step(plan, loads[k], chemistry=False)
-        print(f"[{form}] warmup increment {k + 1}: newton {[s['newton_iters'] for s in st['newton']]} "
+        print(f"[{form}] warmup increment {first + k}: newton {[s['newton_iters'] for s in st['newton']]} "
               f"cg {[s['lin_history'] for s in st['newton']]}", flush=True)
     torch.cuda.synchronize()
     prof_all = plan.profile_end()
@@ -208,8 +216,9 @@ def run_ramp_form(work, form, steps, warmup):
         its = sum(s["lin_iters_total"] for s in st["newton"])
         cg_iters += its
         newton_iters += sum(s["newton_iters"] for s in st["newton"])
-        print(f"[{form}] increment {k + 1}: newton {[s['newton_iters'] for s in st['newton']]} "
-              f"cg {[s['lin_history'] for s in st['newton']]} err {st['err_res']:.2e}", flush=True)
+        print(f"[{form}] increment {first + k}: staggered {st['stag_iters']}, newton "
+              f"{[s['newton_iters'] for s in st['newton']]} cg {[s['lin_history'] for s in st['newton']]} "
+              f"err {st['err_res']:.2e}", flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = plan.profile_end()
@@ -656,7 +665,7 @@ def run_ramp(args, work, forms, N):
     """--ramp: staggered load increments (Newton-CG, history, phase field)."""
     res = {}
     for form in forms:
-        res[form] = run_ramp_form(work, form, args.steps, args.warmup)
+        res[form] = run_ramp_form(work, form, args.steps, args.warmup, args.first_increment)
     main_form = "fp64" if "fp64" in res else forms[0]
     r0 = res[main_form]
     value = N * r0["cg_iters"] / r0["elapsed"]
@@ -673,8 +682,9 @@ def run_ramp(args, work, forms, N):
         "vs_baseline": None,
         "dtype": "f64" if main_form == "fp64" else "f32/f64",
         "data": "synthetic",
-        "config": {"workload": f"polydisperse RVE {args.n}^3, load increments {args.warmup + 1}.."
-                               f"{args.warmup + args.steps} of the stretch ramp, damage on, chemistry off; "
+        "config": {"workload": f"polydisperse RVE {args.n}^3, load increments "
+                               f"{args.first_increment + args.warmup}..{args.first_increment - 1 + args.warmup + args.steps}"
+                               f" of the stretch ramp (sigma_max = 0.25 E), damage on, chemistry off; "
                                f"step = one staggered load increment",
                    "voxels": N, "cg_iters": r0["cg_iters"], "newton_iters": r0["newton_iters"]},
         "roofline": roofline(r0, N, 8 if main_form == "fp64" else 4),

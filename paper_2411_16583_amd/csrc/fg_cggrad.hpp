@@ -107,10 +107,14 @@ k_cg_rupd_march(const T* __restrict__ U, long ucs, T* __restrict__ rbuf, const K
     // one plane: store the own voxels, add |D rho|^2 against the lower plane
     auto plane_step = [&](int i0, const T (&cur)[2][W + 1]) {
       if (mode == 0) {
-        V w;
+        // streaming store: the new rho is read again only by the next
+        // iteration's front (measured at 256^3: 283 -> 244 us FP64)
+        typedef T nvw __attribute__((ext_vector_type(W)));
+        nvw a;
 #pragma unroll
-        for (int q = 0; q < W; ++q) reinterpret_cast<T*>(&w)[q] = cur[0][q + 1];
-        at_bytes(reinterpret_cast<V*>(rn), (unsigned)i0 * plane_b + lo[0]) = w;
+        for (int q = 0; q < W; ++q) a[q] = cur[0][q + 1];
+        __builtin_nontemporal_store(a, reinterpret_cast<nvw*>(&at_bytes(reinterpret_cast<V*>(rn),
+                                                                        (unsigned)i0 * plane_b + lo[0])));
       }
       T u[2][2][W + 1];
 #pragma unroll

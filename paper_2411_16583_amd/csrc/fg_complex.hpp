@@ -39,6 +39,25 @@ template <typename C> __device__ __forceinline__ void st_stream(C* p, C v) {
   nv2 w = {v.x, v.y};
   __builtin_nontemporal_store(w, reinterpret_cast<nv2*>(p));
 }
+// Streaming load of one complex value (nontemporal: for read streams that
+// are used once).
+template <typename C> __device__ __forceinline__ C ld_stream(const C* p) {
+  using T = decltype(C::x);
+  typedef T nv2 __attribute__((ext_vector_type(2)));
+  const nv2 w = __builtin_nontemporal_load(reinterpret_cast<const nv2*>(p));
+  return mk<C>(w[0], w[1]);
+}
+// The same for 16 bytes of single-precision values (two complex numbers).
+__device__ __forceinline__ float4 ld_stream_f4(const void* p) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 w = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+  return make_float4(w[0], w[1], w[2], w[3]);
+}
+__device__ __forceinline__ void st_stream_f4(void* p, float4 v) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<f4*>(p));
+}
 // multiply by -i (forward quarter turn) / +i
 template <typename C> __device__ __forceinline__ C mul_mi(C a) { return mk<C>(a.y, -a.x); }
 template <typename C> __device__ __forceinline__ C mul_pi(C a) { return mk<C>(-a.y, a.x); }

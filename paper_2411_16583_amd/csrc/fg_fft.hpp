@@ -353,10 +353,13 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
   const bool active = lm.active;
   const C* src = reinterpret_cast<const C*>(in) + line * M;
   C* my = lds + ll * (M + PAD);
-  // one global load per element; the mirror X[M - k] comes from LDS
+  // one global load per element; the mirror X[M - k] comes from LDS.  Double
+  // precision streams both ways (measured at 256^3 on the 3-component
+  // potential: 159 -> 143 us; single precision got slower, 71 -> 103 us)
   C v[LS::E];
 #pragma unroll
-  for (int e = 0; e < LS::E; ++e) v[e] = active ? src[LS::idxA(t, e)] : mk<C>(R(0), R(0));
+  for (int e = 0; e < LS::E; ++e)
+    v[e] = active ? (sizeof(R) == 8 ? ld_stream(src + LS::idxA(t, e)) : src[LS::idxA(t, e)]) : mk<C>(R(0), R(0));
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) my[LS::idxA(t, e)] = v[e];
   __syncthreads();
@@ -385,7 +388,10 @@ k_fft_x_c2r(const R* in, R* out, long nlines, SpecTables<R> tb, C2REpi epi) {
     const int n = LS::idxB(t, e);
     const C y = cscale(v[e], sg);
     if (active) {
-      dst[n] = y;
+      if constexpr (sizeof(R) == 8)
+        st_stream(dst + n, y);
+      else
+        dst[n] = y;
       if (epi.partials) {
         if (epi.self_dot) {
           acc += (double)y.x * (double)y.x + (double)y.y * (double)y.y;

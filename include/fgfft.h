@@ -12,8 +12,12 @@
  * --------------------------------
  * Grid: N0 x N1 x N2 voxels on a periodic box, spacing h[3] (metres), N2 the
  * fastest axis, N = N0 N1 N2.  Supported sizes: N0, N1 in {4, 6, 8, 12, 16,
- * 24, 32, 48, 64, 96, 128, 256}; N2 = 2 M with M in {2, 3, 4, 6, 8, 12, 16,
- * 24, 32, 48, 64, 96, 128, 256}.  Others return FG_E_SIZE.
+ * 24, 32, 48, 64, 96, 128, 256}, and also N0 = 1; N2 = 2 M with M in {2, 3,
+ * 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256}.  Others return FG_E_SIZE.
+ * N0 = 1 is a plane (the 2-D problems of Sec. 4.3 and 5.1): the box is one
+ * voxel thick and periodic along axis 0, so every difference along axis 0
+ * vanishes and F_00 stays at its macroscopic value (plane strain, with the
+ * out-of-plane stretch prescribed by F_macro).
  * Fields: device pointers, double precision, component-major.  A scalar field
  * is N doubles in C order (index (i0 N1 + i1) N2 + i2); a 3x3 tensor field is
  * 9 such planes, plane 3 i + j holding the ij component (row-major tensor

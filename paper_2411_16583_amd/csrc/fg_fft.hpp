@@ -101,6 +101,7 @@ static_assert(sizeof(KrylovScalars) % sizeof(int) == 0, "gate stride");
 template <int L> struct LineShape;
 #define FG_LINE_SHAPE(L_, R1_, R2_) \
   template <> struct LineShape<L_> { static constexpr int R1 = R1_, R2 = R2_; };
+FG_LINE_SHAPE(1, 1, 1)
 FG_LINE_SHAPE(2, 2, 1)
 FG_LINE_SHAPE(3, 3, 1)
 FG_LINE_SHAPE(4, 4, 1)

@@ -35,6 +35,9 @@ bool fft_length_supported(int L) {
   return false;
 }
 bool fft_axis_length_supported(int L) { return L >= 4 && fft_length_supported(L); }
+// N0 may also be 1: a single plane (2-D problem), where the N0 transform is
+// the identity and every difference along axis 0 vanishes
+bool fft_n0_length_supported(int L) { return L == 1 || fft_axis_length_supported(L); }
 
 int line_threads(int L) {
   switch (L) {
@@ -1120,7 +1123,7 @@ fg_status plan_new(const int grid[3], const double spacing[3], fg_precision prec
   if (nitems < 1) return FG_E_ARG;
   for (int k = 0; k < 3; ++k)
     if (!(spacing[k] > 0.0) || !std::isfinite(spacing[k])) return FG_E_ARG;
-  if (!fg::fft_axis_length_supported(grid[0]) || !fg::fft_axis_length_supported(grid[1])) return FG_E_SIZE;
+  if (!fg::fft_n0_length_supported(grid[0]) || !fg::fft_axis_length_supported(grid[1])) return FG_E_SIZE;
   if (grid[2] % 2 != 0 || !fg::fft_length_supported(grid[2] / 2) || grid[2] < 4) return FG_E_SIZE;
   fg_plan* P = new (std::nothrow) fg_plan();
   if (!P) return FG_E_HIP;
@@ -2294,7 +2297,7 @@ fg_status fg_project_noalloc(const int grid[3], const double spacing[3], const d
   if (!grid || !spacing || !x || !y) return FG_E_ARG;
   for (int k = 0; k < 3; ++k)
     if (!(spacing[k] > 0.0) || !std::isfinite(spacing[k])) return FG_E_ARG;
-  if (!fg::fft_axis_length_supported(grid[0]) || !fg::fft_axis_length_supported(grid[1])) return FG_E_SIZE;
+  if (!fg::fft_n0_length_supported(grid[0]) || !fg::fft_axis_length_supported(grid[1])) return FG_E_SIZE;
   if (grid[2] % 2 != 0 || grid[2] < 4 || !fg::fft_length_supported(grid[2] / 2)) return FG_E_SIZE;
   const long N = (long)grid[0] * grid[1] * grid[2];
   if ((size_t)N * 9 * sizeof(double) > kScratchWorkBytes) return FG_E_SIZE;

@@ -46,6 +46,8 @@ __all__ = [
     "batch_workloads",
     "grf_workload",
     "homogeneous_workload",
+    "plane_inclusion_workload",
+    "in_plane_schedule",
 ]
 
 GAS_R = 8.314462618  # J / (mol K)
@@ -68,6 +70,17 @@ def uniaxial_schedule(total_strain, n_inc):
     for n in range(1, n_inc + 1):
         F = np.eye(3)
         F[0, 0] += total_strain * n / n_inc
+        out.append(F)
+    return out
+
+
+def in_plane_schedule(total_strain, n_inc, axis=1):
+    """F_n = I + (n / n_inc) * total_strain * e_a (x) e_a, a = axis (an
+    in-plane axis of a plane grid (1, N1, N2): 1 or 2)."""
+    out = []
+    for n in range(1, n_inc + 1):
+        F = np.eye(3)
+        F[axis, axis] += total_strain * n / n_inc
         out.append(F)
     return out
 
@@ -121,6 +134,33 @@ def inclusion_workload(n=16, radius=None, n_inc=5, total_strain=0.01):
         RT=GAS_R * 298.15, c_max=3.0e4,
         c0=np.zeros(shape), d0=np.zeros(shape),
         loads=uniaxial_schedule(total_strain, n_inc),
+        tol_newton=1e-8, tol_lin=1e-10,
+    )
+
+
+def plane_inclusion_workload(n=32, radius=None, n_inc=3, total_strain=0.01, thickness=1):
+    """Plane (2-D) twin of the inclusion workload: a grid (thickness, n, n)
+    of unit in-plane size, a centred circular inclusion (a cylinder through
+    the thickness) of radius n/4, stiff inclusion in a compliant matrix as in
+    the 3-D case, in-plane uniaxial stretch along axis 1.  With thickness 1
+    it is a 2-D plan; with thickness > 1 the same cell is a prismatic 3-D
+    grid whose solution does not vary along axis 0."""
+    shape = (int(thickness), int(n), int(n))
+    h = 1.0 / n
+    spacing = (h, h, h)
+    if radius is None:
+        radius = n / 4.0
+    inc = sphere_mask((1, n, n), radius)
+    inc = np.broadcast_to(inc, shape).copy()
+    E = np.where(inc, 100e9, 10e9)
+    nu = np.where(inc, 0.25, 0.3)
+    return Workload(
+        name="plane_inclusion", shape=shape, spacing=spacing, phase=inc,
+        E=E, nu=nu, Omega=np.zeros(shape), D=np.full(shape, 1e-14),
+        sigma_max=np.full(shape, 1e30), gc=1.0, lc=2.0 * h,
+        RT=GAS_R * 298.15, c_max=3.0e4,
+        c0=np.zeros(shape), d0=np.zeros(shape),
+        loads=in_plane_schedule(total_strain, n_inc),
         tol_newton=1e-8, tol_lin=1e-10,
     )
 

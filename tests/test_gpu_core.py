@@ -18,7 +18,9 @@ from tests.gpu_util import DEV, dt, host, plan_for, rel
 pytestmark = pytest.mark.gpu
 
 GRIDS = [(4, 4, 4), (8, 8, 8), (16, 16, 16), (12, 24, 48), (6, 8, 12), (32, 48, 64), (96, 16, 24),
-         (64, 64, 128), (256, 4, 8), (4, 256, 16), (8, 4, 512)]
+         (64, 64, 128), (256, 4, 8), (4, 256, 16), (8, 4, 512),
+         # plane (2-D) grids: one voxel along N0
+         (1, 4, 8), (1, 16, 32), (1, 48, 96), (1, 64, 64), (1, 256, 512)]
 
 
 def unpack_packed(Z, shape):
@@ -99,12 +101,14 @@ def _random_state(work, rng, amp=0.05):
     return F
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 16, 24), (32, 32, 32), (256, 4, 8), (4, 256, 16), (8, 4, 512)])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 16, 24), (32, 32, 32), (256, 4, 8), (4, 256, 16), (8, 4, 512),
+                                   (1, 32, 48), (1, 256, 512)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
 def test_operator_matches_oracle(shape, precision, tol):
     """One application of the operator of eq. (30) against the oracle, also on
     grids with 256-long lines along N0 and N1 (the single-precision N0 and N1
-    passes of length 256 that the 256^3 mixed form runs) and 512 along N2."""
+    passes of length 256 that the 256^3 mixed form runs), 512 along N2, and
+    plane grids (N0 = 1)."""
     print(f"operator shape={shape} {precision}", flush=True)
     rng = np.random.default_rng(102)
     work = synth.homogeneous_workload(shape, 1.0)

@@ -123,7 +123,7 @@ def test_staggered_particle_twin_matches_oracle():
     t = _state(plan, F0, w["c0"], w["d0"], np.zeros(shape))
     cdot = dt(w["cdot_B"])
     Fo, co, do, Ho = F0.copy(), w["c0"].copy(), w["d0"].copy(), np.zeros(shape)
-    for step in range(1):
+    for step in range(2):
         sg = staggered_step(plan, np.eye(3), dt=w["dt"], cdot_B=cdot, tol_lin=1e-10)
         Fo, co, do, Ho, so = staggered.staggered_step(Fo, co, do, Ho, np.eye(3), np.eye(3), w, dt=w["dt"],
                                                       cdot_B=w["cdot_B"])

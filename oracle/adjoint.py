@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .constitutive import apply_tangent, stress, stress_param_derivatives, tangent
+from .constitutive import apply_tangent, law_of, stress, stress_param_derivatives, tangent
 from .krylov import cg
 from .mechanics import norm, operator
 from .spectral import project
@@ -29,12 +29,12 @@ def adjoint_gradient(F, c, d, mat, tol_lin=1e-10, maxit=20000):
     grid's shape."""
     spacing = mat["spacing"]
     shape = F.shape[2:]
-    K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+    K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
     E11 = np.zeros((3, 3) + tuple(shape))
     E11[0, 0] = 1.0
     rhs = -project(apply_tangent(K, E11), spacing)
     lam, it, _ = cg(lambda X: operator(K, X, spacing), rhs, tol_lin, maxit)
-    P, dP_dOm = stress_param_derivatives(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+    P, dP_dOm = stress_param_derivatives(F, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
     W = E11 + lam
     N = float(np.prod(shape))
     gE = np.einsum("ij...,ij...->...", W, P) / N
@@ -48,14 +48,14 @@ def _difference_solve(F0, c, d, mat_pert, P0, tol=1e-11, max_newton=30, tol_lin=
     dF = np.zeros_like(F0)
     ref = None
     for _ in range(max_newton):
-        P = stress(F0 + dF, c, d, mat_pert["E"], mat_pert["nu"], mat_pert["Omega"])
+        P = stress(F0 + dF, c, d, mat_pert["E"], mat_pert["nu"], mat_pert["Omega"], law_of(mat_pert))
         b = -project(project(P - P0, spacing), spacing)
         nb = norm(b)
         if ref is None:
             ref = max(nb, 1e-300)
         if nb <= tol * ref:
             break
-        K = tangent(F0 + dF, c, d, mat_pert["E"], mat_pert["nu"], mat_pert["Omega"])
+        K = tangent(F0 + dF, c, d, mat_pert["E"], mat_pert["nu"], mat_pert["Omega"], law_of(mat_pert))
         x, _, _ = cg(lambda X: operator(K, X, spacing), b, tol_lin, 20000)
         dF = dF + x
     return dF
@@ -65,7 +65,7 @@ def fd_gradient(F0, c, d, mat, voxel, param, eta):
     """Central finite difference of L = <P_11> with respect to log E
     (``param='logE'``) or Omega (``param='Omega'``) at one voxel (flat
     index), by two difference solves."""
-    P0 = stress(F0, c, d, mat["E"], mat["nu"], mat["Omega"])
+    P0 = stress(F0, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
     out = []
     for sgn in (+1.0, -1.0):
         m = dict(mat)
@@ -78,6 +78,6 @@ def fd_gradient(F0, c, d, mat, voxel, param, eta):
             Om[voxel] += sgn * eta
             m["Omega"] = Om.reshape(mat["Omega"].shape)
         dF = _difference_solve(F0, c, d, m, P0)
-        P = stress(F0 + dF, c, d, m["E"], m["nu"], m["Omega"])
+        P = stress(F0 + dF, c, d, m["E"], m["nu"], m["Omega"], law_of(m))
         out.append(float(np.mean(P[0, 0] - P0[0, 0])))
     return (out[0] - out[1]) / (2.0 * eta)

@@ -19,7 +19,9 @@ Readings of the paper taken here:
 * mu_e is re-derived from the chosen energy (the printed eq. (18) is
   garbled):  mu_e = dpsi_e/dc = -g Omega / (3 (1 + Omega c))
   [ G (tr C_e - 3) + 3 lambda ln J_e ]  (J/m^3), divided by c_max (mol/m^3)
-  to give J/mol before adding to mu_c.
+  to give J/mol before adding to mu_c.  For the Saint-Venant-Kirchhoff law
+  (E_e = (s^-2 C - I)/2, dE_e/dc = -Omega/(3a) (2 E_e + I), a = 1 + Omega c):
+  mu_e = -g Omega / (3a) [ 2 lambda tr^2 E_e + 4 G E_e:E_e + (3 lambda + 2 G) tr E_e ].
 * The Newton linearisation keeps only mu_c (as eq. (45) does):
       dmu_c/dc = w = RT (1/c + 1/(1 - c)),
   and the linear step is solved for dmu = w dc with the SPD operator
@@ -44,7 +46,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .constitutive import DomainError, det_and_inv_transpose, lame, swelling_factors
+from .constitutive import DomainError, det_and_inv_transpose, green_lagrange_elastic, lame, law_of, swelling_factors
 from .krylov import pcg
 from .spectral import forward_difference_symbol, irfft3, laplacian_symbol, rfft3
 
@@ -59,11 +61,21 @@ def chemical_potential(c, F, d, mat):
     Om = mat["Omega"]
     g = (1.0 - d) ** 2
     a, s2inv = swelling_factors(c, Om)
+    if law_of(mat) == "svk":
+        t, q = _svk_invariants(F, c, Om)
+        mu_e = -g * Om / (3.0 * a) * (2.0 * lam * t * t + 4.0 * G * q + (3.0 * lam + 2.0 * G) * t)
+        return mu_c + mu_e / mat["c_max"]
     J, _ = det_and_inv_transpose(F)
     lnJe = np.log(J) - np.log(a)
     trC = np.einsum("ij...,ij...->...", F, F)
     mu_e = -g * Om / (3.0 * a) * (G * (trC * s2inv - 3.0) + 3.0 * lam * lnJe)
     return mu_c + mu_e / mat["c_max"]
+
+
+def _svk_invariants(F, c, Omega):
+    """(tr E_e, E_e : E_e) of the elastic Green-Lagrange strain."""
+    Ee = green_lagrange_elastic(F, c, Omega)
+    return np.einsum("ii...->...", Ee), np.einsum("ij...,ij...->...", Ee, Ee)
 
 
 def elastic_potential_slope(c, F, d, mat):
@@ -75,6 +87,14 @@ def elastic_potential_slope(c, F, d, mat):
     Om = mat["Omega"]
     g = (1.0 - d) ** 2
     a, s2inv = swelling_factors(c, Om)
+    if law_of(mat) == "svk":
+        # with t = tr E_e, q = E_e:E_e, T = 2 lambda t^2 + 4 G q + (3 lambda + 2 G) t:
+        # d mu_e/dc = g Omega^2 / (3 a^2) [ T + ((4 lambda t + 3 lambda + 2 G)(2 t + 3)
+        #                                        + 8 G (2 q + t)) / 3 ]
+        t, q = _svk_invariants(F, c, Om)
+        T = 2.0 * lam * t * t + 4.0 * G * q + (3.0 * lam + 2.0 * G) * t
+        dT = ((4.0 * lam * t + 3.0 * lam + 2.0 * G) * (2.0 * t + 3.0) + 8.0 * G * (2.0 * q + t)) / 3.0
+        return g * Om * Om / (3.0 * a * a) * (T + dT) / mat["c_max"]
     J, _ = det_and_inv_transpose(F)
     lnJe = np.log(J) - np.log(a)
     trC = np.einsum("ij...,ij...->...", F, F)

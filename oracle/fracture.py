@@ -17,20 +17,27 @@ Readings of the paper taken here:
 * H carries the factor g_c/(2 l_c):  H = max(H_old, g_c/(2 l_c) D_f), which
   makes eq. (6) read  d - l_c^2 Lap d = (1 - d) max D_f.
 * sigma is the effective (undegraded) Cauchy stress
-      sigma = J^-1 [ G (b/s^2 - I) + lambda ln J_e I ],  b = F F^T.
+      sigma = J^-1 [ G (b/s^2 - I) + lambda ln J_e I ],  b = F F^T,
+  for the Neo-Hookean law, and sigma = J^-1 s^-2 F S F^T (the push-forward
+  of the undegraded P = s^-2 F S) for the Saint-Venant-Kirchhoff law.
 * Alg. 2's printed operator drops the factor d; it is [g_c/l_c + 2H] d.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .constitutive import det_and_inv_transpose, lame, swelling_factors
+from .constitutive import det_and_inv_transpose, lame, law_of, svk_second_piola, swelling_factors
 from .krylov import pcg
 from .spectral import irfft3, laplacian_symbol, rfft3
 
 
-def effective_cauchy(F, c, E, nu, Omega):
+def effective_cauchy(F, c, E, nu, Omega, law="neo_hookean"):
     """Undegraded Cauchy stress, shape (3, 3, ...)."""
+    if law == "svk":
+        _, s2inv = swelling_factors(c, Omega)
+        J, _ = det_and_inv_transpose(F)
+        S = svk_second_piola(F, c, E, nu, Omega)
+        return s2inv * np.einsum("ik...,kl...,jl...->ij...", F, S, F) / J
     lam, G = lame(E, nu)
     a, s2inv = swelling_factors(c, Omega)
     J, _ = det_and_inv_transpose(F)
@@ -57,7 +64,7 @@ def driving_force(sigma, sigma_max):
 
 def update_history(H_old, F, c, mat):
     """H <- max(H_old, g_c/(2 l_c) D_f(sigma(F)))."""
-    sig = effective_cauchy(F, c, mat["E"], mat["nu"], mat["Omega"])
+    sig = effective_cauchy(F, c, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
     Df = driving_force(sig, mat["sigma_max"])
     return np.maximum(H_old, mat["gc"] / (2.0 * mat["lc"]) * Df)
 

@@ -14,20 +14,20 @@ from __future__ import annotations
 
 import numpy as np
 
-from .constitutive import stress, tangent
+from .constitutive import law_of, stress, tangent
 
 
-def _pt(F, c, d, E, nu, Om):
+def _pt(F, c, d, E, nu, Om, law="neo_hookean"):
     Fp = F.reshape(3, 3, 1)
     f = lambda x: np.asarray(x, dtype=np.float64).reshape(1)
-    P = stress(Fp, f(c), f(d), f(E), f(nu), f(Om))[:, :, 0]
-    K = tangent(Fp, f(c), f(d), f(E), f(nu), f(Om))[:, :, 0].reshape(3, 3, 3, 3)
+    P = stress(Fp, f(c), f(d), f(E), f(nu), f(Om), law)[:, :, 0]
+    K = tangent(Fp, f(c), f(d), f(E), f(nu), f(Om), law)[:, :, 0].reshape(3, 3, 3, 3)
     return P, K
 
 
 def laminate_solution(Fbar, axis, phi, matA, matB, tol=1e-15, max_iter=50):
-    """matA / matB: dicts with scalars E, nu, Omega, c, d.  Returns
-    (F_A, F_B, a)."""
+    """matA / matB: dicts with scalars E, nu, Omega, c, d (and optionally
+    the law).  Returns (F_A, F_B, a)."""
     Fbar = np.asarray(Fbar, dtype=np.float64)
     n = axis
     e = np.zeros(3)
@@ -36,8 +36,8 @@ def laminate_solution(Fbar, axis, phi, matA, matB, tol=1e-15, max_iter=50):
     for _ in range(max_iter):
         FA = Fbar + (1.0 - phi) * np.outer(a, e)
         FB = Fbar - phi * np.outer(a, e)
-        PA, KA = _pt(FA, matA["c"], matA["d"], matA["E"], matA["nu"], matA["Omega"])
-        PB, KB = _pt(FB, matB["c"], matB["d"], matB["E"], matB["nu"], matB["Omega"])
+        PA, KA = _pt(FA, matA["c"], matA["d"], matA["E"], matA["nu"], matA["Omega"], law_of(matA))
+        PB, KB = _pt(FB, matB["c"], matB["d"], matB["E"], matB["nu"], matB["Omega"], law_of(matB))
         res = PA[:, n] - PB[:, n]
         scale = max(np.abs(PA).max(), np.abs(PB).max(), 1e-300)
         if np.abs(res).max() <= tol * scale:

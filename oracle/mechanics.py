@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .constitutive import apply_tangent, stress, tangent
+from .constitutive import apply_tangent, law_of, stress, tangent
 from .krylov import cg
 from .spectral import project
 
@@ -49,13 +49,13 @@ def operator(K, X, spacing):
 
 def residual_rhs(F, c, d, mat, spacing):
     """Equilibrium residual of eq. (30)/(31): returns (G*P(F), P)."""
-    P = stress(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+    P = stress(F, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
     return project(P, spacing), P
 
 
 def err_denominator(Fbar, c, d, mat, spacing):
     shape = np.shape(c)
-    Pbar = stress(uniform_field(Fbar, shape), c, d, mat["E"], mat["nu"], mat["Omega"])
+    Pbar = stress(uniform_field(Fbar, shape), c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
     GP = project(Pbar, spacing)
     return max(norm(GP), 1e-14 * norm(Pbar), 1e-300)
 
@@ -81,7 +81,7 @@ def newton_solve(F, Fbar, c, d, mat, spacing, tol_newton=1e-8, tol_lin=1e-10,
         if it >= max_newton:
             raise NoConvergence("Newton did not converge")
         b = -project(GP, spacing)
-        K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+        K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
         fixed = None if fixed_lin is None else fixed_lin[it]
         dF, n, _ = cg(lambda X: operator(K, X, spacing), b, tol_lin, max_lin,
                       fixed_iters=fixed)
@@ -112,7 +112,7 @@ def solve_increments(work, loads=None, F=None, c=None, d=None, **kw):
 
 def mean_stress(F, c, d, mat):
     """Homogenised (voxel-mean) first Piola-Kirchhoff stress <P>."""
-    P = stress(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+    P = stress(F, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
     return P.reshape(3, 3, -1).mean(axis=-1)
 
 
@@ -125,7 +125,7 @@ def homogenized_tangent(F, c, d, mat, W, tol_lin=1e-12, maxit=20000):
     and then d<P> = <K : (W + dF)>.  Returns (3x3 array, CG iterations)."""
     spacing = mat["spacing"]
     shape = F.shape[2:]
-    K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+    K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
     Wf = uniform_field(W, shape)
     b = -project(project(apply_tangent(K, Wf), spacing), spacing)
     dF, it, _ = cg(lambda X: operator(K, X, spacing), b, tol_lin, maxit)
@@ -162,7 +162,7 @@ def newton_solve_mixed(F, Fbar, mask, Pbar, c, d, mat, spacing, tol_newton=1e-8,
     den = None
     it = 0
     while True:
-        P = stress(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+        P = stress(F, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
         R = project_mixed(P, mask, spacing) - np.broadcast_to(target, (3, 3) + tuple(shape))
         nr = norm(R)
         if den is None:
@@ -174,7 +174,7 @@ def newton_solve_mixed(F, Fbar, mask, Pbar, c, d, mat, spacing, tol_newton=1e-8,
         if it >= max_newton:
             raise NoConvergence("mixed-control Newton did not converge")
         b = -project_mixed(R, mask, spacing)
-        K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"])
+        K = tangent(F, c, d, mat["E"], mat["nu"], mat["Omega"], law_of(mat))
         dF, n, _ = cg(lambda X: project_mixed(apply_tangent(K, X), mask, spacing), b, tol_lin, max_lin)
         lin_iters.append(n)
         F = F + dF

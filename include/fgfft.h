@@ -67,6 +67,19 @@ typedef enum {
  * stress and F stay double, so Newton refines to the double tolerance. */
 typedef enum { FG_FP64 = 0, FG_MIXED = 1 } fg_precision;
 
+/* Material law of a plan (fg_set_law).
+ * FG_LAW_NEO_HOOKE: compressible Neo-Hookean energy psi_0 = G/2 (tr C_e - 3)
+ *   - G ln J_e + lambda/2 (ln J_e)^2 (the default).
+ * FG_LAW_SVK: the paper's Saint-Venant-Kirchhoff energy (Sec. 2.1 eqs. (3),
+ *   (4), (12)): psi_0 = lambda/2 tr^2 E_e + G tr(E_e^2), E_e = (F_e^T F_e -
+ *   I)/2.  Both take F_e = F (1 + Omega c)^{-1/3} (eq. (2)), the degradation
+ *   g(d) = (1 - d)^2 and the energy per reference volume, so that for SVK
+ *   P = g (1 + Omega c)^{-2/3} F S(E_e), eq. (12) when Omega c = 0.  The law
+ *   sets the stress, the CG operator's tangent, the effective Cauchy stress
+ *   of the driving force, the elastic chemical potential and the adjoint's
+ *   parameter derivatives. */
+typedef enum { FG_LAW_NEO_HOOKE = 0, FG_LAW_SVK = 1 } fg_law;
+
 typedef struct {
   double tol_newton; /* err_res tolerance (eq. (31)), e.g. 1e-8           */
   double tol_lin;    /* CG tolerance ||r|| <= tol ||b||, e.g. 1e-10       */
@@ -102,6 +115,14 @@ size_t fg_plan_workspace_bytes(const fg_plan* plan);
  * transform and symbol tables into it (asynchronously on the plan stream).
  * Errors: FG_E_ARG, FG_E_SIZE (too small), FG_E_HIP. */
 fg_status fg_plan_set_workspace(fg_plan* plan, void* dev, size_t bytes);
+
+/* Choose the plan's material law (fg_law).  Call before
+ * fg_plan_workspace_bytes / fg_plan_set_workspace: the SVK tangent state
+ * takes 18 words per voxel instead of 12, so the workspace size depends on
+ * the law.  Batch plans use the Neo-Hookean law only.
+ * Errors: FG_E_ARG (unknown law, null plan, a batch group), FG_E_STATE (the
+ * workspace is already set). */
+fg_status fg_set_law(fg_plan* plan, int law);
 
 /* Material fields (Sec. 2; Table of Sec. 4.3 for the kind of data): Young's
  * modulus E (Pa), Poisson ratio nu, swelling coefficient Omega (eq. (2)),

@@ -4,7 +4,8 @@
 //   xi <- xi + alpha_{k-1} pi_{k-1}        (deferred solution update, k > 0)
 //   pi <- rho (k = 0) or rho + beta pi     (search direction)
 //   p  = D pi                              (9 components, never stored)
-//   Y  = K : p                             (tangent contraction, 12-word state)
+//   Y  = K : p                             (tangent contraction from the law's
+//                                           state: 12 words Neo-Hookean, 18 SVK)
 //   p . Y per block (FP64)                 (= p . G(K p) since p is compatible)
 //   Y -> packed real-to-complex transform along N2, written as the spectrum.
 // The contracted field never goes to HBM: it is staged in LDS, line by line,
@@ -77,7 +78,7 @@ template <int M> struct FrontShape {
   static constexpr int LSTRIDE = M + PADC;  // complex elements per line buffer
 };
 
-template <typename R, int M>
+template <typename R, int M, int LAW>
 __global__ void __launch_bounds__(FrontShape<M>::THREADS)
 k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, const R* __restrict__ rbuf,
            const R* __restrict__ st, const KrylovScalars* __restrict__ ksb, double* __restrict__ partials,
@@ -100,7 +101,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   pbuf += (long)item * 9 * N;
   xbuf += (long)item * 9 * N;
   rbuf += (long)item * 9 * N;
-  st += (long)item * 12 * N;
+  st += (long)item * state_words(LAW) * N;
   const int tid = threadIdx.x;
   const long line0 = ((long)blockIdx.x - (long)item * bpi) * LB;
   const int iter = ks->iter;
@@ -171,11 +172,10 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
 #pragma unroll
         for (int w = 0; w < W; ++w) X[w][3 * c + j] = Z[j][w];
     }
-    PV A[9];
+    constexpr int NS = (LAW == kLawSVK) ? 17 : 12;  // state words read
+    PV A[NS];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) A[k] = pk_load_nt<R, W>(sv + k * Nw + g);
-    const PV al = pk_load_nt<R, W>(sv + 9 * Nw + g), be = pk_load_nt<R, W>(sv + 10 * Nw + g),
-             ga = pk_load_nt<R, W>(sv + 11 * Nw + g);
+    for (int k = 0; k < NS; ++k) A[k] = pk_load_nt<R, W>(sv + k * Nw + g);
 #pragma unroll
     for (int w = 0; w < W; w += 2) {
       R A0[9], A1[9], Y0[9], Y1[9];
@@ -184,8 +184,20 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
         A0[k] = pk_get<R>(A[k], w);
         A1[k] = pk_get<R>(A[k], w + 1);
       }
-      tangent_apply<R>(A0, pk_get<R>(al, w), pk_get<R>(be, w), pk_get<R>(ga, w), X[w], Y0);
-      tangent_apply<R>(A1, pk_get<R>(al, w + 1), pk_get<R>(be, w + 1), pk_get<R>(ga, w + 1), X[w + 1], Y1);
+      if constexpr (LAW == kLawSVK) {
+        R S0[6], S1[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          S0[k] = pk_get<R>(A[9 + k], w);
+          S1[k] = pk_get<R>(A[9 + k], w + 1);
+        }
+        svk_apply<R>(A0, S0, pk_get<R>(A[15], w), pk_get<R>(A[16], w), X[w], Y0);
+        svk_apply<R>(A1, S1, pk_get<R>(A[15], w + 1), pk_get<R>(A[16], w + 1), X[w + 1], Y1);
+      } else {
+        tangent_apply<R>(A0, pk_get<R>(A[9], w), pk_get<R>(A[10], w), pk_get<R>(A[11], w), X[w], Y0);
+        tangent_apply<R>(A1, pk_get<R>(A[9], w + 1), pk_get<R>(A[10], w + 1), pk_get<R>(A[11], w + 1), X[w + 1],
+                         Y1);
+      }
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         acc += (double)X[w][k] * (double)Y0[k] + (double)X[w + 1][k] * (double)Y1[k];

@@ -209,7 +209,7 @@ void launch_zscalar(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R s
 template <typename R>
 int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st, const KrylovScalars* ks,
                     double* partials, long N, int n0, int n1, const double h[3], const SpecTables<R>& tb,
-                    hipStream_t s, int nitems, hipEvent_t ev0, hipEvent_t ev1) {
+                    hipStream_t s, int nitems, hipEvent_t ev0, hipEvent_t ev1, int law) {
   const R q0 = (R)(0.25 / h[0]), q1 = (R)(0.25 / h[1]), q2 = (R)(0.25 / h[2]);
   const long nlines = (long)n0 * n1;
   switch (M) {
@@ -217,12 +217,12 @@ int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st
   case L_: {                                                                                          \
     using FS = FrontShape<L_>;                                                                        \
     const long blocks = nitems * ((nlines + FS::LB - 1) / FS::LB);                                    \
-    if (ev0)                                                                                          \
-      hipExtLaunchKernelGGL((k_cg_front<R, L_>), dim3((unsigned)blocks), dim3(FS::THREADS), 0, s, ev0, ev1, 0, \
-                            spec, pbuf, xbuf, rbuf, st, ks, partials, N, n0, n1, tb, q0, q1, q2);     \
+    if (law == kLawSVK)                                                                            \
+      launch_ev((k_cg_front<R, L_, kLawSVK>), dim3((unsigned)blocks), dim3(FS::THREADS), 0, s, ev0, ev1, spec, \
+                pbuf, xbuf, rbuf, st, ks, partials, N, n0, n1, tb, q0, q1, q2);                         \
     else                                                                                              \
-      hipLaunchKernelGGL((k_cg_front<R, L_>), dim3((unsigned)blocks), dim3(FS::THREADS), 0, s, spec, pbuf, xbuf, \
-                         rbuf, st, ks, partials, N, n0, n1, tb, q0, q1, q2);                          \
+      launch_ev((k_cg_front<R, L_, kLawNH>), dim3((unsigned)blocks), dim3(FS::THREADS), 0, s, ev0, ev1, spec, \
+                pbuf, xbuf, rbuf, st, ks, partials, N, n0, n1, tb, q0, q1, q2);                         \
     return (int)blocks;                                                                               \
   }
     FG_FOR_M(FG_CASE)
@@ -234,7 +234,7 @@ int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st
 #define FG_INSTANTIATE_LAUNCHERS(R)                                                                     \
   template int launch_cg_front<R>(int, R*, R*, R*, const R*, const R*, const KrylovScalars*, double*, long, int, \
                                   int, const double*, const SpecTables<R>&, hipStream_t, int, hipEvent_t,   \
-                                  hipEvent_t);                                                          \
+                                  hipEvent_t, int);                                                     \
   template void launch_r2c<R>(int, const R*, R*, long, const SpecTables<R>&, const Skip&, hipStream_t); \
   template int launch_c2r<R>(int, const R*, R*, long, const SpecTables<R>&, const C2REpi&, hipStream_t, hipEvent_t, \
                              hipEvent_t);                                                           \

@@ -36,11 +36,13 @@ int zgrad_tile(int L, int M, int elem_bytes);  // built-in tile of launch_zgrad
 
 // Fused CG front on the potentials (deferred xi update, direction update,
 // p = D pi, contraction, p.Kp, N2 real-to-complex pass); h: grid spacings;
-// returns the number of partials written.
+// law: kLawNH or kLawSVK (the tangent state's layout); returns the
+// number of partials written.
 template <typename R>
 int launch_cg_front(int M, R* spec, R* pbuf, R* xbuf, const R* rbuf, const R* st, const KrylovScalars* ks,
                     double* partials, long N, int n0, int n1, const double h[3], const SpecTables<R>& tb,
-                    hipStream_t s, int nitems = 1, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    hipStream_t s, int nitems = 1, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                    int law = 0);
 
 template <typename R>
 void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const Skip& skip,

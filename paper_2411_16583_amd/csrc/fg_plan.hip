@@ -156,6 +156,7 @@ struct fg_plan {
   // [0] N1 pass FP64, [1] N0 projection pass FP64, [2] N1 pass FP32, [3] N0 projection pass FP32
   int tiles[4] = {0, 0, 0, 0};
   int tiles_gen = 0;  // bumped by fg_plan_set_tiles (a captured batch graph is then stale)
+  int law = ::FG_LAW_NEO_HOOKE;  // material law (fg_set_law, before the workspace)
   double h[3];
   fg_precision prec;
   hipStream_t stream;
@@ -180,7 +181,7 @@ struct fg_plan {
   void* x = nullptr;             // 9N T
   void* r = nullptr;             // 9N T
   void* p = nullptr;             // 9N T
-  void* st = nullptr;            // 12N T tangent state
+  void* st = nullptr;            // tangent state, state_words(law) N T
   void* dcb = nullptr;           // kx = 0 column of the row slots, contiguous along N0 (9 n0 n1 complex per item)
   double* sc = nullptr;          // scalar solver area, 16N doubles
   size_t part_n = 0;
@@ -262,7 +263,7 @@ size_t layout(fg_plan* P, char* base) {
   P->x = carve<char>(base, off, 9 * NT * tb);
   P->r = carve<char>(base, off, 9 * NT * tb);
   P->p = carve<char>(base, off, 9 * NT * tb);
-  P->st = carve<char>(base, off, 12 * NT * tb);
+  P->st = carve<char>(base, off, (size_t)fg::state_words(P->law) * NT * tb);
   P->dcb = carve<char>(base, off, (size_t)9 * n0 * n1 * P->nitems * sizeof(cplx<double>));
   // scalar solvers (phase field, Fick) only on single plans; batches keep
   // just the zero fields standing in for c and d
@@ -471,10 +472,10 @@ void constitutive(fg_plan* P, const double* Fu, double* Pout, void* state, doubl
   const double* d = P->d ? P->d : P->zeroN;
   if (P->prec == FG_FP64)
     hipLaunchKernelGGL((k_constitutive<double>), grid, dim3(256), 0, P->stream, P->F, Fu, c, d, P->E, P->nu,
-                       P->Om, Pout, (double*)state, pparts, P->flags, P->N, idle);
+                       P->Om, Pout, (double*)state, pparts, P->flags, P->N, idle, P->law);
   else
     hipLaunchKernelGGL((k_constitutive<float>), grid, dim3(256), 0, P->stream, P->F, Fu, c, d, P->E, P->nu,
-                       P->Om, Pout, (float*)state, pparts, P->flags, P->N, idle);
+                       P->Om, Pout, (float*)state, pparts, P->flags, P->N, idle, P->law);
   check_launch();
 }
 
@@ -574,7 +575,7 @@ void cg_iteration(fg_plan* P) {
   {
     ProfScope ps(P, FG_PASS_FRONT, true);
     nbf = launch_cg_front<T>(P->M, S, (T*)P->p, (T*)P->x, (const T*)P->r, (const T*)P->st, ks, P->part, P->N, P->n0,
-                             P->n1, P->h, tb, P->stream, nit, ps.start, ps.stop);
+                             P->n1, P->h, tb, P->stream, nit, ps.start, ps.stop, P->law);
   }
   {
     // alpha = r.r / p.Ap is formed by the row pass (one workgroup per item)
@@ -792,12 +793,21 @@ void newton(fg_plan* P, const double Fmacro[9], const fg_solver_opts* o, fg_stat
 // <K : (W + lam)> of the adjoint solution lam into Tout (host, 9): the
 // homogenised tangent applied to W (d<P>/dFbar : W), by the major symmetry
 // of K the same linear solve as the adjoint.
+// Y = K : X from the stored tangent state of the plan's law (one item).
+template <typename T> void launch_contract(fg_plan* P, T* Y, const T* X) {
+  const dim3 grid(blocks_for(P->N / 2));
+  if (P->law == ::FG_LAW_SVK)
+    hipLaunchKernelGGL((k_contract<T, fg::kLawSVK>), grid, dim3(256), 0, P->stream, Y, X, (const T*)P->st, P->N);
+  else
+    hipLaunchKernelGGL((k_contract<T, fg::kLawNH>), grid, dim3(256), 0, P->stream, Y, X, (const T*)P->st, P->N);
+}
+
 void tangent_mean(fg_plan* P, const double* lam, double* Tout) {
   const long N = P->N;
   const double* c = P->c ? P->c : P->zeroN;
   const double* d = P->d ? P->d : P->zeroN;
   hipLaunchKernelGGL(k_tangent_apply_f64, dim3(blocks_for(N)), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu,
-                     P->Om, (const double*)P->Fu, lam, P->S64, P->flags, N);
+                     P->Om, (const double*)P->Fu, lam, P->S64, P->flags, N, P->law);
   check_launch();
   mean9(P, P->S64);
   sync_read(P);
@@ -815,8 +825,7 @@ void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_sol
   FG_HIP(hipMemcpyAsync(P->Fu, W, 9 * sizeof(double), hipMemcpyHostToDevice, P->stream));
   hipLaunchKernelGGL((k_fill_uniform9<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, pbuf, (const double*)P->Fu,
                      N);
-  hipLaunchKernelGGL((k_contract<T>), dim3(blocks_for(N / 2)), dim3(256), 0, P->stream, S, (const T*)pbuf,
-                     (const T*)P->st, N);
+  launch_contract<T>(P, S, (const T*)pbuf);
   check_launch();
   static_assert(sizeof(T) == 8, "the single-precision adjoint is adjoint_mixed");
   {
@@ -834,7 +843,7 @@ void adjoint(fg_plan* P, const double W[9], double* gE, double* gO, const fg_sol
   const double* d = P->d ? P->d : P->zeroN;
   if (gE || gO) {
     hipLaunchKernelGGL((k_adjoint_grad<T>), dim3(blocks_for(N)), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu,
-                       P->Om, (const T*)lam, (const double*)P->Fu, gE, gO, P->flags, N);
+                       P->Om, (const T*)lam, (const double*)P->Fu, gE, gO, P->flags, N, P->law);
     check_launch();
   }
   if (Tout) tangent_mean(P, lam, Tout);
@@ -864,7 +873,7 @@ void adjoint_mixed(fg_plan* P, const double W[9], double* gE, double* gO, const 
   int refine = 0;
   for (;; ++refine) {
     hipLaunchKernelGGL(k_tangent_apply_f64, dim3(nbN), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu, P->Om,
-                       (const double*)P->Fu, (const double*)lam, P->S64, P->flags, N);
+                       (const double*)P->Fu, (const double*)lam, P->S64, P->flags, N, P->law);
     check_launch();
     C2REpi e1{1.0, nullptr, true, nullptr, Skip{}};
     project9<double>(P, P->S64, P->S64, P->S64, e1);
@@ -903,7 +912,7 @@ void adjoint_mixed(fg_plan* P, const double W[9], double* gE, double* gO, const 
   }
   if (gE || gO) {
     hipLaunchKernelGGL((k_adjoint_grad<double>), dim3(nbN), dim3(256), 0, P->stream, P->F, c, d, P->E, P->nu, P->Om,
-                       (const double*)lam, (const double*)P->Fu, gE, gO, P->flags, N);
+                       (const double*)lam, (const double*)P->Fu, gE, gO, P->flags, N, P->law);
     check_launch();
   }
   if (Tout) tangent_mean(P, lam, Tout);
@@ -999,7 +1008,7 @@ void pff(fg_plan* P, const fg_solver_opts* o, fg_stats* stats) {
   const unsigned nbN = blocks_for(P->N);
   const double* c = P->c ? P->c : P->zeroN;
   hipLaunchKernelGGL(k_pff_history, dim3(nbN), dim3(256), 0, P->stream, P->F, c, P->E, P->nu, P->Om, P->smax, P->H,
-                     v.a, v.r, v.x, P->gc, P->lc, P->part, P->part2, P->flags, P->N);
+                     v.a, v.r, v.x, P->gc, P->lc, P->part, P->part2, P->flags, P->N, P->law);
   check_launch();
   reduce_to(P, P->part, (int)nbN, 0);  // sum H
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, P->stream, P->part2, (int)nbN, P->ksc, (double*)nullptr,
@@ -1042,7 +1051,7 @@ void fick(fg_plan* P, double dt, const double* cdot, const fg_solver_opts* o, fg
   }
   for (int it = 0; it < o->max_newton; ++it) {
     hipLaunchKernelGGL(k_fick_mu, dim3(nbN), dim3(256), 0, P->stream, P->c, P->F, d, P->E, P->nu, P->Om, P->RT,
-                       P->cmax, v.mu, v.w, P->part, P->flags, N, full_jacobian);
+                       P->cmax, v.mu, v.w, P->part, P->flags, N, full_jacobian, P->law);
     check_launch();
     reduce_to(P, P->part, (int)nbN, 2);  // sum 1/w
     hipLaunchKernelGGL(k_fick_residual, dim3(nbN), dim3(256), 0, P->stream, P->c, v.ct, v.mu, v.A6, cdot, dt, g,
@@ -1165,6 +1174,19 @@ fg_status fg_plan_create(const int grid[3], const double spacing[3], fg_precisio
 }
 
 size_t fg_plan_workspace_bytes(const fg_plan* P) { return P ? P->need : 0; }
+
+static_assert(FG_LAW_NEO_HOOKE == fg::kLawNH && FG_LAW_SVK == fg::kLawSVK, "law codes");
+
+fg_status fg_set_law(fg_plan* P, int law) {
+  if (!P || P->batch_group || (law != ::FG_LAW_NEO_HOOKE && law != ::FG_LAW_SVK)) return FG_E_ARG;
+  if (P->ws) {
+    P->err = "the law must be set before the workspace";
+    return FG_E_STATE;
+  }
+  P->law = law;
+  P->need = layout(P, nullptr) + kAlign;
+  return FG_OK;
+}
 
 fg_status fg_plan_set_workspace(fg_plan* P, void* dev, size_t bytes) {
   if (!P || !dev || P->batch_group) return FG_E_ARG;
@@ -1403,8 +1425,7 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
     const unsigned nbN = blocks_for(P->N);
     if (P->prec == FG_FP64) {
       constitutive(P, nullptr, nullptr, P->st, nullptr);
-      hipLaunchKernelGGL((k_contract<double>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, y, x,
-                         (const double*)P->st, P->N);
+      launch_contract<double>(P, y, x);
       check_launch();
       C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
       project9<double>(P, y, y, y, epi);
@@ -1414,8 +1435,7 @@ fg_status fg_apply_operator(fg_plan* P, const double* x, double* y) {
       float* yf = (float*)P->S;
       hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_stride_blocks(n9)), dim3(256), 0, P->stream, xf, x,
                          n9);
-      hipLaunchKernelGGL((k_contract<float>), dim3(blocks_for(P->N / 2)), dim3(256), 0, P->stream, yf,
-                         (const float*)xf, (const float*)P->st, P->N);
+      launch_contract<float>(P, yf, (const float*)xf);
       check_launch();
       C2REpi epi{1.0, nullptr, true, nullptr, Skip{}};
       project9<float>(P, yf, yf, yf, epi);

@@ -60,6 +60,91 @@ __device__ __forceinline__ NHPoint neo_hooke_point(const double (&f)[9], double 
   return q;
 }
 
+// Saint-Venant-Kirchhoff point (Sec. 2.1 eqs. (3), (4), (11), (12) with the
+// swelling of eq. (2); energy per reference volume, F_e = F / s):
+//   E_e = (s^-2 F^T F - I) / 2,  S = lambda tr E_e I + 2 G E_e,
+//   P = g s^-2 F S   (eq. (12) when Omega c = 0),
+// the tangent state {St = g s^-2 S, lp = g s^-4 lambda, mp = g s^-4 G} of
+// svk_apply, and dP/dOmega = g s^-2 F [ -(2c/3a) S + lambda tr(dE) I + 2 G dE ]
+// with dE = -(c/3a)(2 E_e + I), a = 1 + Omega c.
+// ok = false when 1 + Omega c <= 0 (then a = 1 is used).
+struct SVKPoint {
+  double P[9];
+  double St[6];  // 00 11 22 12 02 01
+  double lp, mp;
+  double t, q;   // tr E_e, E_e : E_e
+  double e[6];   // E_e
+  double S[6];   // undegraded S
+  double s2inv, g, a, lam, G;
+  bool ok;
+};
+
+__device__ __forceinline__ SVKPoint svk_point(const double (&f)[9], double cc, double dd, double EE, double nn,
+                                              double oo) {
+  SVKPoint q;
+  double a = 1.0 + oo * cc;
+  q.ok = a > 0.0;
+  if (!q.ok) a = 1.0;
+  q.a = a;
+  q.G = EE / (2.0 * (1.0 + nn));
+  q.lam = EE * nn / ((1.0 + nn) * (1.0 - 2.0 * nn));
+  q.g = (1.0 - dd) * (1.0 - dd);
+  q.s2inv = exp(-2.0 / 3.0 * log(a));
+  // C = F^T F (symmetric): C_mn = sum_k F_km F_kn
+  auto Cmn = [&](int m, int n) { return f[m] * f[n] + f[3 + m] * f[3 + n] + f[6 + m] * f[6 + n]; };
+  const double e00 = 0.5 * (q.s2inv * Cmn(0, 0) - 1.0), e11 = 0.5 * (q.s2inv * Cmn(1, 1) - 1.0),
+               e22 = 0.5 * (q.s2inv * Cmn(2, 2) - 1.0);
+  const double e12 = 0.5 * q.s2inv * Cmn(1, 2), e02 = 0.5 * q.s2inv * Cmn(0, 2), e01 = 0.5 * q.s2inv * Cmn(0, 1);
+  q.e[0] = e00;
+  q.e[1] = e11;
+  q.e[2] = e22;
+  q.e[3] = e12;
+  q.e[4] = e02;
+  q.e[5] = e01;
+  q.t = e00 + e11 + e22;
+  q.q = e00 * e00 + e11 * e11 + e22 * e22 + 2.0 * (e12 * e12 + e02 * e02 + e01 * e01);
+  const double lt = q.lam * q.t, G2 = 2.0 * q.G;
+  q.S[0] = lt + G2 * e00;
+  q.S[1] = lt + G2 * e11;
+  q.S[2] = lt + G2 * e22;
+  q.S[3] = G2 * e12;
+  q.S[4] = G2 * e02;
+  q.S[5] = G2 * e01;
+  const double gs = q.g * q.s2inv;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) q.St[k] = gs * q.S[k];
+  q.lp = gs * q.s2inv * q.lam;
+  q.mp = gs * q.s2inv * q.G;
+  const double Sm[9] = {q.St[0], q.St[5], q.St[4], q.St[5], q.St[1], q.St[3], q.St[4], q.St[3], q.St[2]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      q.P[3 * i + j] = f[3 * i] * Sm[j] + f[3 * i + 1] * Sm[3 + j] + f[3 * i + 2] * Sm[6 + j];
+  return q;
+}
+
+// dP/dOmega of the SVK law at fixed F (q from svk_point at the same point).
+__device__ __forceinline__ void svk_dP_dOmega(const SVKPoint& q, const double (&f)[9], double cc, double (&o)[9]) {
+  const double k = cc / (3.0 * q.a);
+  const double(&e)[6] = q.e;
+  // dE = -k (2 E_e + I)
+  const double de[6] = {-k * (2.0 * e[0] + 1.0), -k * (2.0 * e[1] + 1.0), -k * (2.0 * e[2] + 1.0),
+                        -k * 2.0 * e[3],         -k * 2.0 * e[4],         -k * 2.0 * e[5]};
+  const double ltd = q.lam * (de[0] + de[1] + de[2]);
+  const double m = -2.0 * k;  // -(2c / 3a)
+  const double in6[6] = {m * q.S[0] + ltd + 2.0 * q.G * de[0], m * q.S[1] + ltd + 2.0 * q.G * de[1],
+                         m * q.S[2] + ltd + 2.0 * q.G * de[2], m * q.S[3] + 2.0 * q.G * de[3],
+                         m * q.S[4] + 2.0 * q.G * de[4],       m * q.S[5] + 2.0 * q.G * de[5]};
+  const double In[9] = {in6[0], in6[5], in6[4], in6[5], in6[1], in6[3], in6[4], in6[3], in6[2]};
+  const double gs = q.g * q.s2inv;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      o[3 * i + j] = gs * (f[3 * i] * In[j] + f[3 * i + 1] * In[3 + j] + f[3 * i + 2] * In[6 + j]);
+}
+
 // Constitutive update over the field: P (FP64) and the tangent state (type
 // S).  F is either the field F (9 planes) or, when Fu != nullptr, the uniform
 // tensor Fu.  P may be nullptr; state may be nullptr.  pnorm_partials
@@ -70,7 +155,7 @@ k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, cons
                const double* __restrict__ d, const double* __restrict__ E, const double* __restrict__ nu,
                const double* __restrict__ Om, double* __restrict__ P, S* __restrict__ state,
                double* __restrict__ pnorm_partials, int* __restrict__ flags, long N,
-               const int* __restrict__ idle) {
+               const int* __restrict__ idle, int law) {
   // voxel i of batch item b = blockIdx.y (item-major fields: material, c and
   // d at b N + i, tensor fields at (9 b + k) N + i, Fu per item); items with
   // idle[b] != 0 are left alone (idle may be nullptr); partial sums at
@@ -84,7 +169,7 @@ k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, cons
     F += b * 9 * N;
     if (Fu) Fu += 9 * b;
     if (P) P += b * 9 * N;
-    if (state) state += b * 12 * N;
+    if (state) state += b * state_words(law) * N;
     c += b * N;
     d += b * N;
     E += b * N;
@@ -93,22 +178,43 @@ k_constitutive(const double* __restrict__ F, const double* __restrict__ Fu, cons
     double f[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) f[k] = Fu ? Fu[k] : F[k * N + i];
-    const NHPoint q = neo_hooke_point(f, c[i], d[i], E[i], nu[i], Om[i]);
-    if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
-    if (P) {
+    if (law == kLawSVK) {
+      const SVKPoint q = svk_point(f, c[i], d[i], E[i], nu[i], Om[i]);
+      if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
+      if (P) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const double pk = q.c1 * f[k] + q.c2 * q.A[k];
-        P[k * N + i] = pk;
-        pp += pk * pk;
+        for (int k = 0; k < 9; ++k) {
+          P[k * N + i] = q.P[k];
+          pp += q.P[k] * q.P[k];
+        }
       }
-    }
-    if (state) {
+      if (state) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) state[k * N + i] = (S)q.A[k];
-      state[9 * N + i] = (S)q.alpha;
-      state[10 * N + i] = (S)q.beta;
-      state[11 * N + i] = (S)q.gamma;
+        for (int k = 0; k < 9; ++k) state[k * N + i] = (S)f[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) state[(9 + k) * N + i] = (S)q.St[k];
+        state[15 * N + i] = (S)q.lp;
+        state[16 * N + i] = (S)q.mp;
+        state[17 * N + i] = (S)0;
+      }
+    } else {
+      const NHPoint q = neo_hooke_point(f, c[i], d[i], E[i], nu[i], Om[i]);
+      if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
+      if (P) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const double pk = q.c1 * f[k] + q.c2 * q.A[k];
+          P[k * N + i] = pk;
+          pp += pk * pk;
+        }
+      }
+      if (state) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) state[k * N + i] = (S)q.A[k];
+        state[9 * N + i] = (S)q.alpha;
+        state[10 * N + i] = (S)q.beta;
+        state[11 * N + i] = (S)q.gamma;
+      }
     }
   }
   if (pnorm_partials) {
@@ -123,7 +229,7 @@ __global__ void __launch_bounds__(256)
 k_tangent_apply_f64(const double* __restrict__ F, const double* __restrict__ c, const double* __restrict__ d,
                     const double* __restrict__ E, const double* __restrict__ nu, const double* __restrict__ Om,
                     const double* __restrict__ W, const double* __restrict__ X, double* __restrict__ Y,
-                    int* __restrict__ flags, long N) {
+                    int* __restrict__ flags, long N, int law) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   double f[9], x[9], y[9];
@@ -132,18 +238,24 @@ k_tangent_apply_f64(const double* __restrict__ F, const double* __restrict__ c, 
     f[k] = F[k * N + i];
     x[k] = W[k] + X[k * N + i];
   }
-  const NHPoint q = neo_hooke_point(f, c[i], d[i], E[i], nu[i], Om[i]);
-  if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
-  tangent_apply<double>(q.A, q.alpha, q.beta, q.gamma, x, y);
+  if (law == kLawSVK) {
+    const SVKPoint q = svk_point(f, c[i], d[i], E[i], nu[i], Om[i]);
+    if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
+    svk_apply<double>(f, q.St, q.lp, q.mp, x, y);
+  } else {
+    const NHPoint q = neo_hooke_point(f, c[i], d[i], E[i], nu[i], Om[i]);
+    if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
+    tangent_apply<double>(q.A, q.alpha, q.beta, q.gamma, x, y);
+  }
 #pragma unroll
   for (int k = 0; k < 9; ++k) Y[k * N + i] = y[k];
 }
 
-// Tangent contraction Y = K : X from the 12-word state (one application of
-// K outside the CG, e.g. the operator diagnostic and the adjoint's
-// right-hand side).  Two voxels per thread (one 2-vector load per plane); N
-// is even.
-template <typename T>
+// Tangent contraction Y = K : X from the tangent state (12 words for the
+// Neo-Hookean law, 18 for SVK; one application of K outside the CG, e.g.
+// the operator diagnostic and the adjoint's right-hand side).  Two voxels per
+// thread (one 2-vector load per plane); N is even.
+template <typename T, int LAW>
 __global__ void __launch_bounds__(256)
 k_contract(T* __restrict__ Y, const T* __restrict__ X, const T* __restrict__ st, long N) {
   using V = cplx<T>;
@@ -163,10 +275,23 @@ k_contract(T* __restrict__ Y, const T* __restrict__ X, const T* __restrict__ st,
     A0[k] = a.x;
     A1[k] = a.y;
   }
-  const V al = sv[9 * N2v + i], be = sv[10 * N2v + i], ga = sv[11 * N2v + i];
   T Y0[9], Y1[9];
-  tangent_apply<T>(A0, al.x, be.x, ga.x, X0, Y0);
-  tangent_apply<T>(A1, al.y, be.y, ga.y, X1, Y1);
+  if constexpr (LAW == kLawSVK) {
+    T S0[6], S1[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const V a = sv[(9 + k) * N2v + i];
+      S0[k] = a.x;
+      S1[k] = a.y;
+    }
+    const V lp = sv[15 * N2v + i], mp = sv[16 * N2v + i];
+    svk_apply<T>(A0, S0, lp.x, mp.x, X0, Y0);
+    svk_apply<T>(A1, S1, lp.y, mp.y, X1, Y1);
+  } else {
+    const V al = sv[9 * N2v + i], be = sv[10 * N2v + i], ga = sv[11 * N2v + i];
+    tangent_apply<T>(A0, al.x, be.x, ga.x, X0, Y0);
+    tangent_apply<T>(A1, al.y, be.y, ga.y, X1, Y1);
+  }
 #pragma unroll
   for (int k = 0; k < 9; ++k) yv[k * N2v + i] = mk<V>(Y0[k], Y1[k]);
 }
@@ -359,18 +484,36 @@ __global__ void __launch_bounds__(256) k_fill_uniform9(T* __restrict__ dst, cons
 //   dL/dlogE(x) = (W + lam(x)) : P(x) / N,
 //   dL/dOmega(x) = (W + lam(x)) : dP/dOmega(x) / N,
 // dP/dlogE = P (both Lame constants scale with E) and
-//   dP/dOmega = g [ -(2/3) G c (1 + Omega c)^{-5/3} F - lambda c / (1 + Omega c) F^-T ].
+//   dP/dOmega = g [ -(2/3) G c (1 + Omega c)^{-5/3} F - lambda c / (1 + Omega c) F^-T ]
+// for the Neo-Hookean law (svk_dP_dOmega for SVK).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_adjoint_grad(const double* __restrict__ F, const double* __restrict__ c, const double* __restrict__ d,
                const double* __restrict__ E, const double* __restrict__ nu, const double* __restrict__ Om,
                const T* __restrict__ lam, const double* __restrict__ W, double* __restrict__ gE,
-               double* __restrict__ gO, int* __restrict__ flags, long N) {
+               double* __restrict__ gO, int* __restrict__ flags, long N, int law) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   double f[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) f[k] = F[k * N + i];
+  if (law == kLawSVK) {
+    const SVKPoint q = svk_point(f, c[i], d[i], E[i], nu[i], Om[i]);
+    if (!q.ok) flags[0] = FG_FLAG_DOMAIN;
+    double o[9];
+    svk_dP_dOmega(q, f, c[i], o);
+    double sE = 0.0, sO = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double w = W[k] + (double)lam[k * N + i];
+      sE += w * q.P[k];
+      sO += w * o[k];
+    }
+    const double invN = 1.0 / (double)N;
+    if (gE) gE[i] = sE * invN;
+    if (gO) gO[i] = sO * invN;
+    return;
+  }
   double cof[9];
   cof[0] = f[4] * f[8] - f[5] * f[7];
   cof[1] = f[5] * f[6] - f[3] * f[8];

@@ -46,7 +46,8 @@ __device__ __forceinline__ void sym_eig3(double a00, double a11, double a22, dou
 }
 
 // History update (eqs. (7), (8)): effective Cauchy stress
-//   sigma = J^-1 [ G s^-2 F F^T + (lambda ln J_e - G) I ],
+//   sigma = J^-1 [ G s^-2 F F^T + (lambda ln J_e - G) I ]   (Neo-Hookean),
+//   sigma = J^-1 s^-2 F S F^T                               (SVK),
 // D_f = < sum <sigma_i>^2 / sigma_max^2 - 1 >, H <- max(H, gc/(2 lc) D_f).
 // Writes the PFF coefficient a = gc/lc + 2H, the right-hand side b = 2H (into
 // r), zeroes the solution x, and per-block partials of H (part_h) and b.b
@@ -55,7 +56,8 @@ __global__ void __launch_bounds__(256)
 k_pff_history(const double* __restrict__ F, const double* __restrict__ c, const double* __restrict__ E,
               const double* __restrict__ nu, const double* __restrict__ Om, const double* __restrict__ smax,
               double* __restrict__ H, double* __restrict__ acoef, double* __restrict__ r, double* __restrict__ x,
-              double gc, double lc, double* __restrict__ part_h, double* __restrict__ part_b, int* flags, long N) {
+              double gc, double lc, double* __restrict__ part_h, double* __restrict__ part_b, int* flags, long N,
+              int law) {
   __shared__ double red[16];
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double hv = 0.0, bb = 0.0;
@@ -86,9 +88,21 @@ k_pff_history(const double* __restrict__ F, const double* __restrict__ c, const 
       for (int jj = 0; jj < 3; ++jj)
         b[3 * ii + jj] = f[3 * ii] * f[3 * jj] + f[3 * ii + 1] * f[3 * jj + 1] + f[3 * ii + 2] * f[3 * jj + 2];
     const double sh = lam * lnJe - G;
-    const double s00 = (G * s2inv * b[0] + sh) * iJ, s11 = (G * s2inv * b[4] + sh) * iJ,
-                 s22 = (G * s2inv * b[8] + sh) * iJ;
-    const double s01 = G * s2inv * b[1] * iJ, s02 = G * s2inv * b[2] * iJ, s12 = G * s2inv * b[5] * iJ;
+    double s00 = (G * s2inv * b[0] + sh) * iJ, s11 = (G * s2inv * b[4] + sh) * iJ, s22 = (G * s2inv * b[8] + sh) * iJ;
+    double s01 = G * s2inv * b[1] * iJ, s02 = G * s2inv * b[2] * iJ, s12 = G * s2inv * b[5] * iJ;
+    if (law == kLawSVK) {
+      // undegraded P_0 = s^-2 F S (d = 0), sigma = J^-1 P_0 F^T
+      const SVKPoint q = svk_point(f, cc, 0.0, EE, nn, Om[i]);
+      auto sg = [&](int ii, int jj) {
+        return (q.P[3 * ii] * f[3 * jj] + q.P[3 * ii + 1] * f[3 * jj + 1] + q.P[3 * ii + 2] * f[3 * jj + 2]) * iJ;
+      };
+      s00 = sg(0, 0);
+      s11 = sg(1, 1);
+      s22 = sg(2, 2);
+      s01 = sg(0, 1);
+      s02 = sg(0, 2);
+      s12 = sg(1, 2);
+    }
     double e0, e1, e2;
     sym_eig3(s00, s11, s22, s01, s02, s12, e0, e1, e2);
     const double sm = smax[i];
@@ -191,13 +205,15 @@ k_fick_coef(const double* __restrict__ F, const double* __restrict__ d, const do
 }
 
 // Chemical potential mu = RT log(c/(1-c)) + mu_e / c_max with
-//   mu_e = -g Omega / (3 (1 + Omega c)) [ G (s^-2 tr C - 3) + 3 lambda ln J_e ],
+//   mu_e = -g Omega / (3 (1 + Omega c)) [ G (s^-2 tr C - 3) + 3 lambda ln J_e ]
+// (Neo-Hookean) or, for SVK with t = tr E_e, q = E_e : E_e,
+//   mu_e = -g Omega / (3 (1 + Omega c)) [ 2 lambda t^2 + 4 G q + (3 lambda + 2 G) t ],
 // the slope w = RT (1/c + 1/(1-c)) and partials of 1/w.  Flags c outside (0,1).
 __global__ void __launch_bounds__(256)
 k_fick_mu(const double* __restrict__ c, const double* __restrict__ F, const double* __restrict__ d,
           const double* __restrict__ E, const double* __restrict__ nu, const double* __restrict__ Om, double RT,
           double cmax, double* __restrict__ mu, double* __restrict__ w, double* __restrict__ part_winv, int* flags,
-          long N, int full_jacobian) {
+          long N, int full_jacobian, int law) {
   __shared__ double red[16];
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double wi = 0.0;
@@ -229,13 +245,22 @@ k_fick_mu(const double* __restrict__ c, const double* __restrict__ F, const doub
     const double la = log(a > 0.0 ? a : 1.0);
     const double s2inv = exp(-2.0 / 3.0 * la);
     const double lnJe = log(J) - la;
-    const double mue = -g * oo / (3.0 * a) * (G * (trC * s2inv - 3.0) + 3.0 * lam * lnJe);
+    double mue = -g * oo / (3.0 * a) * (G * (trC * s2inv - 3.0) + 3.0 * lam * lnJe);
+    // d(mu_e / cmax)/dc at fixed F and d:
+    // g Omega^2 / (3 a^2) [ (5/3) G a^(-2/3) tr C - 3 G + 3 lambda (ln J_e + 1) ] / cmax
+    double dmue = g * oo * oo / (3.0 * a * a) * ((5.0 / 3.0) * G * s2inv * trC - 3.0 * G + 3.0 * lam * (lnJe + 1.0));
+    if (law == kLawSVK) {
+      const SVKPoint q = svk_point(f, cc, dd, EE, nn, oo);
+      const double T = 2.0 * lam * q.t * q.t + 4.0 * G * q.q + (3.0 * lam + 2.0 * G) * q.t;
+      mue = -g * oo / (3.0 * a) * T;
+      // g Omega^2 / (3 a^2) [ T + ((4 lambda t + 3 lambda + 2 G)(2 t + 3) + 8 G (2 q + t)) / 3 ]
+      dmue = g * oo * oo / (3.0 * a * a) *
+             (T + ((4.0 * lam * q.t + 3.0 * lam + 2.0 * G) * (2.0 * q.t + 3.0) + 8.0 * G * (2.0 * q.q + q.t)) / 3.0);
+    }
     mu[i] = RT * log(cc / (1.0 - cc)) + mue / cmax;
     double ww = RT * (1.0 / cc + 1.0 / (1.0 - cc));
     if (full_jacobian) {
-      // d(mu_e / cmax)/dc at fixed F and d:
-      // g Omega^2 / (3 a^2) [ (5/3) G a^(-2/3) tr C - 3 G + 3 lambda (ln J_e + 1) ] / cmax
-      ww += g * oo * oo / (3.0 * a * a) * ((5.0 / 3.0) * G * s2inv * trC - 3.0 * G + 3.0 * lam * (lnJe + 1.0)) / cmax;
+      ww += dmue / cmax;
       if (!(ww > 0.0)) {
         flags[0] = FG_FLAG_DOMAIN;  // the linear step would not be SPD
         ww = RT * (1.0 / cc + 1.0 / (1.0 - cc));

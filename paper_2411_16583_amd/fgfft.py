@@ -19,10 +19,12 @@ LIB_PATH = os.path.join(HERE, "libfgfft.so")
 FG_OK, FG_E_ARG, FG_E_SIZE, FG_E_HIP, FG_E_NOCONV, FG_E_BREAKDOWN, FG_E_DOMAIN, FG_E_STATE = range(8)
 FG_FP64, FG_MIXED = 0, 1
 PRECISIONS = {"fp64": FG_FP64, "mixed": FG_MIXED}
+FG_LAW_NEO_HOOKE, FG_LAW_SVK = 0, 1
+LAWS = {"neo_hookean": FG_LAW_NEO_HOOKE, "svk": FG_LAW_SVK}
 
 # Every function declared in include/fgfft.h.
 EXPORTED = [
-    "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_material",
+    "fg_plan_create", "fg_plan_workspace_bytes", "fg_plan_set_workspace", "fg_set_law", "fg_set_material",
     "fg_set_state", "fg_apply_macro", "fg_newton_solve", "fg_newton_solve_shifted", "fg_newton_linear_begin", "fg_cg_iterate",
     "fg_adjoint_gradient", "fg_homogenized_tangent", "fg_residual", "fg_homogenized_stress", "fg_stress",
     "fg_apply_operator", "fg_project", "fg_project_noalloc", "fg_project_grad", "fg_fft_r2c", "fg_fft_c2r", "pff_solve", "fick_step", "fick_step_full",
@@ -96,6 +98,7 @@ def load_library(path=LIB_PATH):
         "fg_plan_create": ([ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_int, vp, ctypes.POINTER(vp)], c_int),
         "fg_plan_workspace_bytes": ([vp], c_size),
         "fg_plan_set_workspace": ([vp, vp, c_size], c_int),
+        "fg_set_law": ([vp, c_int], c_int),
         "fg_set_material": ([vp, dptr, dptr, dptr, dptr, dptr, c_double, c_double, c_double, c_double], c_int),
         "fg_set_state": ([vp, dptr, dptr, dptr, dptr], c_int),
         "fg_apply_macro": ([vp, ctypes.POINTER(c_double)], c_int),
@@ -194,10 +197,13 @@ class Plan:
     """One grid / precision / stream.  Holds references to every tensor it
     was given so that their memory outlives the plan's use of it."""
 
-    def __init__(self, grid, spacing, precision="fp64", stream=None, device="cuda"):
+    def __init__(self, grid, spacing, precision="fp64", stream=None, device="cuda", law="neo_hookean"):
         import torch
 
+        if law not in LAWS:
+            raise ValueError(f"unknown law {law!r}; one of {sorted(LAWS)}")
         self.lib = load_library()
+        self.law = law
         self.grid = tuple(int(n) for n in grid)
         self.spacing = tuple(float(h) for h in spacing)
         self.N = int(np.prod(self.grid))
@@ -213,6 +219,8 @@ class Plan:
         if st != FG_OK:
             raise FgError(st, f"fg_plan_create{self.grid}: {self.lib.fg_status_string(st).decode()}")
         self.handle = out
+        if law != "neo_hookean":
+            self._check(self.lib.fg_set_law(self.handle, LAWS[law]), "fg_set_law")
         nbytes = int(self.lib.fg_plan_workspace_bytes(self.handle))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self._check(self.lib.fg_plan_set_workspace(self.handle, ctypes.c_void_p(self.workspace.data_ptr()),

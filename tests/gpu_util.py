@@ -17,7 +17,7 @@ def host(t, shape=None):
 
 
 def plan_for(work, precision="fp64", with_chem=False):
-    plan = Plan(work["shape"], work["spacing"], precision)
+    plan = Plan(work["shape"], work["spacing"], precision, law=work.get("law", "neo_hookean"))
     mats = dict(E=dt(work["E"]), nu=dt(work["nu"]), Omega=dt(work["Omega"]),
                 D=dt(work["D"]), sigma_max=dt(work["sigma_max"]))
     plan.set_material(mats["E"], mats["nu"], mats["Omega"], mats["D"], mats["sigma_max"],

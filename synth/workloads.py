@@ -48,6 +48,7 @@ __all__ = [
     "homogeneous_workload",
     "plane_inclusion_workload",
     "in_plane_schedule",
+    "plate_workload",
 ]
 
 GAS_R = 8.314462618  # J / (mol K)
@@ -162,6 +163,82 @@ def plane_inclusion_workload(n=32, radius=None, n_inc=3, total_strain=0.01, thic
         c0=np.zeros(shape), d0=np.zeros(shape),
         loads=in_plane_schedule(total_strain, n_inc),
         tol_newton=1e-8, tol_lin=1e-10,
+    )
+
+
+def plate_workload(n=64, corner=0, plate=40, corner_len=20, n_steps=60, dt=1.0, q_edge=1e-3, q_corner=3e-3,
+                   law="svk", buffer_E=1e-2):
+    """The chemo-mechanical plate of Sec. 4.3 (Table of Sec. 4.3): a plane
+    grid (1, n, n) of side 0.008 mm (voxel 1.25e-4 mm, also the thickness),
+    a homogeneous plate (E = 15 GPa, nu = 0.3, Omega = 1.3, D = 1e-9 mm^2/s,
+    sigma_max = 50 MPa, l_c = 2 voxels) in a buffer with small stiffness and
+    diffusivity and no swelling, an inward source on the plate's one-voxel
+    boundary band (delta L = 1 voxel), stronger near one corner.
+
+    Readings (the figure that fixes the geometry is not available, the units
+    of the printed fluxes do not fit a normalised concentration, and two of
+    the table's values do not let this discretisation run):
+    * the plate is the centred plate x plate square (40 of 64 voxels, its
+      corners near 0.2 L and 0.8 L, where the paper's stress concentrates);
+    * the source rates are q_edge and q_corner per second in normalised
+      concentration, in the band voxels; q_corner covers the band voxels
+      within corner_len voxels of the plate corner `corner` (0: high i1 and
+      high i2, then 90-degree turns: the fields of corner k are those of
+      corner 0 turned k times by numpy.rot90 over (i1, i2));
+    * q_corner / q_edge = 3 over 20-voxel corner segments (the paper: 1.5,
+      extent not given): the forward-difference flux of eqs. (49)-(50) puts
+      the plate's mobility on the faces from its upper band into the buffer
+      and the buffer's on the faces below its lower band, so the lower bands
+      keep more of their source; with the ratio 1.5 the tension near the
+      (low, low) corner (0.97 sigma_max) stays above that near the flux
+      corner (0.75) and damage starts there whatever the flux corner;
+    * the buffer's stiffness is buffer_E E = 1e-2 E (table: 1e-5 E): the
+      swollen, compressed one-voxel band on a softer foundation makes the
+      Newton system indefinite (negative geometric stiffness of the
+      compressed band; p.Kp < 0 in the first step for two of the four
+      corners at 1e-3 E), and at 1e-5 E the CG also reaches its rounding
+      floor (relative residual 8e-8, incompatible direction at 7e-8) before
+      tol_lin; the buffer's diffusivity is 1e-5 D as in the table;
+    * c_0 = 1e-2 (the initial concentration of Sec. 4.1), dt = 1 s;
+    * g_c / l_c as printed (2e-3 / 2.5e-4) enters only as the scale of H,
+      which cancels in the phase-field equation d - l_c^2 Lap d = (1 - d) D_f
+      (history reading), so g_c = 8 l_c here;
+    * the law is the paper's Saint-Venant-Kirchhoff law; F_macro = I (the
+      compliant buffer lets the plate deform freely); the chemistry is
+      solved with the full Jacobian (the mu_c-only Newton of Alg. 3 stalls
+      at Omega = 1.3).
+    """
+    shape = (1, int(n), int(n))
+    h = 0.008e-3 / n
+    spacing = (h, h, h)
+    lo = (n - plate) // 2
+    hi = lo + plate
+    part = np.zeros((n, n), dtype=bool)
+    part[lo:hi, lo:hi] = True
+    band = part.copy()
+    band[lo + 1:hi - 1, lo + 1:hi - 1] = False
+    near = np.zeros((n, n), dtype=bool)
+    near[hi - corner_len:hi, hi - corner_len:hi] = True  # corner 0: high i1, high i2
+    rate = np.where(band, q_edge, 0.0)
+    rate = np.where(band & near, q_corner, rate)
+    rate = np.rot90(rate, k=corner).copy()
+    corner_mask = np.zeros((n, n), dtype=bool)
+    corner_mask[hi - 1, hi - 1] = True
+    site = tuple(int(v) for v in np.argwhere(np.rot90(corner_mask, k=corner))[0])  # plate corner of the flux
+    part3 = part[None]
+    Ep, Dp = 15e9, 1e-15
+    E = np.where(part3, Ep, buffer_E * Ep)
+    D = np.where(part3, Dp, 1e-5 * Dp)
+    Omega = np.where(part3, 1.3, 0.0)
+    lc = 2.0 * h
+    return Workload(
+        name="plate", shape=shape, spacing=spacing, phase=part3, corner=corner, law=law,
+        E=E, nu=np.full(shape, 0.3), Omega=Omega, D=D, sigma_max=np.full(shape, 50e6),
+        gc=8.0 * lc, lc=lc, RT=GAS_R * 298.15, c_max=3.0e4,
+        c0=np.full(shape, 1e-2), d0=np.zeros(shape), cdot_B=rate[None].copy(),
+        dt=dt, n_steps=n_steps, loads=[np.eye(3)] * n_steps, jacobian="full",
+        tol_newton=1e-8, tol_lin=1e-6, tol_chem=1e-8,
+        corner_site=site,
     )
 
 

@@ -12,8 +12,9 @@
  * --------------------------------
  * Grid: N0 x N1 x N2 voxels on a periodic box, spacing h[3] (metres), N2 the
  * fastest axis, N = N0 N1 N2.  Supported sizes: N0, N1 in {4, 6, 8, 12, 16,
- * 24, 32, 48, 64, 96, 128, 256}, and also N0 = 1; N2 = 2 M with M in {2, 3,
- * 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256}.  Others return FG_E_SIZE.
+ * 24, 32, 48, 64, 96, 128, 256}, and also N0 = 1 and N1 = 512; N2 = 2 M with
+ * M in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256}.  Others return
+ * FG_E_SIZE.
  * N0 = 1 is a plane (the 2-D problems of Sec. 4.3 and 5.1): the box is one
  * voxel thick and periodic along axis 0, so every difference along axis 0
  * vanishes and F_00 stays at its macroscopic value (plane strain, with the

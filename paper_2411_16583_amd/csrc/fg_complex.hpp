@@ -62,10 +62,10 @@ __device__ __forceinline__ void st_stream_f4(void* p, float4 v) {
 template <typename C> __device__ __forceinline__ C mul_mi(C a) { return mk<C>(a.y, -a.x); }
 template <typename C> __device__ __forceinline__ C mul_pi(C a) { return mk<C>(-a.y, a.x); }
 
-// cos(2 pi k / 48) and sin(2 pi k / 48), k = 0..47, correctly rounded.
-// Every twiddle of the radix-2/3/4/6/8/12/16 codelets is one of these.
-constexpr double kCos48[48] = {1.0, 0.9914448613738104, 0.9659258262890683, 0.9238795325112867, 0.8660254037844386, 0.7933533402912352, 0.7071067811865476, 0.6087614290087207, 0.5, 0.3826834323650898, 0.25881904510252074, 0.1305261922200516, 0.0, -0.1305261922200516, -0.25881904510252074, -0.3826834323650898, -0.5, -0.6087614290087207, -0.7071067811865476, -0.7933533402912352, -0.8660254037844386, -0.9238795325112867, -0.9659258262890683, -0.9914448613738104, -1.0, -0.9914448613738104, -0.9659258262890683, -0.9238795325112867, -0.8660254037844386, -0.7933533402912352, -0.7071067811865476, -0.6087614290087207, -0.5, -0.3826834323650898, -0.25881904510252074, -0.1305261922200516, 0.0, 0.1305261922200516, 0.25881904510252074, 0.3826834323650898, 0.5, 0.6087614290087207, 0.7071067811865476, 0.7933533402912352, 0.8660254037844386, 0.9238795325112867, 0.9659258262890683, 0.9914448613738104};
-constexpr double kSin48[48] = {0.0, 0.1305261922200516, 0.25881904510252074, 0.3826834323650898, 0.5, 0.6087614290087207, 0.7071067811865476, 0.7933533402912352, 0.8660254037844386, 0.9238795325112867, 0.9659258262890683, 0.9914448613738104, 1.0, 0.9914448613738104, 0.9659258262890683, 0.9238795325112867, 0.8660254037844386, 0.7933533402912352, 0.7071067811865476, 0.6087614290087207, 0.5, 0.3826834323650898, 0.25881904510252074, 0.1305261922200516, 0.0, -0.1305261922200516, -0.25881904510252074, -0.3826834323650898, -0.5, -0.6087614290087207, -0.7071067811865476, -0.7933533402912352, -0.8660254037844386, -0.9238795325112867, -0.9659258262890683, -0.9914448613738104, -1.0, -0.9914448613738104, -0.9659258262890683, -0.9238795325112867, -0.8660254037844386, -0.7933533402912352, -0.7071067811865476, -0.6087614290087207, -0.5, -0.3826834323650898, -0.25881904510252074, -0.1305261922200516};
+// cos(2 pi k / 96) and sin(2 pi k / 96), k = 0..95, correctly rounded.
+// Every twiddle of the radix-2/3/4/6/8/12/16/24/32/48 codelets is one of these.
+constexpr double kCos96[96] = {1.0, 0.9978589232386035, 0.9914448613738104, 0.9807852804032304, 0.9659258262890683, 0.9469301294951057, 0.9238795325112867, 0.8968727415326883, 0.8660254037844386, 0.8314696123025452, 0.7933533402912352, 0.7518398074789774, 0.7071067811865476, 0.6593458151000688, 0.6087614290087207, 0.5555702330196022, 0.5, 0.4422886902190013, 0.3826834323650898, 0.3214394653031616, 0.25881904510252074, 0.19509032201612828, 0.1305261922200516, 0.06540312923014306, 0.0, -0.06540312923014306, -0.1305261922200516, -0.19509032201612828, -0.25881904510252074, -0.3214394653031616, -0.3826834323650898, -0.4422886902190013, -0.5, -0.5555702330196022, -0.6087614290087207, -0.6593458151000688, -0.7071067811865476, -0.7518398074789774, -0.7933533402912352, -0.8314696123025452, -0.8660254037844386, -0.8968727415326883, -0.9238795325112867, -0.9469301294951057, -0.9659258262890683, -0.9807852804032304, -0.9914448613738104, -0.9978589232386035, -1.0, -0.9978589232386035, -0.9914448613738104, -0.9807852804032304, -0.9659258262890683, -0.9469301294951057, -0.9238795325112867, -0.8968727415326883, -0.8660254037844386, -0.8314696123025452, -0.7933533402912352, -0.7518398074789774, -0.7071067811865476, -0.6593458151000688, -0.6087614290087207, -0.5555702330196022, -0.5, -0.4422886902190013, -0.3826834323650898, -0.3214394653031616, -0.25881904510252074, -0.19509032201612828, -0.1305261922200516, -0.06540312923014306, 0.0, 0.06540312923014306, 0.1305261922200516, 0.19509032201612828, 0.25881904510252074, 0.3214394653031616, 0.3826834323650898, 0.4422886902190013, 0.5, 0.5555702330196022, 0.6087614290087207, 0.6593458151000688, 0.7071067811865476, 0.7518398074789774, 0.7933533402912352, 0.8314696123025452, 0.8660254037844386, 0.8968727415326883, 0.9238795325112867, 0.9469301294951057, 0.9659258262890683, 0.9807852804032304, 0.9914448613738104, 0.9978589232386035};
+constexpr double kSin96[96] = {0.0, 0.06540312923014306, 0.1305261922200516, 0.19509032201612828, 0.25881904510252074, 0.3214394653031616, 0.3826834323650898, 0.4422886902190013, 0.5, 0.5555702330196022, 0.6087614290087207, 0.6593458151000688, 0.7071067811865476, 0.7518398074789774, 0.7933533402912352, 0.8314696123025452, 0.8660254037844386, 0.8968727415326883, 0.9238795325112867, 0.9469301294951057, 0.9659258262890683, 0.9807852804032304, 0.9914448613738104, 0.9978589232386035, 1.0, 0.9978589232386035, 0.9914448613738104, 0.9807852804032304, 0.9659258262890683, 0.9469301294951057, 0.9238795325112867, 0.8968727415326883, 0.8660254037844386, 0.8314696123025452, 0.7933533402912352, 0.7518398074789774, 0.7071067811865476, 0.6593458151000688, 0.6087614290087207, 0.5555702330196022, 0.5, 0.4422886902190013, 0.3826834323650898, 0.3214394653031616, 0.25881904510252074, 0.19509032201612828, 0.1305261922200516, 0.06540312923014306, 0.0, -0.06540312923014306, -0.1305261922200516, -0.19509032201612828, -0.25881904510252074, -0.3214394653031616, -0.3826834323650898, -0.4422886902190013, -0.5, -0.5555702330196022, -0.6087614290087207, -0.6593458151000688, -0.7071067811865476, -0.7518398074789774, -0.7933533402912352, -0.8314696123025452, -0.8660254037844386, -0.8968727415326883, -0.9238795325112867, -0.9469301294951057, -0.9659258262890683, -0.9807852804032304, -0.9914448613738104, -0.9978589232386035, -1.0, -0.9978589232386035, -0.9914448613738104, -0.9807852804032304, -0.9659258262890683, -0.9469301294951057, -0.9238795325112867, -0.8968727415326883, -0.8660254037844386, -0.8314696123025452, -0.7933533402912352, -0.7518398074789774, -0.7071067811865476, -0.6593458151000688, -0.6087614290087207, -0.5555702330196022, -0.5, -0.4422886902190013, -0.3826834323650898, -0.3214394653031616, -0.25881904510252074, -0.19509032201612828, -0.1305261922200516, -0.06540312923014306};
 
 // Multiply by W_R^j = e^{-+ 2 pi i j / R} with j a compile-time constant
 // (after unrolling); the quarter turns are exact.
@@ -77,9 +77,10 @@ __device__ __forceinline__ C twiddle_const(C a, int j) {
   if (4 * j == R) return INV ? mul_pi(a) : mul_mi(a);
   if (2 * j == R) return mk<C>(-a.x, -a.y);
   if (4 * j == 3 * R) return INV ? mul_mi(a) : mul_pi(a);
-  const int k = j * (48 / R);
-  const T c = (T)kCos48[k];
-  const T s = INV ? (T)kSin48[k] : -(T)kSin48[k];
+  static_assert(96 % R == 0, "constant twiddles for radices dividing 96");
+  const int k = j * (96 / R);
+  const T c = (T)kCos96[k];
+  const T s = INV ? (T)kSin96[k] : -(T)kSin96[k];
   return cmul(a, mk<C>(c, s));
 }
 

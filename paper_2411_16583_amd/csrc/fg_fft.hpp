@@ -116,6 +116,7 @@ FG_LINE_SHAPE(64, 8, 8)
 FG_LINE_SHAPE(96, 12, 8)
 FG_LINE_SHAPE(128, 16, 8)
 FG_LINE_SHAPE(256, 16, 16)
+FG_LINE_SHAPE(512, 32, 16)
 #undef FG_LINE_SHAPE
 
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }

@@ -28,6 +28,9 @@ template <> struct Line3Shape<128> {
 template <> struct Line3Shape<96> {
   static constexpr int R1 = 4, R2 = 4, R3 = 6, T = 8;
 };
+template <> struct Line3Shape<512> {
+  static constexpr int R1 = 8, R2 = 8, R3 = 8, T = 64;
+};
 
 // CPT adjacent columns of one LDS row position in one access (two
 // single-precision complex values: one 16-byte access, the same bank pattern
@@ -344,6 +347,9 @@ template <> struct ZLineSel<128> {
 };
 template <> struct ZLineSel<96> {
   using type = Line3<96>;
+};
+template <> struct ZLineSel<512> {
+  using type = Line3<512>;
 };
 template <int L> using ZLine = typename ZLineSel<L>::type;
 

@@ -12,6 +12,8 @@ namespace fg {
 
 #define FG_FOR_M(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
 #define FG_FOR_AXIS(X) X(1) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
+// N1 passes also take 512-long lines (plane grids of 512 x 512)
+#define FG_FOR_N1(X) FG_FOR_AXIS(X) X(512)
 
 template <typename R>
 void launch_r2c(int M, const R* in, R* out, long nlines, const SpecTables<R>& tb, const Skip& skip,
@@ -81,7 +83,7 @@ void launch_axis(int L, bool inv, R* data, long estride, long ystride, long zstr
                   zstride, B, tw, skip);                                                               \
     }                                                                                                  \
     return;
-    FG_FOR_AXIS(FG_CASE)
+    FG_FOR_N1(FG_CASE)
 #undef FG_CASE
   }
   throw std::invalid_argument("unsupported axis length");
@@ -118,7 +120,7 @@ void launch_axis_rows(int N1, R* data, int N0, int M, const SpecTables<R>& tb, c
       launch_ev((k_fft_axis_rows<R, L_, 1>), grid, dim3(T * B), shm, s, ev0, ev1, data, (long)M, plane,  \
                          3L * N0 * plane, (long)N0 * plane, B, tb, sk, pap_partials, nparts, ks, dcb); \
     return;
-    FG_FOR_AXIS(FG_CASE)
+    FG_FOR_N1(FG_CASE)
 #undef FG_CASE
   }
   throw std::invalid_argument("unsupported axis length");

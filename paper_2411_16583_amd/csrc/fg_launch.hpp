@@ -23,6 +23,7 @@ inline void launch_ev(F kernel, dim3 grid, dim3 block, unsigned shm, hipStream_t
 bool fft_length_supported(int L);       // complex line lengths
 bool fft_axis_length_supported(int L);  // N1 (and N0 > 1)
 bool fft_n0_length_supported(int L);    // N0: the axis lengths and 1 (a plane)
+bool fft_n1_length_supported(int L);    // N1: the axis lengths and 512
 
 // Largest power-of-two column tile dividing M with T * B <= 256 threads and
 // an exchange buffer of L * B complex values within 64 KiB.

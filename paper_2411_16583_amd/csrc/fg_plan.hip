@@ -38,6 +38,8 @@ bool fft_axis_length_supported(int L) { return L >= 4 && fft_length_supported(L)
 // N0 may also be 1: a single plane (2-D problem), where the N0 transform is
 // the identity and every difference along axis 0 vanishes
 bool fft_n0_length_supported(int L) { return L == 1 || fft_axis_length_supported(L); }
+// N1 may also be 512 (the N1 passes have 512-long lines; N0 stays <= 256)
+bool fft_n1_length_supported(int L) { return L == 512 || fft_axis_length_supported(L); }
 
 int line_threads(int L) {
   switch (L) {
@@ -49,6 +51,7 @@ int line_threads(int L) {
     case 96: return Line<96>::T;
     case 128: return Line<128>::T;
     case 256: return Line<256>::T;
+    case 512: return Line<512>::T;
     default: return 1;
   }
 }
@@ -85,6 +88,7 @@ int zline_threads(int L) {
   if (L == 256) return Line3<256>::T;
   if (L == 128) return Line3<128>::T;
   if (L == 96) return Line3<96>::T;
+  if (L == 512) return Line3<512>::T;
   return line_threads(L);
 }
 
@@ -1132,7 +1136,7 @@ fg_status plan_new(const int grid[3], const double spacing[3], fg_precision prec
   if (nitems < 1) return FG_E_ARG;
   for (int k = 0; k < 3; ++k)
     if (!(spacing[k] > 0.0) || !std::isfinite(spacing[k])) return FG_E_ARG;
-  if (!fg::fft_n0_length_supported(grid[0]) || !fg::fft_axis_length_supported(grid[1])) return FG_E_SIZE;
+  if (!fg::fft_n0_length_supported(grid[0]) || !fg::fft_n1_length_supported(grid[1])) return FG_E_SIZE;
   if (grid[2] % 2 != 0 || !fg::fft_length_supported(grid[2] / 2) || grid[2] < 4) return FG_E_SIZE;
   fg_plan* P = new (std::nothrow) fg_plan();
   if (!P) return FG_E_HIP;
@@ -2317,7 +2321,7 @@ fg_status fg_project_noalloc(const int grid[3], const double spacing[3], const d
   if (!grid || !spacing || !x || !y) return FG_E_ARG;
   for (int k = 0; k < 3; ++k)
     if (!(spacing[k] > 0.0) || !std::isfinite(spacing[k])) return FG_E_ARG;
-  if (!fg::fft_n0_length_supported(grid[0]) || !fg::fft_axis_length_supported(grid[1])) return FG_E_SIZE;
+  if (!fg::fft_n0_length_supported(grid[0]) || !fg::fft_n1_length_supported(grid[1])) return FG_E_SIZE;
   if (grid[2] % 2 != 0 || grid[2] < 4 || !fg::fft_length_supported(grid[2] / 2)) return FG_E_SIZE;
   const long N = (long)grid[0] * grid[1] * grid[2];
   if ((size_t)N * 9 * sizeof(double) > kScratchWorkBytes) return FG_E_SIZE;

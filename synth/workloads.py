@@ -49,6 +49,8 @@ __all__ = [
     "plane_inclusion_workload",
     "in_plane_schedule",
     "plate_workload",
+    "gumbel_field",
+    "plane_particle_workload",
 ]
 
 GAS_R = 8.314462618  # J / (mol K)
@@ -239,6 +241,70 @@ def plate_workload(n=64, corner=0, plate=40, corner_len=20, n_steps=60, dt=1.0, 
         dt=dt, n_steps=n_steps, loads=[np.eye(3)] * n_steps, jacobian="full",
         tol_newton=1e-8, tol_lin=1e-6, tol_chem=1e-8,
         corner_site=site,
+    )
+
+
+def gumbel_field(shape, mean_value, m, rng):
+    """Per-voxel property of eq. (Gumbell): value_i = mean_value *
+    log(1 / (1 - omega_i))^(1/m), omega_i uniform in (0, 1), one draw per voxel.
+    (log(1/(1 - omega)) is a unit exponential, so value / mean_value follows
+    a Weibull law of shape m and unit scale, mean Gamma(1 + 1/m).)"""
+    omega = rng.random(shape)
+    return mean_value * np.log(1.0 / (1.0 - omega)) ** (1.0 / m)
+
+
+def plane_particle_workload(n=512, n_steps=400, dt=2.0, q_in=8e-4, sigma_max=160e6, m=3.0, delta_l=None,
+                            void=1e-2, law="svk", seed_offset=51):
+    """The 2-D circular particle of Sec. 5.1 (Table of Sec. 5.1): a plane grid
+    (1, n, n) of side 16 um with a centred disc of diameter 12.8 um, Young's
+    modulus and threshold stress drawn per voxel from eq. (Gumbell) (m = 3)
+    around E_mat = 15 GPa and sigma_max, nu = 0.3, Omega = 1.3,
+    D = 1e-9 mm^2/s, a void with E and D scaled by `void` (table: 1e-5) and no
+    swelling, and an inward source q_in on the particle's band of delta_l
+    voxels (6 at n = 512, scaled with n).
+
+    Readings: the text gives sigma_max = 100 MPa and l_c = 1.25e-4 mm, the
+    table 160 MPa and 2.325e-4 mm; the table's sigma_max and the text's l_c
+    (4 voxels at n = 512; at least 2 voxels in the coarser twins) are taken.  The source q_in is a
+    rate per second in normalised concentration on the band (the printed
+    8e-5 mol/mm^3/s does not fit c in (0, 1)); q_in = 8e-4 / s with
+    dt = 2 s starts damage after about 20 steps in the 64 x 64 twin;
+    c_0 = 1e-2; g_c = 2 l_c (g_c only scales H, which cancels in the
+    phase-field equation).  The void's stiffness and diffusivity are scaled
+    by void = 1e-2 (table: 1e-5): at 1e-5 and 1e-3 the swollen, compressed
+    band on the softer void makes the first Newton system indefinite (the CG
+    breaks down, p.Kp < 0, in the 64 x 64 twin), as for the plate of
+    Sec. 4.3.  Chemistry with the full Jacobian, CG tolerance 1e-6.  Seeded
+    from the workload's own offset; at n < 512 the same recipe at lower
+    resolution (a twin, not a crop).
+    """
+    shape = (1, int(n), int(n))
+    h = 16e-6 / n
+    spacing = (h, h, h)
+    if delta_l is None:
+        delta_l = max(1, int(round(6 * n / 512)))
+    centre = (n - 1) / 2.0
+    i1, i2 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    r = np.hypot(i1 - centre, i2 - centre)
+    radius = 0.5 * 0.8 * n
+    part = r <= radius
+    band = part & (r > radius - delta_l)
+    rng = rng_for(seed_offset)
+    Eg = gumbel_field((n, n), 15e9, m, rng)
+    Sg = gumbel_field((n, n), sigma_max, m, rng)
+    part3, band3 = part[None], band[None]
+    E = np.where(part3, Eg[None], void * 15e9)
+    smax = np.where(part3, Sg[None], sigma_max)
+    Dp = 1e-15
+    D = np.where(part3, Dp, void * Dp)
+    lc = max(1.25e-7, 2.0 * h)  # the text's 1.25e-4 mm (4 voxels at n = 512), at least 2 voxels
+    return Workload(
+        name="plane_particle", shape=shape, spacing=spacing, phase=part3, band=band3, law=law,
+        E=E, nu=np.full(shape, 0.3), Omega=np.where(part3, 1.3, 0.0), D=D, sigma_max=smax,
+        gc=2.0 * lc, lc=lc, RT=GAS_R * 298.15, c_max=3.0e4,
+        c0=np.full(shape, 1e-2), d0=np.zeros(shape), cdot_B=np.where(band3, q_in, 0.0),
+        dt=dt, n_steps=n_steps, loads=[np.eye(3)] * n_steps, jacobian="full",
+        tol_newton=1e-8, tol_lin=1e-6, tol_chem=1e-8,
     )
 
 

@@ -19,8 +19,8 @@ pytestmark = pytest.mark.gpu
 
 GRIDS = [(4, 4, 4), (8, 8, 8), (16, 16, 16), (12, 24, 48), (6, 8, 12), (32, 48, 64), (96, 16, 24),
          (64, 64, 128), (256, 4, 8), (4, 256, 16), (8, 4, 512),
-         # plane (2-D) grids: one voxel along N0
-         (1, 4, 8), (1, 16, 32), (1, 48, 96), (1, 64, 64), (1, 256, 512)]
+         # plane (2-D) grids: one voxel along N0; N1 = 512
+         (1, 4, 8), (1, 16, 32), (1, 48, 96), (1, 64, 64), (1, 256, 512), (1, 512, 512), (1, 512, 64), (4, 512, 16)]
 
 
 def unpack_packed(Z, shape):
@@ -102,7 +102,7 @@ def _random_state(work, rng, amp=0.05):
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 8), (12, 16, 24), (32, 32, 32), (256, 4, 8), (4, 256, 16), (8, 4, 512),
-                                   (1, 32, 48), (1, 256, 512)])
+                                   (1, 32, 48), (1, 256, 512), (1, 512, 512), (4, 512, 16)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
 def test_operator_matches_oracle(shape, precision, tol):
     """One application of the operator of eq. (30) against the oracle, also on

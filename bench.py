@@ -82,6 +82,10 @@ def parse():
                     help="--coupled: chemistry once per step (the paper) or inside the staggered loop")
     ap.add_argument("--jacobian", choices=["mu_c", "full"], default="mu_c",
                     help="--coupled: Fick Newton linearisation of the paper (mu_c) or fully implicit")
+    ap.add_argument("--plane-particle", action="store_true",
+                    help="the 2-D particle of Sec. 5.1 (512 x 512 plane grid, eq. (Gumbell) fields, SVK law): "
+                         "staggered time steps until the damage has spread, a record line (not the headline)")
+    ap.add_argument("--pp-n", type=int, default=512, help="grid side of --plane-particle")
     ap.add_argument("--batch-items", type=int, default=48)
     ap.add_argument("--graph-ticks", type=int, default=16)
     ap.add_argument("--newton-every", type=int, default=4,
@@ -545,6 +549,9 @@ def main():
     if args.coupled:
         run_coupled(args)
         return
+    if args.plane_particle:
+        run_plane_particle(args)
+        return
     t0 = time.perf_counter()
     work = synth.polydisperse_workload(n=args.n)
     N = int(np.prod(work["shape"]))
@@ -565,6 +572,100 @@ def main():
         run_ramp(args, work, forms, N)
     else:
         run_cg(args, work, forms, N)
+
+
+def run_plane_particle(args):
+    """--plane-particle: the 2-D particle of Sec. 5.1 at full size (512 x 512
+    plane grid, Young's modulus and threshold stress from eq. (Gumbell),
+    SVK law, Omega = 1.3, source on the 6-voxel band), FP64, staggered time
+    steps (Alg. 4, full chemistry Jacobian, CG tolerance 1e-6, staggered loop
+    capped at 100 iterations) until 2 % of the particle has d > 0.9 or
+    --steps steps (default 400).  Prints a record line: the step where the
+    damage first reaches 0.05 and its radius, and at the end the damaged
+    voxels' radii (the paper: damage starts at random points, more likely
+    near the particle centre, and spreads to fracture)."""
+    import torch
+
+    import synth
+    from paper_2411_16583_amd import Plan
+    from paper_2411_16583_amd.driver import staggered_step
+
+    n_steps = args.steps or 400
+    w = synth.plane_particle_workload(args.pp_n)
+    shape = w["shape"]
+    n = shape[1]
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    plan = Plan(shape, w["spacing"], "fp64", law=w["law"])
+    mats = [t(w[k]) for k in ("E", "nu", "Omega", "D", "sigma_max")]
+    plan.set_material(*mats, gc=w["gc"], lc=w["lc"], RT=w["RT"], c_max=w["c_max"])
+    F = torch.zeros((9,) + shape, dtype=torch.float64, device=dev)
+    F[0] = F[4] = F[8] = 1.0
+    c, d, H = t(w["c0"]), t(w["d0"]), torch.zeros(shape, dtype=torch.float64, device=dev)
+    plan.set_state(F, c, d, H)
+    cdot = t(w["cdot_B"])
+    phase = torch.as_tensor(w["phase"], device=dev)
+    n_part = int(phase.sum().item())
+    ctr = (n - 1) / 2.0
+    radius = 0.4 * n
+    from paper_2411_16583_amd import FgError
+
+    steps, nucleation, stop = [], None, None
+    t0 = time.perf_counter()
+    for k in range(n_steps):
+        ts = time.perf_counter()
+        try:
+            st = staggered_step(plan, np.eye(3), dt=w["dt"], cdot_B=cdot, tol_lin=w["tol_lin"],
+                                jacobian=w["jacobian"], max_stag=100, raise_on_noconv=False)
+        except FgError as e:  # e.g. the CG's breakdown once cracked voxels make the operator singular
+            stop = f"step {k + 1}: {e}"
+            print(f"stopped at {stop}", flush=True)
+            break
+        torch.cuda.synchronize()
+        dmax = float(d.max().item())
+        cg = sum(sum(x["lin_history"]) for x in st["newton"])
+        steps.append(dict(stag=st["stag_iters"], converged=st["converged"], cg=cg, d_max=dmax,
+                          ms=1e3 * (time.perf_counter() - ts)))
+        if nucleation is None and dmax >= 0.05:
+            at = np.unravel_index(int(torch.argmax(d).item()), shape)
+            nucleation = dict(step=k + 1, r_over_R=float(np.hypot(at[1] - ctr, at[2] - ctr) / radius))
+        broken = int(((d > 0.9) & phase).sum().item())
+        if k % 20 == 19 or broken >= 0.02 * n_part:
+            print(f"step {k + 1}: stag {st['stag_iters']} cg {cg} d max {dmax:.3f} broken {broken} "
+                  f"({time.perf_counter() - t0:.1f} s)", flush=True)
+        if broken >= 0.02 * n_part:
+            break
+    elapsed = time.perf_counter() - t0
+    dh = d.cpu().numpy()[0]
+    i1, i2 = np.nonzero((dh > 0.5) & w["phase"][0])
+    rr = np.hypot(i1 - ctr, i2 - ctr) / radius
+    line = {
+        "metric": "plane particle of Sec. 5.1: staggered steps to fracture (record, not the headline)",
+        "value": len(steps) / elapsed,  # steps completed
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": len(steps),
+        "warmup": 0,
+        "ms_per_step": 1e3 * elapsed / len(steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"plane particle {n} x {n} (disc 0.8 L, eq. (Gumbell) E and sigma_max, m = 3, "
+                               f"SVK, Omega = 1.3, source on the {max(1, round(6 * n / 512))}-voxel band, "
+                               f"dt = {w['dt']} s)", "voxels": n * n},
+        "nucleation": nucleation,
+        "stopped": stop,
+        "damaged_d_gt_0.5": dict(voxels=int(rr.size), fraction_of_particle=float(rr.size / n_part),
+                                 r_over_R_quartiles=[float(q) for q in np.quantile(rr, [0.25, 0.5, 0.75])]
+                                 if rr.size else None,
+                                 inner_half_radius_fraction=float(np.mean(rr < 0.5)) if rr.size else None),
+        "stag_iters_total": int(sum(s["stag"] for s in steps)),
+        "steps_not_converged": int(sum(not s["converged"] for s in steps)),
+        "cg_iters_total": int(sum(s["cg"] for s in steps)),
+    }
+    print(json.dumps(line), flush=True)
 
 
 def field_error(Fa, Fb, Fbar):

@@ -115,8 +115,13 @@ def test_fick_step_matches_oracle():
 
 def test_staggered_particle_twin_matches_oracle():
     """Two staggered steps of the 16^3 twin of the particle workload (flux,
-    swelling, buffer, damage) through the C ABI vs the oracle's Alg. 4."""
-    w = synth.particle_workload(n=16, n_steps=2, dt=20.0, q_in=4e-10, sigma_max=0.8e6)
+    swelling, buffer, damage) through the C ABI vs the oracle's Alg. 4.
+    Threshold 1.4 MPa: no damage in the first step, 15 staggered iterations
+    and max d 0.08 in the second; at 0.8 MPa the second step cracks the
+    particle through (d 0.99 after about 60 iterations), an unstable regime
+    whose iteration count moves with rounding (64 on the GPU, 61 in the
+    oracle)."""
+    w = synth.particle_workload(n=16, n_steps=2, dt=20.0, q_in=4e-10, sigma_max=1.4e6)
     shape = w["shape"]
     plan = plan_for(w)
     F0 = mechanics.uniform_field(np.eye(3), shape)

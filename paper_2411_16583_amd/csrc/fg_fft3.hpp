@@ -352,6 +352,14 @@ template <> struct ZLineSel<512> {
   using type = Line3<512>;
 };
 template <int L> using ZLine = typename ZLineSel<L>::type;
+// Line of the potential-form N0 pass: ZLine, except the two-stage 16 x 16
+// line in single precision at L = 256 (one column per thread there).
+template <typename R, int L> struct ZGradSel {
+  using type = ZLine<L>;
+};
+template <> struct ZGradSel<float, 256> {
+  using type = Line2Ops<256>;
+};
 
 template <typename R, int L>
 __global__ void __launch_bounds__(256)
@@ -603,7 +611,7 @@ __global__ void __launch_bounds__(256)
 k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor) {
   static_assert(CPT == 1 || (CPT == 2 && sizeof(R) == 4), "column pairs in single precision");
   using C = cplx<R>;
-  using LS = ZLine<L>;
+  using LS = typename ZGradSel<R, L>::type;
   extern __shared__ __align__(16) char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C* stw = lds + L * B;

@@ -156,13 +156,15 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
 template <typename R>
 void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R scale, const Skip& skip,
                   hipStream_t s, int nitems, int tile, const R* dcb, hipEvent_t ev0, hipEvent_t ev1) {
-  const int T = zline_threads(N0);
+  const int T = zgrad_threads(N0, (int)sizeof(cplx<R>));
   const int kymajor = (tile == 0 || (tile & kTileKyMajor)) ? 1 : 0;
   tile &= ~kTileKyMajor;
-  // single precision: two adjacent columns per thread
+  // single precision: two adjacent columns per thread (one at N0 = 256)
   constexpr int CPT = (sizeof(R) == 4) ? 2 : 1;
-  const int B = tile > 0 ? tile : zgrad_tile(N0, M, (int)sizeof(cplx<R>));
-  const int cpt = (B % CPT == 0) ? CPT : 1;
+  int B = tile > 0 ? tile : zgrad_tile(N0, M, (int)sizeof(cplx<R>));
+  auto cpt_of = [&](int b) { return (b % 2 == 0) ? zgrad_cpt(N0, (int)sizeof(cplx<R>)) : 1; };
+  while (B > 1 && T * B / cpt_of(B) > 256) B /= 2;  // a tile chosen for another line shape
+  const int cpt = cpt_of(B);
   const size_t shm = (size_t)N0 * B * sizeof(cplx<R>) + zgrad_extra_lds<R>(N0);
   dim3 grid = kymajor ? dim3((unsigned)N1, (unsigned)(M / B), (unsigned)(3 * nitems))
                       : dim3((unsigned)(M / B), (unsigned)N1, (unsigned)(3 * nitems));

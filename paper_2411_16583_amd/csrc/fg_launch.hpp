@@ -33,6 +33,10 @@ int column_tile_t(int T, int L, int M, int elem_bytes);
 int column_tile_cpt(int L, int M, int elem_bytes, int cpt);
 int line_threads(int L);
 int zline_threads(int L);  // threads per line of the fused N0 projection pass
+// threads per line and columns per thread of the potential-form N0 pass
+// (elem_bytes: bytes of one complex value of the working precision)
+int zgrad_threads(int L, int elem_bytes);
+int zgrad_cpt(int L, int elem_bytes);
 int zgrad_tile(int L, int M, int elem_bytes);  // built-in tile of launch_zgrad
 
 // Fused CG front on the potentials (deferred xi update, direction update,

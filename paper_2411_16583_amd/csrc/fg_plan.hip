@@ -76,13 +76,21 @@ int column_tile_cpt(int L, int M, int elem_bytes, int cpt) {
 // dividing M whose workgroup (two columns per thread in single precision)
 // and LDS fit.
 int zgrad_tile(int L, int M, int elem_bytes) {
-  const int T = zline_threads(L);
-  const int cpt = (elem_bytes == 8) ? 2 : 1;
+  const int T = zgrad_threads(L, elem_bytes);
+  const int cpt = zgrad_cpt(L, elem_bytes);
   int B = 1;
   while (M % (2 * B) == 0 && T * 2 * B / cpt <= 256 && (long)L * 2 * B * elem_bytes + 5L * L * elem_bytes / 2 <= 65536)
     B *= 2;
   return B;
 }
+
+// The potential-form N0 pass in single precision at L = 256 uses the
+// two-stage 16 x 16 line with one column per thread (one LDS exchange per
+// transform instead of two; 140 -> 131 us at 256^3 with its kx = 0 kernel);
+// elsewhere the line of zline_threads, two columns per thread in single
+// precision.
+int zgrad_threads(int L, int elem_bytes) { return (elem_bytes == 8 && L == 256) ? Line<256>::T : zline_threads(L); }
+int zgrad_cpt(int L, int elem_bytes) { return (elem_bytes == 8 && L != 256) ? 2 : 1; }
 
 int zline_threads(int L) {
   if (L == 256) return Line3<256>::T;
@@ -103,11 +111,12 @@ bool tile_valid(bool zproj, int L, int M, int elem_bytes, int tile) {
     pairs = true;
   }
   if (tile < 1 || (tile & (tile - 1)) != 0 || M % tile != 0) return false;
-  const int T = zproj ? zline_threads(L) : line_threads(L);
+  const int T = zproj ? zgrad_threads(L, elem_bytes) : line_threads(L);
   // single-precision N1 pass with column pairs: tile / 2 column groups
   if (pairs && tile % 2 != 0) return false;
   // the single-precision N0 pass takes two columns per thread (even tiles)
-  const int cpt = (pairs || (zproj && elem_bytes == 8 && tile % 2 == 0)) ? 2 : 1;
+  // except at L = 256 (zgrad_cpt)
+  const int cpt = pairs ? 2 : ((zproj && tile % 2 == 0) ? zgrad_cpt(L, elem_bytes) : 1);
   if (T * tile / cpt > 256) return false;
   // exchange buffer, plus the twiddles and kz tables of the projection pass
   // (the potential form of the projection stages one more kz table)
@@ -2210,7 +2219,7 @@ fg_status fg_plan_get_tiles(const fg_plan* P, int tiles[4]) {
   for (int w = 0; w < 4; ++w) {
     const TilePass tp = tile_pass(w);
     const int L = tile_len(P, w);
-    const int T = tp.zproj ? fg::zline_threads(L) : fg::line_threads(L);
+    const int T = tp.zproj ? fg::zgrad_threads(L, tp.elem) : fg::line_threads(L);
     const int built_in = tp.zproj ? (fg::zgrad_tile(L, P->M, tp.elem) | fg::kTileKyMajor)
                                   : fg::column_tile_t(T, L, P->M, tp.elem);
     tiles[w] = P->tiles[w] > 0 ? P->tiles[w] : built_in;

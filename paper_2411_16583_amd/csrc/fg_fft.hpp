@@ -563,8 +563,9 @@ __device__ __forceinline__ void z_dc_body(R* data, int N1, int M, const SpecTabl
   const int grp = threadIdx.x / 64;
   const int col = threadIdx.x % 2;
   const int t = (threadIdx.x % 64) / 2;
-  // idle lanes (t >= T) still take part in every barrier below
-  const bool lane_ok = t < LS::T;
+  // idle lanes (t >= T, and waves beyond the NC components when the body
+  // runs in a larger workgroup) still take part in every barrier below
+  const bool lane_ok = t < LS::T && grp < NC;
   xbuf += grp * 2 * L;
   const int ky1 = (N1 - ky0) % N1;
   const int myky = col ? ky1 : ky0;

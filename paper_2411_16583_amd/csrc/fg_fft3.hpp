@@ -605,10 +605,14 @@ template <typename R> constexpr size_t zgrad_extra_lds(int L) {
 // sy cx A_i1 + cy sx A_i2, so that sum_l A_il r_l = sz X_0 + cz X_1 after the
 // N0 transforms X_0, X_1 of the two slots (two forward transforms and one
 // inverse per row).  Grid (M/B, N1, 3 rows per item), or (N1, M/B, rows) with
-// kymajor.  The kx = 0 column is left to k_fft_z_dc<OP = 2>.
-template <typename R, int L, int CPT>
+// kymajor.  The kx = 0 column is left to k_fft_z_dc<OP = 2>, or with DC to a
+// leading slice z = 0 of this launch that runs the same body (dc_lead pairs);
+// the rows then start at z = 1.  The rows' workgroups read the kx = 0 column
+// too but never use or store what they compute for it.
+template <typename R, int L, int CPT, bool DC = false>
 __global__ void __launch_bounds__(256)
-k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor) {
+k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor, int dc_lead = 0,
+              const R* dcb = nullptr) {
   static_assert(CPT == 1 || (CPT == 2 && sizeof(R) == 4), "column pairs in single precision");
   using C = cplx<R>;
   using LS = typename ZGradSel<R, L>::type;
@@ -618,7 +622,22 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   R* scz = reinterpret_cast<R*>(stw + L);
   R* ssz = scz + L;
   R* snz = ssz + L;
-  if (skip(blockIdx.z)) return;
+  if constexpr (DC) {
+    // leading slice: the kx = 0 column pairs (the body of k_fft_z_dc<OP = 2>,
+    // one pair per workgroup), so that they start first and overlap the rest
+    if (blockIdx.z == 0) {
+      const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+      if (b < dc_lead) {
+        const int ky0 = b % (N1 / 2 + 1), row = b / (N1 / 2 + 1);
+        if (!skip(row))
+          z_dc_body<R, L, 2>(data, N1, M, tb, scale, 0.0, 0.0, ky0, row, lds, lds + z_dc_groups<2>() * 2 * L,
+                             reinterpret_cast<const C*>(dcb));
+      }
+      return;
+    }
+  }
+  const int i = (int)blockIdx.z - (DC ? 1 : 0);  // row of the 3x3 field, items consecutive
+  if (skip(i)) return;
   for (int k = threadIdx.x; k < L; k += blockDim.x) {
     stw[k] = tb.tw0[k];
     scz[k] = tb.cz[k];
@@ -633,7 +652,6 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   const int t = threadIdx.x / BC;
   const int kx0 = (kymajor ? blockIdx.y : blockIdx.x) * B + col0;
   const int ky = kymajor ? blockIdx.x : blockIdx.y;
-  const int i = blockIdx.z;  // row of the 3x3 field, items consecutive
   const long plane = (long)N1 * M;
   const long comp = (long)L * plane;
   // workgroup-uniform base of the row's first slot and a 32-bit element

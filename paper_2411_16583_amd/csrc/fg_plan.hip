@@ -86,7 +86,8 @@ int zgrad_tile(int L, int M, int elem_bytes) {
 
 // The potential-form N0 pass in single precision at L = 256 uses the
 // two-stage 16 x 16 line with one column per thread (one LDS exchange per
-// transform instead of two; 140 -> 131 us at 256^3 with its kx = 0 kernel);
+// transform instead of two; the pass with its kx = 0 kernel 162 -> 154 us at
+// 256^3);
 // elsewhere the line of zline_threads, two columns per thread in single
 // precision.
 int zgrad_threads(int L, int elem_bytes) { return (elem_bytes == 8 && L == 256) ? Line<256>::T : zline_threads(L); }

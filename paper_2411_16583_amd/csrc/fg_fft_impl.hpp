@@ -2,6 +2,7 @@
 // fg_fft_f32.hip, one working precision each).
 #pragma once
 #include <hip/hip_ext.h>
+#include <algorithm>
 #include <stdexcept>
 
 #include "fg_cgfront.hpp"
@@ -154,16 +155,16 @@ void launch_zproj(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
 }
 
 // The potential-form N0 pass with the kx = 0 pairs as its leading slice
-// (single precision at N0 = 256 only; see launch_zgrad).
+// (N0 = 256 only; see launch_zgrad).
 template <typename R, int L>
 void launch_zgrad_fused(dim3 grid, dim3 block, size_t shm, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, R* data,
                         int N1, int M, int B, const SpecTables<R>& tb, R scale, const Skip& sk, int kymajor,
                         int dc_lead, const R* dcb) {
-  if constexpr (sizeof(R) == 4 && L == 256) {
+  if constexpr (L == 256) {
     launch_ev((k_fft_z_grad3<R, L, 1, true>), grid, block, shm, s, ev0, ev1, data, N1, M, B, tb, scale, sk, kymajor,
               dc_lead, dcb);
   } else {
-    throw std::logic_error("the fused kx = 0 slice is built for single precision at N0 = 256 only");
+    throw std::logic_error("the fused kx = 0 slice is built for N0 = 256 only");
   }
 }
 
@@ -184,19 +185,21 @@ void launch_zgrad(int N0, R* data, int N1, int M, const SpecTables<R>& tb, R sca
                       : dim3((unsigned)(M / B), (unsigned)N1, (unsigned)(3 * nitems));
   dim3 gdc((unsigned)(N1 / 2 + 1), (unsigned)(3 * nitems), 1);
   const Skip sk = skip.unit(3);  // grid.z (grad) and grid.y (kx = 0): 3 rows per item
-  // single precision at N0 = 256 (one column per thread, 256 threads): the
-  // kx = 0 pairs run as a leading slice of the same launch when they fit in
-  // it, so that they overlap the rest instead of following it (measured at
-  // 256^3: the pass with its kx = 0 work 152 -> 143 us)
+  // N0 = 256 with one column per thread: the kx = 0 pairs run as a leading
+  // slice of the same launch when they fit in it, so that they overlap the
+  // rest instead of following it (measured at 256^3, the pass with its
+  // kx = 0 work: single precision 152 -> 143 us); the workgroups then take
+  // the larger of the two LDS sizes (in double precision 48 KiB: 3 per CU,
+  // as many as the registers allow anyway)
   const int dc_lead = (N1 / 2 + 1) * 3 * nitems;
-  const bool fuse_dc = sizeof(R) == 4 && N0 == 256 && cpt == 1 && T * B >= 64 * z_dc_groups<2>() &&
-                       (long)dc_lead <= (long)grid.x * grid.y &&
-                       (size_t)z_dc_lds<256, 2>() * sizeof(cplx<R>) <= shm;
+  const size_t shm_dc = std::max(shm, (size_t)z_dc_lds<256, 2>() * sizeof(cplx<R>));
+  const bool fuse_dc = N0 == 256 && cpt == 1 && T * B >= 64 * z_dc_groups<2>() &&
+                       (long)dc_lead <= (long)grid.x * grid.y && shm_dc <= 65536;
   switch (N0) {
 #define FG_CASE(L_)                                                                                    \
   case L_:                                                                                             \
     if (fuse_dc) {                                                                                     \
-      launch_zgrad_fused<R, L_>(dim3(grid.x, grid.y, grid.z + 1), dim3(T * B), shm, s, ev0, ev1, data, N1, M, B, \
+      launch_zgrad_fused<R, L_>(dim3(grid.x, grid.y, grid.z + 1), dim3(T * B), shm_dc, s, ev0, ev1, data, N1, M, B, \
                                 tb, scale, sk, kymajor, dc_lead, dcb);                                 \
       return;                                                                                          \
     }                                                                                                  \

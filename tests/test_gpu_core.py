@@ -313,16 +313,18 @@ def test_newton_small_odd_grids_match_oracle(shape, precision, tol):
     assert e <= tol and m <= tol
 
 
-@pytest.mark.parametrize("shape", [(4, 6, 256), (6, 4, 128), (4, 4, 512), (256, 4, 8), (4, 256, 16), (8, 4, 512)])
+@pytest.mark.parametrize("shape", [(4, 6, 256), (6, 4, 128), (4, 4, 512), (256, 4, 8), (4, 256, 16), (8, 4, 512),
+                                   (4, 512, 8), (1, 512, 16)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
 def test_newton_long_lines_match_oracle(shape, precision, tol):
     """Newton-CG on grids whose lines along N2 are one or two waves of
     stencil groups (N2 = 256 in single precision, 128 in double precision:
     the stencil's lower corner is taken from the neighbouring lane; N2 = 512:
-    lines spanning two waves) and on grids with 256-long lines along N0 or N1
+    lines spanning two waves), on grids with 256-long lines along N0 or N1
     (the N0 projection pass and the N1 row pass of length 256, in both
-    precisions), random two-phase material, mixed macro load, against the
-    oracle's discrete solution."""
+    precisions), and with 512-long lines along N1 (3-D and a plane grid),
+    random two-phase material, mixed macro load, against the oracle's
+    discrete solution."""
     work = synth.homogeneous_workload(shape)
     rng = np.random.default_rng(71207 + shape[2])
     phase = rng.random(shape) < 0.3

@@ -90,6 +90,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   constexpr int LB = FS::LB;
   __shared__ C buf[9 * LB * FS::LSTRIDE];
   __shared__ double red[16];
+  __shared__ C stw[M], spost[M];
   const long nlines = (long)n0 * n1;
   // batch item of this workgroup (items are nlines lines of 9 components
   // each, item-major; ceil(nlines / LB) workgroups per item)
@@ -103,6 +104,14 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   rbuf += (long)item * 9 * N;
   st += (long)item * state_words(LAW) * N;
   const int tid = threadIdx.x;
+  // the N2 line's stage twiddles and the R2C post-processing factors in LDS,
+  // read once per workgroup (phase A's barrier below orders them); read from
+  // the caches inside phase B they cost the single-precision front 525 -> 488
+  // us at 256^3 (FP64 950 -> 940 us)
+  for (int k = tid; k < M; k += FS::THREADS) {
+    stw[k] = tb.twM[k];
+    spost[k] = tb.post[k];
+  }
   const long line0 = ((long)blockIdx.x - (long)item * bpi) * LB;
   const int iter = ks->iter;
   const bool first = iter == 0;
@@ -220,7 +229,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   // sit in one wave (T divides 64): wave-level ordering suffices
   static_assert(64 % LS::T == 0, "lines within one wave");
   lds_sync<true>();  // every line fully read before the exchange writes into it
-  line_fft_AB<M, false, C, true>(v, my, 1, t, tb.twM);
+  line_fft_AB<M, false, C, true>(v, my, 1, t, stw);
 #pragma unroll
   for (int e = 0; e < LS::E; ++e) my[LS::idxB(t, e)] = v[e];
   lds_sync<true>();
@@ -236,7 +245,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
       const C zm = my[M - k];
       const C ev = cscale(cadd(zk, cconj(zm)), R(0.5));
       const C od = cscale(mul_mi(csub(zk, cconj(zm))), R(0.5));
-      X = cadd(ev, cmul(od, tb.post[k]));
+      X = cadd(ev, cmul(od, spost[k]));
     }
     if (active) st_stream(dst + k, X);
   }

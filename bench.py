@@ -238,8 +238,9 @@ def measured_traffic(kernel, word_bytes):
     sources changed since those counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "front_polydisperse256_fp64_traffic.json")
-    if kernel != "front" or word_bytes != 8 or not os.path.exists(path):
+    form = {8: "fp64", 4: "fp32"}.get(word_bytes)
+    path = os.path.join(ROOT, "profiles", f"front_polydisperse256_{form}_traffic.json")
+    if kernel != "front" or form is None or not os.path.exists(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()

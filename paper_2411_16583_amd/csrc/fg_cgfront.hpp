@@ -72,10 +72,13 @@ template <int M> struct FrontShape {
   // elements apart in the banks instead of one (a pad of one element puts
   // line l + 1's element t on the banks of line l's element t + 1).  In
   // single precision this removed most of the front's LDS bank conflicts
-  // (counted conflict cycles 4.5e7 -> 0.7e7 at 256^3).
+  // (counted conflict cycles 4.5e7 -> 0.7e7 at 256^3).  Double precision
+  // takes a one-element pad: its buffers (with the stage twiddles) then fit
+  // four workgroups per CU instead of three (the front 948 -> 930 us at
+  // 256^3).
   static constexpr bool kBankPad = M % 32 == 0 && (T == 4 || T == 8 || T == 16);
   static constexpr int PADC = kBankPad ? T : ((M >= 16) ? 1 : 0);
-  static constexpr int LSTRIDE = M + PADC;  // complex elements per line buffer
+  template <typename R> static constexpr int lstride() { return sizeof(R) == 8 ? M + 1 : M + PADC; }
 };
 
 template <typename R, int M, int LAW>
@@ -88,9 +91,14 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   using FS = FrontShape<M>;
   constexpr int N2 = 2 * M;
   constexpr int LB = FS::LB;
-  __shared__ C buf[9 * LB * FS::LSTRIDE];
+  constexpr int LSTRIDE = FS::template lstride<R>();  // complex elements per line buffer
+  __shared__ C buf[9 * LB * LSTRIDE];
   __shared__ double red[16];
-  __shared__ C stw[M], spost[M];
+  // the R2C post-processing factors in LDS in single precision only (double
+  // precision reads them from the caches, once per output element, to keep
+  // four workgroups per CU)
+  constexpr bool kPostLds = sizeof(R) == 4;
+  __shared__ C stw[M], spost[kPostLds ? M : 1];
   const long nlines = (long)n0 * n1;
   // batch item of this workgroup (items are nlines lines of 9 components
   // each, item-major; ceil(nlines / LB) workgroups per item)
@@ -104,13 +112,13 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   rbuf += (long)item * 9 * N;
   st += (long)item * state_words(LAW) * N;
   const int tid = threadIdx.x;
-  // the N2 line's stage twiddles and the R2C post-processing factors in LDS,
-  // read once per workgroup (phase A's barrier below orders them); read from
-  // the caches inside phase B they cost the single-precision front 525 -> 488
-  // us at 256^3 (FP64 950 -> 940 us)
+  // the N2 line's stage twiddles (and the R2C post-processing factors) in
+  // LDS, read once per workgroup (phase A's barrier below orders them); read
+  // from the caches inside phase B they cost the single-precision front
+  // 525 -> 488 us at 256^3 (FP64 950 -> 940 us)
   for (int k = tid; k < M; k += FS::THREADS) {
     stw[k] = tb.twM[k];
-    spost[k] = tb.post[k];
+    if constexpr (kPostLds) spost[k] = tb.post[k];
   }
   const long line0 = ((long)blockIdx.x - (long)item * bpi) * LB;
   const int iter = ks->iter;
@@ -210,7 +218,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         acc += (double)X[w][k] * (double)Y0[k] + (double)X[w + 1][k] * (double)Y1[k];
-        buf[(k * LB + l) * FS::LSTRIDE + n * (W / 2) + w / 2] = mk<C>(Y0[k], Y1[k]);
+        buf[(k * LB + l) * LSTRIDE + n * (W / 2) + w / 2] = mk<C>(Y0[k], Y1[k]);
       }
     }
   }
@@ -220,7 +228,7 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   const int t = tid % LS::T;
   const int comp = lt / LB;
   const int l = lt % LB;
-  C* my = buf + lt * FS::LSTRIDE;
+  C* my = buf + lt * LSTRIDE;
   const bool active = (line0 + l) < nlines;
   C v[LS::E];
 #pragma unroll
@@ -234,20 +242,38 @@ k_cg_front(R* __restrict__ spec, R* __restrict__ pbuf, R* __restrict__ xbuf, con
   for (int e = 0; e < LS::E; ++e) my[LS::idxB(t, e)] = v[e];
   lds_sync<true>();
   C* dst = reinterpret_cast<C*>(spec) + ((long)comp * nlines + line0 + l) * M;
-#pragma unroll
-  for (int e = 0; e < LS::E; ++e) {
-    const int k = LS::idxB(t, e);
+  // X_k of the real line from the packed transform z (k = 0 carries both
+  // ends of the spectrum)
+  auto post = [&](int k) {
     const C zk = my[k];
-    C X;
-    if (k == 0) {
-      X = mk<C>(zk.x + zk.y, zk.x - zk.y);
-    } else {
-      const C zm = my[M - k];
-      const C ev = cscale(cadd(zk, cconj(zm)), R(0.5));
-      const C od = cscale(mul_mi(csub(zk, cconj(zm))), R(0.5));
-      X = cadd(ev, cmul(od, spost[k]));
+    if (k == 0) return mk<C>(zk.x + zk.y, zk.x - zk.y);
+    const C zm = my[M - k];
+    const C ev = cscale(cadd(zk, cconj(zm)), R(0.5));
+    const C od = cscale(mul_mi(csub(zk, cconj(zm))), R(0.5));
+    if constexpr (kPostLds)
+      return cadd(ev, cmul(od, spost[k]));
+    else
+      return cadd(ev, cmul(od, tb.post[k]));
+  };
+  if constexpr (sizeof(R) == 4 && M % (2 * LS::T) == 0) {
+    // single precision: two adjacent elements per thread and store, so that
+    // a line's T threads write 16 T contiguous bytes (whole 128-byte lines at
+    // T = 8); the nontemporal half-line stores of one element per thread
+    // counted 15% more written bytes than the spectrum and cost the front
+    // 494 -> 440 us at 256^3
+#pragma unroll
+    for (int j = 0; j < M / (2 * LS::T); ++j) {
+      const int k = 2 * (j * LS::T + t);
+      const C x0 = post(k), x1 = post(k + 1);
+      if (active) st_stream_f4(dst + k, make_float4(x0.x, x0.y, x1.x, x1.y));
     }
-    if (active) st_stream(dst + k, X);
+  } else {
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const int k = LS::idxB(t, e);
+      const C X = post(k);
+      if (active) st_stream(dst + k, X);
+    }
   }
   const double s = block_sum(acc, red);
   if (tid == 0) partials[blockIdx.x] = s;

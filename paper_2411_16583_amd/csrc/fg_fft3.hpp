@@ -504,7 +504,9 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
   auto offA = [&](int e) { return ucol + (unsigned)LS::idxA(t, e) * ues; };
   auto offB = [&](int e) { return ucol + (unsigned)LS::idxB(t, e) * ues; };
   // double precision: streaming loads and stores (measured at 256^3: 426 ->
-  // 418 us; in single precision they made the pass slower, 210 -> 219 us)
+  // 418 us; in single precision they made the pass slower, 210 -> 219 us);
+  // single precision streams its stores only (the pass unchanged, the N0 pass
+  // that reads them 144 -> 140 us)
   auto load = [&](C* b, unsigned off, C (&x)[CPT]) {
     if constexpr (CPT == 2) {
       const float4 w = at_bytes(reinterpret_cast<float4*>(b), off);
@@ -518,7 +520,7 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
   };
   auto store = [&](C* b, unsigned off, const C (&x)[CPT]) {
     if constexpr (CPT == 2)
-      at_bytes(reinterpret_cast<float4*>(b), off) = make_float4(x[0].x, x[0].y, x[CPT - 1].x, x[CPT - 1].y);
+      st_stream_f4(&at_bytes(reinterpret_cast<float4*>(b), off), make_float4(x[0].x, x[0].y, x[CPT - 1].x, x[CPT - 1].y));
     else if constexpr (sizeof(R) == 8)
       st_stream(&at_bytes(b, off), x[0]);
     else

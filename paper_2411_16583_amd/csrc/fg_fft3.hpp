@@ -588,9 +588,9 @@ k_fft_axis_rows(R* data, long estride, long ystride, long zstride, long cstride,
 }
 
 // LDS bytes of k_fft_z_grad3 beyond the L x B exchange buffer: the stage
-// twiddles and three kz tables (cos, scaled sin, sin).
+// twiddles and two kz tables (cos, scaled sin).
 template <typename R> constexpr size_t zgrad_extra_lds(int L) {
-  return (size_t)L * sizeof(cplx<R>) + 3 * (size_t)L * sizeof(R);
+  return (size_t)L * sizeof(cplx<R>) + 2 * (size_t)L * sizeof(R);
 }
 
 // N0 pass fused with the projection, potential form (eq. (28) with the
@@ -604,15 +604,22 @@ template <typename R> constexpr size_t zgrad_extra_lds(int L) {
 // and its gradient is formed in real space by the corner stencil
 // (k_cg_rupd_march, k_grad_store).  The input is the output of
 // k_fft_axis_rows: slot 3i holds cy cx A_i0 and slot 3i + 1 holds
-// sy cx A_i1 + cy sx A_i2, so that sum_l A_il r_l = sz X_0 + cz X_1 after the
-// N0 transforms X_0, X_1 of the two slots (two forward transforms and one
-// inverse per row).  Grid (M/B, N1, 3 rows per item), or (N1, M/B, rows) with
+// sy cx A_i1 + cy sx A_i2, so that sum_l A_il r_l = sz X_0 + cz X_1 with X_0,
+// X_1 the N0 transforms of the two slots x0, x1.  With sz = (2 / h0)
+// sin(qz / 2) and cz = cos(qz / 2), e^{i qz / 2} (sz X_0 + cz X_1) is the
+// transform of the two-point stencil along N0
+//   c[n] = (x1[n] + x1[n + 1]) / 2 - i (x0[n + 1] - x0[n]) / h0,
+// so each row takes one forward transform (of c) and one inverse instead of
+// two and one, and the phase e^{i qz / 2} of U needs no kz factor (measured
+// at 256^3 with the kx = 0 pairs: 272 -> 271 us FP64; 141 -> 132 us FP32,
+// where the freed registers also allow 4 waves per SIMD).  Grid (M/B, N1, 3
+// rows per item), or (N1, M/B, rows) with
 // kymajor.  The kx = 0 column is left to k_fft_z_dc<OP = 2>, or with DC to a
 // leading slice z = 0 of this launch that runs the same body (dc_lead pairs);
 // the rows then start at z = 1.  The rows' workgroups read the kx = 0 column
 // too but never use or store what they compute for it.
 template <typename R, int L, int CPT, bool DC = false>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && CPT == 1) ? 4 : 1)))
 k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor, int dc_lead = 0,
               const R* dcb = nullptr) {
   static_assert(CPT == 1 || (CPT == 2 && sizeof(R) == 4), "column pairs in single precision");
@@ -623,7 +630,6 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   C* stw = lds + L * B;
   R* scz = reinterpret_cast<R*>(stw + L);
   R* ssz = scz + L;
-  R* snz = ssz + L;
   if constexpr (DC) {
     // leading slice: the kx = 0 column pairs (the body of k_fft_z_dc<OP = 2>,
     // one pair per workgroup), so that they start first and overlap the rest
@@ -644,7 +650,6 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
     stw[k] = tb.tw0[k];
     scz[k] = tb.cz[k];
     ssz[k] = tb.sz[k];
-    snz[k] = tb.snz[k];
   }
   __syncthreads();
   // CPT adjacent columns per thread (single precision: two, one 16-byte
@@ -697,13 +702,35 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
   // the second slot's loads (measured at 256^3: 294 -> 281 us FP64, 167 ->
   // 162 us FP32, with the kx = 0 kernel)
   __builtin_amdgcn_sched_barrier(0);
+  // the stencil c[n] = p[n] + s[n + 1] with p = x1 / 2 + i x0 / h0 and
+  // s = x1 / 2 - i x0 / h0 (s[n + 1] from the thread that holds it, through
+  // LDS; 1 / h0 from the tables: sz[1] = (2 / h0) snz[1])
+  const R rh0 = (L >= 2) ? tb.sz[1] / (R(2) * tb.snz[1]) : R(0);
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const C x0 = v[c][e], x1 = acc[c][e];
+      const C ix0 = mk<C>(-x0.y * rh0, x0.x * rh0);  // i x0 / h0
+      v[c][e] = mk<C>(R(0.5) * x1.x + ix0.x, R(0.5) * x1.y + ix0.y);    // p
+      acc[c][e] = mk<C>(R(0.5) * x1.x - ix0.x, R(0.5) * x1.y - ix0.y);  // s
+      lds[LS::idxA(t, e) * B + col0 + c] = acc[c][e];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int e = 0; e < LS::E; ++e) {
+      const int n = LS::idxA(t, e) + 1;
+      v[c][e] = cadd(v[c][e], lds[(n == L ? 0 : n) * B + col0 + c]);
+    }
+  __syncthreads();  // every s read before the transform's exchange
   LS::template fwd_cols<false, CPT>(v, lds + col0, B, t, stw);
-  LS::template fwd_cols<false, CPT>(acc, lds + col0, B, t, stw);
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const R cx = cxs[c], sx = sxs[c];
     const R fx0 = cy * cx, fx1 = sy * cx, fx2 = cy * sx;
-    // -i e^{i (qy + qx) / 2}; the kz factor is applied per element
+    // -i e^{i (qy + qx) / 2} (the kz half of the phase is in the stencil)
     const C eyx = mul_mi(cmul(mk<C>(cy, sny), mk<C>(cx, snxs[c])));
 #pragma unroll
     for (int e = 0; e < LS::E; ++e) {
@@ -712,8 +739,7 @@ k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip ski
       const R a = sz * fx0, b = cz * fx1, cc = cz * fx2;
       const R r2 = a * a + b * b + cc * cc;
       const R f = (r2 > R(0)) ? scale / r2 : R(0);
-      const C w = mk<C>((v[c][e].x * sz + acc[c][e].x * cz) * f, (v[c][e].y * sz + acc[c][e].y * cz) * f);
-      acc[c][e] = cmul(w, cmul(mk<C>(cz, snz[kz]), eyx));
+      acc[c][e] = cmul(cscale(v[c][e], f), eyx);
     }
   }
   LS::template inv_cols<CPT>(acc, lds + col0, B, t, stw);

@@ -79,7 +79,7 @@ int zgrad_tile(int L, int M, int elem_bytes) {
   const int T = zgrad_threads(L, elem_bytes);
   const int cpt = zgrad_cpt(L, elem_bytes);
   int B = 1;
-  while (M % (2 * B) == 0 && T * 2 * B / cpt <= 256 && (long)L * 2 * B * elem_bytes + 5L * L * elem_bytes / 2 <= 65536)
+  while (M % (2 * B) == 0 && T * 2 * B / cpt <= 256 && (long)L * 2 * B * elem_bytes + 2L * L * elem_bytes <= 65536)
     B *= 2;
   return B;
 }
@@ -119,9 +119,9 @@ bool tile_valid(bool zproj, int L, int M, int elem_bytes, int tile) {
   // except at L = 256 (zgrad_cpt)
   const int cpt = pairs ? 2 : ((zproj && tile % 2 == 0) ? zgrad_cpt(L, elem_bytes) : 1);
   if (T * tile / cpt > 256) return false;
-  // exchange buffer, plus the twiddles and kz tables of the projection pass
-  // (the potential form of the projection stages one more kz table)
-  const long lds = (long)L * tile * elem_bytes + (zproj ? 5L * L * elem_bytes / 2 : 0L);
+  // exchange buffer, plus the stage twiddles and the two kz tables of the
+  // projection pass
+  const long lds = (long)L * tile * elem_bytes + (zproj ? 2L * L * elem_bytes : 0L);
   return lds <= 65536;
 }
 

@@ -129,3 +129,23 @@ def test_bench_byte_model_and_roofline():
     assert r["achieved"] == pytest.approx(36 * 8 * N / 1693.2e-6 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
     assert set(r["per_class"]) == {"front", "axis"}
+
+
+@pytest.mark.parametrize("L", [1, 3, 6, 8, 12, 96, 256])
+def test_two_point_stencil_identity_of_the_n0_pass(L):
+    """The identity the N0 projection pass rests on: with sz = (2/h) sin(pi k/L),
+    cz = cos(pi k/L) and q = 2 pi k / L (the same k for every factor),
+    e^{i q/2} (sz X0 + cz X1) is the DFT of the two-point stencil
+    c[n] = (x1[n] + x1[n+1]) / 2 - i (x0[n+1] - x0[n]) / h (periodic), so one
+    forward transform replaces two.  Checked with numpy's FFT on random
+    complex data, odd lengths and L = 1 included."""
+    rng = np.random.default_rng(L)
+    h = 0.37
+    x0 = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    x1 = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    k = np.arange(L)
+    a = np.pi * k / L
+    sz, cz = (2.0 / h) * np.sin(a), np.cos(a)
+    lhs = np.exp(1j * a) * (sz * np.fft.fft(x0) + cz * np.fft.fft(x1))
+    c = 0.5 * (x1 + np.roll(x1, -1)) - 1j * (np.roll(x0, -1) - x0) / h
+    assert np.allclose(np.fft.fft(c), lhs, rtol=0, atol=1e-12 * max(1.0, np.abs(lhs).max()))

@@ -612,12 +612,12 @@ template <typename R> constexpr size_t zgrad_extra_lds(int L) {
 // so each row takes one forward transform (of c) and one inverse instead of
 // two and one, and the phase e^{i qz / 2} of U needs no kz factor (measured
 // at 256^3 with the kx = 0 pairs: 272 -> 271 us FP64; 141 -> 132 us FP32,
-// where the freed registers also allow 4 waves per SIMD).  Grid (M/B, N1, 3
-// rows per item), or (N1, M/B, rows) with
-// kymajor.  The kx = 0 column is left to k_fft_z_dc<OP = 2>, or with DC to a
-// leading slice z = 0 of this launch that runs the same body (dc_lead pairs);
-// the rows then start at z = 1.  The rows' workgroups read the kx = 0 column
-// too but never use or store what they compute for it.
+// where the freed registers also allow 4 waves per SIMD).  Grid (M/B, N1,
+// 3 rows per item), or (N1, M/B, rows) with kymajor.  The kx = 0 column is
+// left to k_fft_z_dc<OP = 2>, or with DC to a leading slice z = 0 of this
+// launch that runs the same body (dc_lead pairs); the rows then start at
+// z = 1.  The rows' workgroups read the kx = 0 column too but never use or
+// store what they compute for it.
 template <typename R, int L, int CPT, bool DC = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && CPT == 1) ? 4 : 1)))
 k_fft_z_grad3(R* data, int N1, int M, int B, SpecTables<R> tb, R scale, Skip skip, int kymajor, int dc_lead = 0,
